@@ -1,0 +1,276 @@
+"""FP64 CPU oracle of the hybrid chemotaxis step (test infrastructure only).
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  It wraps ``oracle.c`` (built with
+gcc into ``liboracle.so`` next to it by :func:`build`) and shares no code
+with the GPU library.
+
+Function map (all arrays are numpy, float64 unless stated):
+
+* :func:`philox`            Philox4x32-10 words for explicit counters / keys
+* :func:`normals`           Box-Muller normals of one instance at one step
+* :func:`forces`            pair repulsion at every agent (all-pairs or cell list)
+* :func:`neighbours_f32`    float32-decided neighbour sets: counts and id hashes
+* :func:`gradient`          node gradients of c
+* :func:`interp`            multilinear interpolation of a node field
+* :func:`drift`             chi * interpolated gradient at every agent
+* :func:`deposit`           piecewise-linear deposit of source / uptake
+* :func:`pde`               n_sub forward-Euler updates of the chemical
+* :func:`step` / :func:`run` whole time steps of one instance
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+import subprocess
+from pathlib import Path
+
+import numpy as np
+
+_HERE = Path(__file__).resolve().parent
+_SRC = _HERE / "oracle.c"
+_LIB = _HERE / "liboracle.so"
+MAX_SPECIES = 8
+
+
+def build(force: bool = True) -> Path:
+    """Compile oracle.c with gcc (FP64, OpenMP, no FMA contraction)."""
+    if force or not _LIB.exists() or _LIB.stat().st_mtime < _SRC.stat().st_mtime:
+        tmp = _LIB.with_suffix(".so.tmp%d" % os.getpid())
+        cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
+               "-fno-fast-math", str(_SRC), "-o", str(tmp), "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class Params(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("periodic", C.c_int32), ("L", C.c_double),
+                ("grid_n", C.c_int32), ("n_sub", C.c_int32),
+                ("dt", C.c_double), ("k", C.c_double), ("D_c", C.c_double),
+                ("gamma", C.c_double), ("n_species", C.c_int32), ("mode", C.c_int32),
+                ("diam", C.c_double * MAX_SPECIES), ("D", C.c_double * MAX_SPECIES),
+                ("chi", C.c_double * MAX_SPECIES), ("source", C.c_double * MAX_SPECIES),
+                ("uptake", C.c_double * MAX_SPECIES), ("seed", C.c_uint64),
+                ("inst", C.c_uint32), ("chi_scale", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not _LIB.exists() or _LIB.stat().st_mtime < _SRC.stat().st_mtime:
+            build()
+        L = C.CDLL(str(_LIB))
+        P = C.POINTER(Params)
+        vp = C.c_void_p
+        i64 = C.c_int64
+        sig = {
+            "orc_num_threads": ([], C.c_int),
+            "orc_set_threads": ([C.c_int], None),
+            "orc_philox_batch": ([i64, vp, vp, vp], None),
+            "orc_normals": ([P, C.c_uint32, i64, vp, vp], None),
+            "orc_forces": ([P, i64, vp, vp, vp], None),
+            "orc_forces_subset": ([P, i64, vp, vp, i64, vp, vp], None),
+            "orc_neighbours_f32": ([C.c_int, C.c_int, C.c_float, i64, vp, vp, vp, vp, C.c_int,
+                                    C.c_int, vp, vp], None),
+            "orc_hash_id": ([C.c_uint32], C.c_uint64),
+            "orc_gradient": ([P, vp, vp], None),
+            "orc_interp": ([P, vp, i64, vp, vp], None),
+            "orc_drift": ([P, vp, i64, vp, vp, vp], None),
+            "orc_deposit": ([P, i64, vp, vp, vp, vp], None),
+            "orc_pde": ([P, vp, vp, vp], None),
+            "orc_step": ([P, i64, vp, vp, vp, vp, vp], None),
+            "orc_run": ([P, i64, vp, vp, vp, vp, vp, C.c_int], None),
+        }
+        for name, (args, res) in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _c(a, dtype) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def auto_substeps(dim: int, periodic: bool, L: float, grid_n: int, dt: float, D_c: float) -> int:
+    """Smallest substep count keeping D_c dt' / h^2 within 90% of the
+    explicit limit 1/(2 dim) of forward Euler with the centred Laplacian."""
+    h = L / grid_n if periodic else L / (grid_n - 1)
+    r = D_c * dt / (h * h)
+    return max(1, math.ceil(r / (0.9 / (2 * dim))))
+
+
+def params(w, inst: int = 0, mode: int = 1, **over) -> Params:
+    """Oracle parameters of instance `inst` of a workloads.Workload."""
+    p = Params()
+    p.dim = w.dim
+    p.periodic = 1 if w.periodic else 0
+    p.L = w.L
+    p.grid_n = w.grid_n
+    p.n_sub = w.pde_substeps or auto_substeps(w.dim, w.periodic, w.L, w.grid_n, w.dt, w.D_c)
+    p.dt, p.k, p.D_c, p.gamma = w.dt, w.k, w.D_c, w.gamma
+    p.n_species = len(w.species)
+    for s, sp in enumerate(w.species):
+        p.diam[s], p.D[s], p.chi[s] = sp.diameter, sp.D, sp.chi
+        p.source[s], p.uptake[s] = sp.source, sp.uptake
+    ins = w.instances[inst]
+    p.seed = ins.seed & (2**64 - 1)
+    p.inst = inst
+    p.chi_scale = ins.chi_scale
+    p.mode = mode
+    for k, v in over.items():
+        setattr(p, k, v)
+    return p
+
+
+def num_threads() -> int:
+    return lib().orc_num_threads()
+
+
+def set_threads(n: int) -> None:
+    lib().orc_set_threads(n)
+
+
+def philox(ctr: np.ndarray, key: np.ndarray) -> np.ndarray:
+    ctr = _c(ctr, np.uint32).reshape(-1, 4)
+    key = _c(key, np.uint32).reshape(-1, 2)
+    out = np.empty_like(ctr)
+    lib().orc_philox_batch(len(ctr), _ptr(ctr), _ptr(key), _ptr(out))
+    return out
+
+
+def normals(p: Params, step: int, ids: np.ndarray) -> np.ndarray:
+    ids = _c(ids, np.uint32)
+    out = np.empty((len(ids), p.dim), np.float64)
+    lib().orc_normals(C.byref(p), step, len(ids), _ptr(ids), _ptr(out))
+    return out
+
+
+def forces(p: Params, X: np.ndarray, sp: np.ndarray) -> np.ndarray:
+    X = _c(X, np.float64)
+    sp = _c(sp, np.uint8)
+    F = np.empty_like(X)
+    lib().orc_forces(C.byref(p), len(X), _ptr(X), _ptr(sp), _ptr(F))
+    return F
+
+
+def forces_subset(p: Params, X: np.ndarray, sp: np.ndarray, which: np.ndarray) -> np.ndarray:
+    X = _c(X, np.float64)
+    sp = _c(sp, np.uint8)
+    which = _c(which, np.int64)
+    F = np.empty((len(which), p.dim), np.float64)
+    lib().orc_forces_subset(C.byref(p), len(X), _ptr(X), _ptr(sp), len(which), _ptr(which),
+                            _ptr(F))
+    return F
+
+
+def cut2_table(diameters) -> np.ndarray:
+    """float32 squared contact distances ((d_a + d_b) / 2)^2, rounded once."""
+    d = np.asarray(diameters, np.float64)
+    m = 0.5 * (d[:, None] + d[None, :])
+    return np.ascontiguousarray((m * m).astype(np.float32))
+
+
+def neighbours_f32(dim: int, periodic: bool, L: float, X: np.ndarray, sp: np.ndarray,
+                   ids: np.ndarray, diameters, mode: int = 1):
+    X = _c(X, np.float32)
+    sp = _c(sp, np.uint8)
+    ids = _c(ids, np.uint32)
+    cut2 = cut2_table(diameters)
+    n = len(X)
+    cnt = np.empty(n, np.uint32)
+    h = np.empty(n, np.uint64)
+    lib().orc_neighbours_f32(dim, 1 if periodic else 0, float(L), n, _ptr(X), _ptr(sp),
+                             _ptr(ids), _ptr(cut2), cut2.shape[0], mode, _ptr(cnt), _ptr(h))
+    return cnt, h
+
+
+def hash_id(i: int) -> int:
+    return int(lib().orc_hash_id(i))
+
+
+def n_nodes(p: Params) -> int:
+    return p.grid_n ** p.dim
+
+
+def gradient(p: Params, c: np.ndarray) -> np.ndarray:
+    c = _c(c, np.float64)
+    g = np.empty(p.dim * n_nodes(p), np.float64)
+    lib().orc_gradient(C.byref(p), _ptr(c), _ptr(g))
+    return g.reshape(p.dim, -1)
+
+
+def interp(p: Params, f: np.ndarray, X: np.ndarray) -> np.ndarray:
+    f = _c(f, np.float64)
+    X = _c(X, np.float64)
+    out = np.empty(len(X), np.float64)
+    lib().orc_interp(C.byref(p), _ptr(f), len(X), _ptr(X), _ptr(out))
+    return out
+
+
+def drift(p: Params, c: np.ndarray, X: np.ndarray, sp: np.ndarray) -> np.ndarray:
+    c = _c(c, np.float64)
+    X = _c(X, np.float64)
+    sp = _c(sp, np.uint8)
+    out = np.empty_like(X)
+    lib().orc_drift(C.byref(p), _ptr(c), len(X), _ptr(X), _ptr(sp), _ptr(out))
+    return out
+
+
+def deposit(p: Params, X: np.ndarray, sp: np.ndarray):
+    X = _c(X, np.float64)
+    sp = _c(sp, np.uint8)
+    Ss = np.empty(n_nodes(p), np.float64)
+    Su = np.empty(n_nodes(p), np.float64)
+    lib().orc_deposit(C.byref(p), len(X), _ptr(X), _ptr(sp), _ptr(Ss), _ptr(Su))
+    return Ss, Su
+
+
+def pde(p: Params, c: np.ndarray, S_src: np.ndarray, S_upt: np.ndarray) -> np.ndarray:
+    c = _c(c, np.float64).copy()
+    S_src = _c(S_src, np.float64)
+    S_upt = _c(S_upt, np.float64)
+    lib().orc_pde(C.byref(p), _ptr(c), _ptr(S_src), _ptr(S_upt))
+    return c
+
+
+def run(p: Params, X: np.ndarray, sp: np.ndarray, c: np.ndarray, step: int, n_steps: int,
+        ids: np.ndarray | None = None):
+    """Advance one instance by n_steps; returns (X, c, step) as new arrays."""
+    X = _c(X, np.float64).copy()
+    c = _c(c, np.float64).copy()
+    sp = _c(sp, np.uint8)
+    ids = np.arange(len(X), dtype=np.uint32) if ids is None else _c(ids, np.uint32)
+    st = C.c_uint32(step)
+    lib().orc_run(C.byref(p), len(X), _ptr(X), _ptr(sp), _ptr(ids), _ptr(c), C.byref(st), n_steps)
+    return X, c, st.value
+
+
+def step(p: Params, X, sp, c, step_no: int, ids=None):
+    return run(p, X, sp, c, step_no, 1, ids)
+
+
+def run_workload(w, inputs: dict, n_steps: int, mode: int = 1, step0: int = 0):
+    """Advance every instance of a workload from `inputs` (workloads.make_inputs)."""
+    xs, cs = [], []
+    off = 0
+    G = w.grid_n ** w.dim
+    for k, ins in enumerate(w.instances):
+        n = ins.n_agents
+        p = params(w, k, mode=mode)
+        X, c, _ = run(p, inputs["x0"][off:off + n], inputs["species0"][off:off + n],
+                      inputs["c0"][k * G:(k + 1) * G], step0, n_steps)
+        xs.append(X)
+        cs.append(c)
+        off += n
+    return np.concatenate(xs, 0), np.concatenate(cs, 0)

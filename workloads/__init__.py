@@ -1,0 +1,225 @@
+"""Seeded synthetic workloads for the hybrid chemotaxis step.
+
+This module is shared by the tests, the benchmark and the CPU oracle's
+drivers.  It only *describes* workloads (parameters and sizes) and draws
+their initial conditions; it contains none of the method's arithmetic
+(no forces, noise, interpolation, deposit or PDE update).  Every array it
+returns is the exact input given to both the GPU library and the oracle.
+
+The paper runs its own simulations only (no public dataset); the five
+workloads below stand in for them:
+
+* ``config(1)``  2D periodic, 1,000 agents, 64^2 grid (parity case)
+* ``config(2)``  2D reflecting walls, 100,000 agents in two species, 512^2 grid
+* ``config(3)``  3D periodic, 1,000,000 agents in 8 Gaussian blobs, 128^3 grid
+* ``config(4)``  256 independent 2D instances of uneven size, 128^2 grids
+* ``config(5)``  2D periodic, 50,000 agents (producers / consumers), 256^2 grid
+
+Initial conditions follow one recipe: a numpy ``PCG64(1000 + cfg)``
+generator draws everything in float64, which is then rounded to float32
+(positions) so that both sides start from identical float32 arrays.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from dataclasses import dataclass, field, replace
+from typing import List, Sequence, Tuple
+
+import numpy as np
+
+__all__ = ["Species", "Instance", "Workload", "config", "scaled", "make_inputs",
+           "node_coords", "CONFIGS"]
+
+
+@dataclass(frozen=True)
+class Species:
+    """One agent species (the paper's cell "type", Sect. 2)."""
+    diameter: float   # interaction range; contact distance is the mean of two diameters
+    D: float          # diffusion coefficient (eq. sde_alpha / sde_beta)
+    chi: float        # chemotactic sensitivity (eq. sde_beta); 0 = no drift
+    source: float     # secretion rate k_alpha (eq. pde_c)
+    uptake: float     # consumption rate k_beta (eq. pde_c)
+
+
+@dataclass(frozen=True)
+class Instance:
+    """One independent realisation: its size, its noise key and chi scale."""
+    n_agents: int
+    seed: int
+    chi_scale: float = 1.0
+
+
+@dataclass(frozen=True)
+class Workload:
+    name: str
+    dim: int
+    periodic: bool
+    L: float
+    grid_n: int
+    dt: float
+    k: float                 # harmonic repulsion stiffness, F = k (d - r) r_hat
+    D_c: float               # chemical diffusivity
+    gamma: float             # chemical decay rate
+    steps: int
+    species: Tuple[Species, ...]
+    instances: Tuple[Instance, ...]
+    pde_substeps: int = 0    # 0 = choose the smallest stable count
+    layout: str = "uniform"  # "uniform" | "blobs"
+    species_rule: str = "single"  # "single" | "halves" (id >= N/2 -> species 1)
+    c0: str = "sin"          # "sin": prod sin(2 pi x) + 1 ; "cos": prod cos(pi x) + 1
+    gen_seed: int = 1000
+
+    @property
+    def n_total(self) -> int:
+        return sum(i.n_agents for i in self.instances)
+
+    @property
+    def n_inst(self) -> int:
+        return len(self.instances)
+
+    @property
+    def n_nodes(self) -> int:
+        return self.grid_n ** self.dim
+
+
+def _one_species_cfg1() -> Tuple[Species, ...]:
+    return (Species(diameter=0.01, D=1.0, chi=1.0, source=1.0, uptake=0.0),)
+
+
+def config(n: int) -> Workload:
+    """The five reference workloads (sizes and parameters as specified)."""
+    if n == 1:
+        return Workload("cfg1_2d_periodic_1k", 2, True, 1.0, 64, 1e-5, 100.0, 1.0, 0.1, 100,
+                        _one_species_cfg1(), (Instance(1000, 1001),), gen_seed=1001)
+    if n == 2:
+        sp = (Species(0.002, 1.0, 0.0, 1.0, 0.0), Species(0.003, 0.5, 2.0, 0.0, 1.0))
+        return Workload("cfg2_2d_walls_100k", 2, False, 1.0, 512, 1e-6, 1000.0, 1.0, 0.1, 1000,
+                        sp, (Instance(100_000, 1002),), species_rule="halves", c0="cos",
+                        gen_seed=1002)
+    if n == 3:
+        sp = (Species(0.004, 1.0, 1.0, 1.0, 0.0),)
+        return Workload("cfg3_3d_periodic_1M_blobs", 3, True, 1.0, 128, 1e-7, 1000.0, 1.0, 0.1,
+                        200, sp, (Instance(1_000_000, 1003),), layout="blobs", gen_seed=1003)
+    if n == 4:
+        rng = np.random.Generator(np.random.PCG64(1004))
+        n_i = np.rint(np.exp(rng.uniform(math.log(500), math.log(20000), 256))).astype(int)
+        chi = rng.uniform(0.0, 3.0, 256)
+        seeds = rng.integers(0, 2**63, 256, dtype=np.int64)
+        inst = tuple(Instance(int(a), int(s), float(c)) for a, s, c in zip(n_i, seeds, chi))
+        return Workload("cfg4_2d_ensemble_256", 2, True, 1.0, 128, 1e-5, 100.0, 1.0, 0.1, 500,
+                        _one_species_cfg1(), inst, gen_seed=1004)
+    if n == 5:
+        return config5()
+    raise ValueError(f"no workload {n}")
+
+
+def config5(chi: float = 1.0, k: float = 100.0, D: float = 1.0, seed: int = 1005) -> Workload:
+    """Differentiation workload: producers (species 0) and consumers (species 1)."""
+    sp = (Species(0.01, D, 0.0, 1.0, 0.0), Species(0.01, D, chi, 0.0, 1.0))
+    return Workload("cfg5_2d_periodic_50k_adjoint", 2, True, 1.0, 256, 1e-5, k, 1.0, 0.1, 200,
+                    sp, (Instance(50_000, seed),), pde_substeps=3, species_rule="halves",
+                    gen_seed=1005)
+
+
+CONFIGS = (1, 2, 3, 4, 5)
+
+
+def scaled(w: Workload, n_agents: int | Sequence[int] | None = None,
+           grid_n: int | None = None, steps: int | None = None, **kw) -> Workload:
+    """A smaller copy of a workload with the same structure (for parity tests)."""
+    inst = w.instances
+    if n_agents is not None:
+        if isinstance(n_agents, int):
+            n_agents = [n_agents] * len(inst)
+        n_agents = list(n_agents)
+        if len(n_agents) != len(inst):
+            inst = tuple(Instance(int(n), inst[i % len(inst)].seed + i // len(inst),
+                                  inst[i % len(inst)].chi_scale)
+                         for i, n in enumerate(n_agents))
+        else:
+            inst = tuple(replace(i, n_agents=int(n)) for i, n in zip(inst, n_agents))
+    return replace(w, instances=inst, grid_n=grid_n or w.grid_n,
+                   steps=w.steps if steps is None else steps, **kw)
+
+
+def node_coords(w: Workload) -> np.ndarray:
+    """1D node coordinates used to draw the initial chemical field.
+
+    Periodic grids put N_c nodes at i*L/N_c; wall grids put N_c nodes at
+    i*L/(N_c-1), on both walls.
+    """
+    n = w.grid_n
+    h = w.L / n if w.periodic else w.L / (n - 1)
+    return np.arange(n, dtype=np.float64) * h
+
+
+def _f32_in_box(x: np.ndarray, w: Workload) -> np.ndarray:
+    x32 = x.astype(np.float32)
+    if w.periodic:
+        # rounding can carry a value just below L up to L; keep [0, L)
+        x32[x32 >= np.float32(w.L)] = np.float32(0.0)
+        x32[x32 < 0] = np.float32(0.0)
+    else:
+        np.clip(x32, np.float32(0.0), np.float32(w.L), out=x32)
+    return x32
+
+
+def _positions(w: Workload, n: int, rng: np.random.Generator) -> np.ndarray:
+    d = w.dim
+    if w.layout == "uniform":
+        x = rng.uniform(0.0, w.L, size=(n, d))
+    elif w.layout == "blobs":
+        centres = rng.uniform(0.0, w.L, size=(8, d))
+        z = rng.standard_normal(size=(n, d))
+        blob = np.arange(n) % 8
+        x = np.mod(centres[blob] + 0.05 * w.L * z, w.L)
+    else:
+        raise ValueError(w.layout)
+    return _f32_in_box(x, w)
+
+
+def _field(w: Workload) -> np.ndarray:
+    xs = node_coords(w)
+    grids = np.meshgrid(*([xs] * w.dim), indexing="ij")  # grids[a] varies along axis a
+    if w.c0 == "sin":
+        f = np.ones_like(grids[0])
+        for g in grids:
+            f = f * np.sin(2 * np.pi * g / w.L)
+        f = f + 1.0
+    elif w.c0 == "cos":
+        f = np.ones_like(grids[0])
+        for g in grids:
+            f = f * np.cos(np.pi * g / w.L)
+        f = f + 1.0
+    elif w.c0 == "zero":
+        f = np.zeros_like(grids[0])
+    else:
+        raise ValueError(w.c0)
+    # storage order: x fastest, i.e. C order [z][y][x] -> transpose the ij grid
+    return np.ascontiguousarray(f.T).astype(np.float32).reshape(-1)
+
+
+def make_inputs(w: Workload) -> dict:
+    """Initial state of every instance, concatenated instance-major.
+
+    Returns ``x0`` (float32, sum(N) x dim, id order within each instance),
+    ``species0`` (uint8, sum(N)) and ``c0`` (float32, n_inst x grid_n^dim,
+    x fastest).
+    """
+    rng = np.random.Generator(np.random.PCG64(w.gen_seed))
+    xs, ss = [], []
+    for inst in w.instances:
+        n = inst.n_agents
+        xs.append(_positions(w, n, rng))
+        if w.species_rule == "single":
+            ss.append(np.zeros(n, np.uint8))
+        elif w.species_rule == "halves":
+            ss.append((np.arange(n) >= n // 2).astype(np.uint8))
+        else:
+            raise ValueError(w.species_rule)
+    f = _field(w)
+    c0 = np.tile(f, w.n_inst)
+    return {"x0": np.ascontiguousarray(np.concatenate(xs, 0)),
+            "species0": np.ascontiguousarray(np.concatenate(ss, 0)),
+            "c0": np.ascontiguousarray(c0)}
