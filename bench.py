@@ -1,0 +1,176 @@
+#!/usr/bin/env python3
+"""Benchmark of the hybrid chemotaxis step on one MI355X.
+
+Workload: the 3D periodic run with 1,000,000 agents in 8 Gaussian blobs on a
+128^3 chemical grid (dt = 1e-7), stepped from its initial state.  W warm-up
+steps run first on the same handle, the state is then restored to the
+initial condition and exactly K steps are timed (HIP-graph replay, inputs
+already resident in HBM).  One JSON line is printed with:
+
+* value: particle-steps/s of the whole timed region;
+* roofline: the dominant kernel's algorithmic bytes per launch divided by
+  its mean launch time (HIP events between the stages of each step, on the
+  library's stream), against the 8 TB/s HBM peak;
+* cpu_baseline: the FP64 oracle timed on the host cores on a bounded sample
+  of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+from pathlib import Path
+
+ROOT = Path(__file__).resolve().parent
+sys.path.insert(0, str(ROOT))
+
+METRIC = ("particle-steps/s (3D, 1M cells) + % HBM roofline; fwd+bwd and ensemble vs plain")
+HBM_PEAK_GBS = 8000.0
+
+
+def algorithmic_bytes(stage: str, w, n_sub: int) -> float:
+    """Bytes a stage must move per launch (per step), by definition of what it
+    computes, independent of how the kernels are built:
+      update:  per agent read position + id/species, write position
+               (8 dim + 4 bytes); per node read c once and write each
+               deposited field once (4 + 4 F bytes), F = fields deposited.
+      pde:     per node and substep read and write c (8 bytes), plus one read
+               of each deposited field (4 F bytes).
+      bin:     per agent read position, write bin and rank (4 dim + 8).
+      scatter: per agent read position/id/bin/rank, write position/id
+               (4 dim + 12 read, 4 dim + 4 write) -> 8 dim + 16.
+      scan:    per bin read count, write start (8 bytes).
+    """
+    N, d = w.n_total, w.dim
+    G = w.n_inst * w.grid_n ** d
+    F = 2 if any(s.uptake > 0 for s in w.species) else 1
+    if stage == "update":
+        return N * (8 * d + 4) + G * (4 + 4 * F)
+    if stage == "pde":
+        return G * (8 * n_sub + 4 * F)
+    if stage == "bin":
+        return N * (4 * d + 8)
+    if stage == "scatter":
+        return N * (8 * d + 16)
+    return 0.0
+
+
+def cpu_baseline(w, inp, budget_s: float = 12.0, max_steps: int = 40):
+    import oracle
+    p = oracle.params(w, 0, mode=1)
+    X, sp, c = inp["x0"], inp["species0"], inp["c0"]
+    steps, t0 = 0, time.perf_counter()
+    st = 0
+    while steps < max_steps:
+        X, c, st = oracle.step(p, X, sp, c, st)
+        steps += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    el = time.perf_counter() - t0
+    return {"value": w.n_total * steps / el, "unit": "particle-steps/s",
+            "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"first {steps} steps of the same workload, FP64 cell-list oracle, "
+                      f"{el:.1f} s"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--config", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--deterministic", action="store_true")
+    ap.add_argument("--bin-size", type=float, default=0.0)
+    ap.add_argument("--block", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_1805_11007_amd import ModelSpec, Sim
+
+    w = W.config(args.config)
+    inp = W.make_inputs(w)
+    spec = ModelSpec.from_workload(w, deterministic=args.deterministic,
+                                   bin_size=args.bin_size, block=args.block)
+    torch.cuda.set_device(0)
+    x0 = torch.from_numpy(inp["x0"]).cuda()
+    s0 = torch.from_numpy(inp["species0"]).cuda()
+    c0 = torch.from_numpy(inp["c0"]).cuda()
+    sim = Sim(spec, x0, s0, c0)
+    if not args.no_graph:
+        sim.use_graph(True)
+    print(f"[bench] {w.name}: N={w.n_total} G={w.n_inst * w.grid_n ** w.dim} "
+          f"info={sim.info}", file=sys.stderr, flush=True)
+
+    # warm-up (also captures the graph), then back to the initial condition
+    sim.step(args.warmup)
+    sim.sync()
+    sim.set_state(x0, c0, 0)
+    torch.cuda.synchronize()
+
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    sim.step(args.steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    sim.sync()
+    value = w.n_total * args.steps / (ms / 1e3)
+    print(f"[bench] timed {args.steps} steps: {ms:.3f} ms", file=sys.stderr, flush=True)
+
+    # per-stage HIP-event profile of the same run (restored initial state)
+    sim.set_state(x0, c0, 0)
+    prof = sim.profile_steps(args.steps)
+    dom = max(prof, key=prof.get)
+    n_sub = sim.info["pde_substeps"]
+    alg = algorithmic_bytes(dom, w, n_sub)
+    achieved = alg / (prof[dom] * 1e-3) / 1e9
+    print(f"[bench] stage ms/step: {json.dumps({k: round(v, 5) for k, v in prof.items()})}",
+          file=sys.stderr, flush=True)
+
+    res = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "dim": w.dim, "n_agents": w.n_total,
+                   "grid": f"{w.grid_n}^{w.dim}", "dt": w.dt, "timed_steps": args.steps,
+                   "graph": not args.no_graph, "deterministic": args.deterministic,
+                   "bins_per_axis": sim.info["bins_per_axis"], "stencil": sim.info["stencil"],
+                   "block": sim.info["block"]},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": None, "algorithmic_bytes_per_launch": alg,
+                     "launch_ms": prof[dom]},
+        "stage_ms": prof,
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
+        res["cpu_baseline"] = cpu_baseline(w, inp)
+    print(json.dumps(res), flush=True)
+    sim.close()
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

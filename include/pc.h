@@ -1,0 +1,231 @@
+/*
+ * pc.h — C ABI of the MI355X (gfx950) library for the hybrid chemotaxis step
+ * of Bruna, Maini & Robinson, "Particle-based simulations of
+ * reaction-diffusion processes with Aboria" (arXiv:1805.11007).
+ *
+ * One time step (Sect. 2 and 3 of the paper, in the order of its listings):
+ *   1. cell-list binning of the agents (counting sort; Sect. 2.2 and the
+ *      neighbour-search set-up of Sect. 3.1);
+ *   2. pairwise soft-sphere repulsion F = k (d - r) r_hat for r < d over the
+ *      neighbour bins (interaction loop of Sect. 3.2; eqs. sde_alpha/beta);
+ *   3. chemotactic drift chi * grad c interpolated multilinearly from the
+ *      node grid (Sect. 2.3 and 3.6);
+ *   4. Euler-Maruyama update with Philox4x32-10 normals (eq. sde_EM) and the
+ *      periodic or reflecting boundary (Sect. 3.2);
+ *   5. piecewise-linear deposit of cell source / uptake at the new positions
+ *      (Sect. 2.3, eq. random_measure);
+ *   6. forward-Euler, centred-difference update of the chemical (eq. pde_c,
+ *      Sect. 3.5), in substeps when the explicit limit requires them.
+ *
+ * Several independent instances (realisations) of one model can be stepped
+ * together; each has its own agents, bins, grid and noise key.
+ *
+ * Conventions for every entry point:
+ *   - Return value: PC_OK (0) or a negative PC_E* code; nothing throws.
+ *     pc_strerror() names a code; pc_last_error() gives the message of the
+ *     last failure on the calling thread.
+ *   - Pointers named *_dev are device pointers (HIP device memory on the
+ *     device that was current at pc_create).  Pointers without the suffix
+ *     are host pointers.
+ *   - The caller owns all device memory, including the workspace; the
+ *     library never allocates or frees device memory after pc_create.  The
+ *     handle itself is a small host object freed by pc_destroy.
+ *   - All device work is enqueued asynchronously on the stream given to
+ *     pc_create unless stated otherwise.  Kernel-side conditions (non-finite
+ *     state, positivity warnings) are latched in device flags and reported
+ *     by pc_sync / pc_warnings.
+ *   - Agent arrays are "instance-major, id order": instance k occupies rows
+ *     [base_k, base_k + N_k), base_k = N_0 + ... + N_{k-1}; within an
+ *     instance, row i is the agent with stable id i.
+ *   - Grid arrays are instance-major, x fastest: node (ix, iy[, iz]) of
+ *     instance k is at k*G + ix + n*(iy + n*iz), G = n^dim.
+ */
+#ifndef PC_H
+#define PC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    PC_OK = 0,
+    PC_EINVAL = -1,      /* invalid argument or parameter set            */
+    PC_EUNSTABLE = -2,   /* explicit PDE substep count above the limit   */
+    PC_ENOSPACE = -3,    /* workspace smaller than pc_workspace_bytes    */
+    PC_EHIP = -4,        /* HIP runtime error                            */
+    PC_ENONFINITE = -5,  /* NaN or Inf reached the state                 */
+    PC_ENOTSUP = -6      /* operation not available for this setup       */
+};
+
+/* Warning bits (pc_warnings). */
+enum {
+    PC_WARN_DT_RULE = 1u,      /* sqrt(2 (D_i + D_j) dt) >= contact distance (Sect. 2.2) */
+    PC_WARN_POSITIVITY = 2u,   /* dt' (gamma + uptake density) >= 1 at some node        */
+    PC_WARN_CLAMPED = 4u       /* a position was clamped into the domain                */
+};
+
+#define PC_MAX_SPECIES 8
+
+typedef struct pc_sim pc_sim;
+
+/* Model and numerics shared by all instances. */
+typedef struct {
+    int32_t dim;            /* 2 or 3                                                   */
+    int32_t periodic;       /* 1: torus [0,L)^dim ; 0: reflecting walls [0,L]^dim       */
+    double L;               /* box side                                                 */
+    int32_t grid_n;         /* chemical nodes per axis (>= 3); periodic spacing L/n,
+                               walls spacing L/(n-1) with nodes on both walls           */
+    double dt;              /* time step                                                */
+    double k_rep;           /* repulsion stiffness k of F = k (d - r) r_hat             */
+    double D_c;             /* chemical diffusivity                                     */
+    double gamma;           /* chemical decay rate                                      */
+    int32_t pde_substeps;   /* 0: smallest count with D_c dt'/h^2 <= 0.9/(2 dim);
+                               > 0: used as given, PC_EUNSTABLE above the limit 1/(2 dim) */
+    double bin_size;        /* 0: automatic; else the cell-list bin side (>= cutoff)    */
+    int32_t deterministic;  /* 1: agents ordered by id inside each bin, so results are
+                               bitwise reproducible run to run                          */
+    int32_t block;          /* 0: automatic; else work-group size of the agent kernels
+                               (64, 128, 256, 512 or 1024)                              */
+    int32_t bin_order;      /* 0: row-major bins (x fastest); 1: 2x2(x2) brick order     */
+    int32_t reserved;
+} pc_config;
+
+/* One agent species (the paper's cell type). */
+typedef struct {
+    double diameter;  /* contact distance of a pair = mean of the two diameters */
+    double D;         /* diffusion coefficient                                  */
+    double chi;       /* chemotactic sensitivity (0: no drift)                  */
+    double source;    /* secretion rate k_alpha into the chemical               */
+    double uptake;    /* consumption rate k_beta (per unit concentration)       */
+} pc_species_t;
+
+/* One independent instance. */
+typedef struct {
+    int32_t n_agents;  /* >= 1                                                  */
+    int32_t stream;    /* noise stream index s of the instance; < 0 means its
+                          position in the array.  Philox key (lo32(seed),
+                          hi32(seed) ^ s), counter (step, id, s, 0), so an
+                          instance run alone with the same seed and stream
+                          reproduces its run inside a batch                     */
+    uint64_t seed;
+    double chi_scale;  /* multiplies every species' chi in this instance        */
+} pc_instance;
+
+/* Bytes of device workspace pc_create needs for this setup (host-only, pure).
+ * Returns 0 if the parameters are invalid (pc_create reports why). */
+size_t pc_workspace_bytes(const pc_config *cfg, const pc_species_t *species, int n_species,
+                          const pc_instance *inst, int n_inst);
+
+/* Create a simulation handle.
+ *   workspace_dev / workspace_bytes: caller-owned device buffer of at least
+ *     pc_workspace_bytes(...) bytes, 256-byte aligned, valid until pc_destroy;
+ *   x0_dev: float32, sum(N) x dim, instance-major id order, inside the box;
+ *   species0_dev: uint8, sum(N), species index < n_species;
+ *   c0_dev: float32, n_inst x grid_n^dim;
+ *   hip_stream: hipStream_t the work is enqueued on (NULL = default stream).
+ * The inputs are copied into the workspace (asynchronously); they may be
+ * released once the stream has passed this call.
+ * Errors: PC_EINVAL (dim not 2/3, N < 1, grid_n < 3, diameter <= 0,
+ * cutoff >= L/2, fewer than 3 bins per axis, species out of range),
+ * PC_EUNSTABLE, PC_ENOSPACE, PC_EHIP. */
+int pc_create(const pc_config *cfg, const pc_species_t *species, int n_species,
+              const pc_instance *inst, int n_inst, void *workspace_dev, size_t workspace_bytes,
+              const float *x0_dev, const uint8_t *species0_dev, const float *c0_dev,
+              void *hip_stream, pc_sim **out);
+
+/* Enqueue n_steps time steps (n_steps >= 0).  With pc_use_graph(sim, 1) the
+ * steps are replayed from a captured HIP graph (captured on first use). */
+int pc_step(pc_sim *sim, int n_steps);
+
+/* Turn HIP-graph replay of pc_step on (1) or off (0). */
+int pc_use_graph(pc_sim *sim, int on);
+
+/* Current positions into out_dev (float32, sum(N) x dim, id order). */
+int pc_positions(pc_sim *sim, float *out_dev);
+
+/* Current chemical field into out_dev (float32, n_inst x grid_n^dim). */
+int pc_field(pc_sim *sim, float *out_dev);
+
+/* Species of every agent into out_dev (uint8, sum(N), id order). */
+int pc_species(pc_sim *sim, uint8_t *out_dev);
+
+/* Checkpoint: positions (as pc_positions), field (as pc_field) and the step
+ * counter (host value; steps enqueued so far plus the initial counter). */
+int pc_get_state(pc_sim *sim, float *x_dev, float *c_dev, uint32_t *step);
+
+/* Restore a checkpoint; the noise of later steps is that of the restored
+ * step counter (Philox is keyed by step, id and instance). */
+int pc_set_state(pc_sim *sim, const float *x_dev, const float *c_dev, uint32_t step);
+
+/* Wait for the stream; report PC_ENONFINITE if a non-finite value reached
+ * the state since the last call, else PC_OK. */
+int pc_sync(pc_sim *sim);
+
+/* Warning bits (PC_WARN_*) seen so far; waits for the stream. */
+int pc_warnings(pc_sim *sim, uint32_t *bits);
+
+/* Read-only facts about a handle. */
+typedef struct {
+    int32_t n_total;        /* sum of agents over instances           */
+    int32_t n_inst;
+    int32_t bins_per_axis;
+    int32_t stencil;        /* 3: 3^dim neighbour bins; 2: 2^dim        */
+    int64_t n_bins_total;
+    int64_t n_nodes_total;
+    int32_t pde_substeps;
+    int32_t block;
+    double bin_side;
+    size_t workspace_bytes;
+} pc_info_t;
+int pc_info(pc_sim *sim, pc_info_t *info);
+
+/* Measurement: run n_steps steps eagerly with HIP events between the
+ * stages of each step and return the mean milliseconds per step of every
+ * stage in stage_ms[PC_N_STAGES] (host): bin, scan, scatter, stable order,
+ * update, PDE.  Synchronises the stream; advances the state like pc_step. */
+enum { PC_STAGE_BIN, PC_STAGE_SCAN, PC_STAGE_SCATTER, PC_STAGE_STABLE, PC_STAGE_UPDATE,
+       PC_STAGE_PDE, PC_N_STAGES };
+int pc_profile_steps(pc_sim *sim, int n_steps, double *stage_ms);
+
+/* Release the handle (does not touch caller memory). */
+int pc_destroy(pc_sim *sim);
+
+const char *pc_strerror(int code);
+const char *pc_last_error(void);
+
+/* --- test / debug entry points: the step's own kernels with extra output --- */
+
+/* Neighbour sets of the current state, as decided inside the pair kernel:
+ * per agent (id order) the number of agents j != i with float32
+ * |minimage(x_j - x_i)|^2 < ((d_i + d_j)/2)^2 (rounded to float32) and the
+ * wrap-around sum over those j of splitmix64(id_j).  count_dev: uint32,
+ * hash_dev: uint64, both sum(N). */
+int pc_debug_neighbours(pc_sim *sim, uint32_t *count_dev, uint64_t *hash_dev);
+
+/* Pair forces of the current state (float32, sum(N) x dim, id order). */
+int pc_debug_forces(pc_sim *sim, float *F_dev);
+
+/* --- differentiation (reverse mode through the step) ---
+ * Adjoint of n_steps steps starting from the current state with its noise
+ * fixed by the Philox keys.  lamX_in_dev (sum(N) x dim) and lamC_in_dev
+ * (n_inst x G) are the loss gradients with respect to the positions and
+ * field after the n_steps steps; lamX_out_dev / lamC_out_dev receive the
+ * gradients with respect to the current positions and field; dtheta_out
+ * (host, 3 doubles per instance) receives dL/d(chi_scale), dL/dk and dL/dD
+ * (D of every species scaled together).  The current state is left as it
+ * was.  Positions are not changed by the call.  Requires n_steps >= 1 and
+ * a workspace created with pc_workspace_bytes_adjoint. */
+size_t pc_workspace_bytes_adjoint(const pc_config *cfg, const pc_species_t *species,
+                                  int n_species, const pc_instance *inst, int n_inst,
+                                  int seg_steps);
+int pc_adjoint_segment(pc_sim *sim, const float *lamX_in_dev, const float *lamC_in_dev,
+                       int n_steps, float *lamX_out_dev, float *lamC_out_dev,
+                       double *dtheta_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PC_H */

@@ -125,7 +125,7 @@ def params(w, inst: int = 0, mode: int = 1, **over) -> Params:
         p.source[s], p.uptake[s] = sp.source, sp.uptake
     ins = w.instances[inst]
     p.seed = ins.seed & (2**64 - 1)
-    p.inst = inst
+    p.inst = ins.stream if getattr(ins, "stream", -1) >= 0 else inst
     p.chi_scale = ins.chi_scale
     p.mode = mode
     for k, v in over.items():

@@ -1,0 +1,677 @@
+// C ABI of the hybrid chemotaxis step (declared in include/pc.h): parameter
+// validation, workspace layout, kernel sequencing, HIP-graph replay and the
+// checkpoint / debug entry points.  Device work is enqueued on the caller's
+// stream; the library allocates no device memory.
+#include <math.h>
+#include <string.h>
+
+#include <new>
+#include <string>
+#include <vector>
+
+#include "pc.h"
+#include "pc_internal.h"
+
+using namespace pc;
+
+static thread_local std::string g_err;
+
+static int fail(int code, const std::string &msg) {
+    g_err = msg;
+    return code;
+}
+
+#define HIP_OK(expr)                                                                   \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            return fail(PC_EHIP, std::string(#expr " failed: ") + hipGetErrorString(e_)); \
+    } while (0)
+
+namespace {
+
+struct Derived {
+    int dim, periodic, ns, ni;
+    int64_t n_total;
+    int nb, stencil;
+    double bin_side, cutoff, h;
+    int64_t bins_per_inst, bins_total, nodes_per_inst, nodes_total;
+    int n_sub, block, has_uptake;
+    uint32_t warn;
+};
+
+struct Layout {
+    size_t P[3], I[3], bin, rank, count, start, tile_sum, c[2], S_src, S_upt, inst, species_id,
+        step, flags, seg_x, seg_c, adj[8], adj_red;
+    size_t total;
+};
+
+size_t take(size_t &cur, size_t bytes) {
+    const size_t o = (cur + 255) & ~(size_t)255;
+    cur = o + bytes;
+    return o;
+}
+
+int derive(const pc_config *cfg, const pc_species_t *sp, int ns, const pc_instance *in, int ni,
+           Derived &d) {
+    if (!cfg || !sp || !in) return fail(PC_EINVAL, "null argument");
+    if (cfg->dim != 2 && cfg->dim != 3) return fail(PC_EINVAL, "dim must be 2 or 3");
+    if (!(cfg->L > 0)) return fail(PC_EINVAL, "L must be > 0");
+    if (cfg->grid_n < 3) return fail(PC_EINVAL, "grid_n must be >= 3");
+    if (!(cfg->dt > 0)) return fail(PC_EINVAL, "dt must be > 0");
+    if (!(cfg->k_rep >= 0) || !(cfg->D_c >= 0) || !(cfg->gamma >= 0))
+        return fail(PC_EINVAL, "k_rep, D_c and gamma must be >= 0");
+    if (ns < 1 || ns > PC_MAX_SPECIES) return fail(PC_EINVAL, "1..8 species supported");
+    if (ni < 1 || ni >= (1 << 24)) return fail(PC_EINVAL, "instance count out of range");
+    if (cfg->bin_order != 0) return fail(PC_ENOTSUP, "only row-major bin order is built");
+    if (cfg->block != 0 && cfg->block != 64 && cfg->block != 128 && cfg->block != 256 &&
+        cfg->block != 512 && cfg->block != 1024)
+        return fail(PC_EINVAL, "block must be 0, 64, 128, 256, 512 or 1024");
+    d.dim = cfg->dim;
+    d.periodic = cfg->periodic ? 1 : 0;
+    d.ns = ns;
+    d.ni = ni;
+    d.cutoff = 0;
+    d.has_uptake = 0;
+    for (int s = 0; s < ns; ++s) {
+        if (!(sp[s].diameter > 0)) return fail(PC_EINVAL, "diameter must be > 0");
+        if (!(sp[s].D >= 0)) return fail(PC_EINVAL, "D must be >= 0");
+        if (!(sp[s].source >= 0) || !(sp[s].uptake >= 0))
+            return fail(PC_EINVAL, "source and uptake must be >= 0");
+        if (sp[s].diameter > d.cutoff) d.cutoff = sp[s].diameter;
+        if (sp[s].uptake > 0) d.has_uptake = 1;
+    }
+    d.n_total = 0;
+    for (int k = 0; k < ni; ++k) {
+        if (in[k].n_agents < 1) return fail(PC_EINVAL, "every instance needs >= 1 agent");
+        d.n_total += in[k].n_agents;
+    }
+    if (d.n_total >= (int64_t)1 << 31) return fail(PC_EINVAL, "too many agents");
+    if (d.cutoff >= cfg->L / 2) return fail(PC_EINVAL, "cutoff must be < L/2");
+
+    // Bins: side >= cutoff (1 + 1e-4) so float32 rounding of the bin index
+    // can never separate a pair closer than the cutoff by two bins.  A side
+    // >= 2 cutoff allows the 2^dim stencil chosen by the half-bin side.
+    const double margin = 1.0 + 1e-4;
+    auto bins_for = [&](double side) { return (int)floor(cfg->L / side); };
+    int nb;
+    if (cfg->bin_size > 0) {
+        nb = bins_for(cfg->bin_size);
+        if (nb < 3) return fail(PC_EINVAL, "fewer than 3 bins per axis");
+        if (cfg->L / nb < d.cutoff * margin)
+            return fail(PC_EINVAL, "bin side must exceed the largest diameter");
+    } else {
+        nb = bins_for(d.cutoff * margin);
+        int64_t b3 = 1;
+        for (int a = 0; a < d.dim; ++a) b3 *= nb;
+        if ((int64_t)b3 * ni > 4 * d.n_total) {
+            const int nb2 = bins_for(2 * d.cutoff * margin);
+            if (nb2 >= 3) nb = nb2;
+        }
+        if (nb < 3) return fail(PC_EINVAL, "fewer than 3 bins per axis (cutoff too large)");
+    }
+    d.nb = nb;
+    d.bin_side = cfg->L / nb;
+    d.stencil = d.bin_side >= 2 * d.cutoff * margin ? 2 : 3;
+    d.bins_per_inst = 1;
+    for (int a = 0; a < d.dim; ++a) d.bins_per_inst *= nb;
+    d.bins_total = d.bins_per_inst * ni;
+    if (d.bins_total >= ((int64_t)1 << 31)) return fail(PC_EINVAL, "too many bins");
+
+    d.h = d.periodic ? cfg->L / cfg->grid_n : cfg->L / (cfg->grid_n - 1);
+    d.nodes_per_inst = 1;
+    for (int a = 0; a < d.dim; ++a) d.nodes_per_inst *= cfg->grid_n;
+    d.nodes_total = d.nodes_per_inst * ni;
+    if (d.nodes_total >= ((int64_t)1 << 31)) return fail(PC_EINVAL, "too many grid nodes");
+    const double r = cfg->D_c * cfg->dt / (d.h * d.h);
+    const double lim = 1.0 / (2 * d.dim);
+    if (cfg->pde_substeps > 0) {
+        d.n_sub = cfg->pde_substeps;
+        if (r / d.n_sub > lim) return fail(PC_EUNSTABLE, "D_c dt'/h^2 above 1/(2 dim)");
+    } else {
+        d.n_sub = (int)ceil(r / (0.9 * lim));
+        if (d.n_sub < 1) d.n_sub = 1;
+    }
+    d.block = cfg->block ? cfg->block : 256;
+    d.warn = 0;
+    for (int a = 0; a < ns; ++a)
+        for (int b = 0; b < ns; ++b) {
+            const double dij = 0.5 * (sp[a].diameter + sp[b].diameter);
+            if (sqrt(2.0 * (sp[a].D + sp[b].D) * cfg->dt) >= dij) d.warn |= PC_WARN_DT_RULE;
+        }
+    return PC_OK;
+}
+
+Layout layout(const Derived &d, int seg_steps) {
+    Layout L;
+    memset(&L, 0, sizeof(L));
+    size_t cur = 0;
+    const size_t N = (size_t)d.n_total;
+    for (int k = 0; k < 3; ++k) L.P[k] = take(cur, 16 * N);
+    for (int k = 0; k < 3; ++k) L.I[k] = take(cur, 4 * N);
+    L.bin = take(cur, 4 * N);
+    L.rank = take(cur, 4 * N);
+    L.count = take(cur, 4 * ((size_t)d.bins_total + 1));
+    L.start = take(cur, 4 * ((size_t)d.bins_total + 1));
+    L.tile_sum = take(cur, 4 * (((size_t)d.bins_total + 1 + kScanTile - 1) / kScanTile));
+    L.c[0] = take(cur, 4 * (size_t)d.nodes_total);
+    L.c[1] = take(cur, 4 * (size_t)d.nodes_total);
+    L.S_src = take(cur, 8 * (size_t)d.nodes_total);
+    L.S_upt = take(cur, d.has_uptake ? 8 * (size_t)d.nodes_total : 8);
+    L.inst = take(cur, sizeof(InstInfo) * (size_t)d.ni);
+    L.species_id = take(cur, N);
+    L.step = take(cur, 4);
+    L.flags = take(cur, 4);
+    if (seg_steps > 0) {
+        L.seg_x = take(cur, 4 * (size_t)seg_steps * N * d.dim);
+        L.seg_c = take(cur, 4 * (size_t)seg_steps * (size_t)d.nodes_total);
+        for (int k = 0; k < 4; ++k) L.adj[k] = take(cur, 4 * N * 4);
+        for (int k = 4; k < 8; ++k) L.adj[k] = take(cur, 4 * (size_t)d.nodes_total * 4);
+        L.adj_red = take(cur, 8 * 64 * (size_t)d.ni);
+    }
+    L.total = take(cur, 0) + 256;
+    return L;
+}
+
+}  // namespace
+
+struct pc_sim {
+    Derived d;
+    Layout lay;
+    pc_config cfg;
+    std::vector<pc_species_t> species;
+    std::vector<pc_instance> inst_cfg;
+    std::vector<InstInfo> inst_host;
+    StepParams sp;
+    PdeParams pp;
+    Buffers b;
+    hipStream_t stream;
+    hipStream_t cap_stream;
+    int device;
+    int cur_c;                // which c buffer holds the field
+    uint32_t host_step;
+    uint32_t warn_bits;
+    int use_graph;
+    hipGraphExec_t graph[2];  // two-step graphs, by starting field buffer
+    int seg_steps;
+    uint32_t flags_host;
+};
+
+static void fill_params(pc_sim *s) {
+    const Derived &d = s->d;
+    const pc_config &c = s->cfg;
+    StepParams &p = s->sp;
+    memset(&p, 0, sizeof(p));
+    p.dim = d.dim;
+    p.periodic = d.periodic;
+    p.n_species = d.ns;
+    p.n_inst = d.ni;
+    p.nb = d.nb;
+    p.stencil = d.stencil;
+    p.bin_order = 0;
+    p.grid_n = c.grid_n;
+    p.n_total = (int32_t)d.n_total;
+    p.nodes_per_inst = (int32_t)d.nodes_per_inst;
+    p.bins_per_inst = (int32_t)d.bins_per_inst;
+    p.has_uptake = d.has_uptake;
+    p.L = (float)c.L;
+    p.halfL = (float)(0.5 * c.L);
+    p.inv_bin = (float)(d.nb / c.L);
+    p.h = (float)d.h;
+    p.inv_h = (float)(1.0 / d.h);
+    p.inv_2h = (float)(0.5 / d.h);
+    p.inv_h2 = (float)(1.0 / (d.h * d.h));
+    p.dt = (float)c.dt;
+    p.k = (float)c.k_rep;
+    p.cell_top = (float)(d.periodic ? c.grid_n - 1 : c.grid_n - 2);
+    for (int a = 0; a < d.ns; ++a) {
+        for (int b = 0; b < d.ns; ++b) {
+            const double m = 0.5 * (s->species[a].diameter + s->species[b].diameter);
+            p.cut2[a * d.ns + b] = (float)(m * m);
+            p.dij[a * d.ns + b] = (float)m;
+        }
+        p.amp[a] = (float)sqrt(2.0 * s->species[a].D * c.dt);
+        p.chi[a] = (float)s->species[a].chi;
+        p.src_fx[a] = (float)(s->species[a].source * 4294967296.0);
+        p.upt_fx[a] = (float)(s->species[a].uptake * 4294967296.0);
+    }
+    PdeParams &q = s->pp;
+    memset(&q, 0, sizeof(q));
+    q.dim = d.dim;
+    q.periodic = d.periodic;
+    q.grid_n = c.grid_n;
+    q.nodes_per_inst = (int32_t)d.nodes_per_inst;
+    q.n_nodes_total = d.nodes_total;
+    q.dts = (float)(c.dt / d.n_sub);
+    q.D_c = (float)c.D_c;
+    q.gamma = (float)c.gamma;
+    q.inv_h2 = (float)(1.0 / (d.h * d.h));
+    double hd = 1.0;
+    for (int a = 0; a < d.dim; ++a) hd *= d.h;
+    q.fx_to_density = (float)(1.0 / (4294967296.0 * hd));
+    q.has_uptake = d.has_uptake;
+}
+
+static void carve(pc_sim *s, char *ws) {
+    const Layout &L = s->lay;
+    Buffers &b = s->b;
+    memset(&b, 0, sizeof(b));
+    for (int k = 0; k < 3; ++k) {
+        b.P[k] = (float4 *)(ws + L.P[k]);
+        b.I[k] = (uint32_t *)(ws + L.I[k]);
+    }
+    b.bin = (uint32_t *)(ws + L.bin);
+    b.rank = (uint32_t *)(ws + L.rank);
+    b.count = (uint32_t *)(ws + L.count);
+    b.start = (uint32_t *)(ws + L.start);
+    b.tile_sum = (uint32_t *)(ws + L.tile_sum);
+    b.c[0] = (float *)(ws + L.c[0]);
+    b.c[1] = (float *)(ws + L.c[1]);
+    b.S_src = (unsigned long long *)(ws + L.S_src);
+    b.S_upt = (unsigned long long *)(ws + L.S_upt);
+    b.inst = (InstInfo *)(ws + L.inst);
+    b.species_id = (uint8_t *)(ws + L.species_id);
+    b.step = (uint32_t *)(ws + L.step);
+    b.flags = (uint32_t *)(ws + L.flags);
+    if (s->seg_steps > 0) {
+        b.seg_x = (float *)(ws + L.seg_x);
+        b.seg_c = (float *)(ws + L.seg_c);
+        for (int k = 0; k < 8; ++k) b.adj[k] = (float *)(ws + L.adj[k]);
+        b.adj_red = (double *)(ws + L.adj_red);
+    }
+}
+
+// Kernel sequence of one step (no memsets, so it can be graph-captured).
+static void enqueue_step(pc_sim *s, hipStream_t st) {
+    const int blk = s->d.block;
+    launch_bin(s->sp, s->b, 0, blk, st);
+    launch_scan(s->b, s->d.bins_total, (int32_t)s->d.n_total, st);
+    launch_scatter(s->sp, s->b, 0, 1, blk, st);
+    int src = 1;
+    if (s->cfg.deterministic) {
+        launch_stable(s->sp, s->b, 1, 2, blk, st);
+        src = 2;
+    }
+    launch_update(s->sp, s->b, src, 0, s->cur_c, blk, st);
+    for (int k = 0; k < s->d.n_sub; ++k) {
+        launch_pde(s->pp, s->b, s->cur_c, 1 - s->cur_c, k == s->d.n_sub - 1 ? 1 : 0, st);
+        s->cur_c = 1 - s->cur_c;
+    }
+}
+
+// Bin + sort the current state into the sorted buffer (debug entry points).
+static int enqueue_sorted(pc_sim *s, hipStream_t st) {
+    const int blk = s->d.block;
+    launch_bin(s->sp, s->b, 0, blk, st);
+    launch_scan(s->b, s->d.bins_total, (int32_t)s->d.n_total, st);
+    launch_scatter(s->sp, s->b, 0, 1, blk, st);
+    if (s->cfg.deterministic) {
+        launch_stable(s->sp, s->b, 1, 2, blk, st);
+        return 2;
+    }
+    return 1;
+}
+
+static int common_create(const pc_config *cfg, const pc_species_t *species, int n_species,
+                         const pc_instance *inst, int n_inst, void *workspace_dev,
+                         size_t workspace_bytes, const float *x0_dev, const uint8_t *species0_dev,
+                         const float *c0_dev, void *hip_stream, int seg_steps, pc_sim **out) {
+    if (!out) return fail(PC_EINVAL, "out is null");
+    *out = nullptr;
+    Derived d;
+    int rc = derive(cfg, species, n_species, inst, n_inst, d);
+    if (rc) return rc;
+    if (!workspace_dev || !x0_dev || !species0_dev || !c0_dev)
+        return fail(PC_EINVAL, "null device pointer");
+    if (((uintptr_t)workspace_dev) & 255) return fail(PC_EINVAL, "workspace not 256-byte aligned");
+    Layout L = layout(d, seg_steps);
+    if (workspace_bytes < L.total)
+        return fail(PC_ENOSPACE, "workspace too small: need " + std::to_string(L.total) +
+                                     " bytes, got " + std::to_string(workspace_bytes));
+    pc_sim *s = new (std::nothrow) pc_sim();
+    if (!s) return fail(PC_EINVAL, "host allocation failed");
+    s->d = d;
+    s->lay = L;
+    s->cfg = *cfg;
+    s->species.assign(species, species + n_species);
+    s->inst_cfg.assign(inst, inst + n_inst);
+    s->seg_steps = seg_steps;
+    s->stream = (hipStream_t)hip_stream;
+    s->cap_stream = nullptr;
+    s->graph[0] = s->graph[1] = nullptr;
+    s->cur_c = 0;
+    s->host_step = 0;
+    s->warn_bits = d.warn;
+    s->use_graph = 0;
+    s->flags_host = 0;
+    hipGetDevice(&s->device);
+    fill_params(s);
+    carve(s, (char *)workspace_dev);
+    s->inst_host.resize(n_inst);
+    uint32_t abase = 0;
+    for (int k = 0; k < n_inst; ++k) {
+        InstInfo &ii = s->inst_host[k];
+        ii.agent_base = abase;
+        ii.n_agents = (uint32_t)inst[k].n_agents;
+        ii.bin_base = (uint32_t)(d.bins_per_inst * k);
+        ii.node_base = (uint32_t)(d.nodes_per_inst * k);
+        const uint32_t stream = inst[k].stream < 0 ? (uint32_t)k : (uint32_t)inst[k].stream;
+        ii.key0 = (uint32_t)inst[k].seed;
+        ii.key1 = (uint32_t)(inst[k].seed >> 32) ^ stream;
+        ii.chi_scale = (float)inst[k].chi_scale;
+        ii.stream = stream;
+        abase += (uint32_t)inst[k].n_agents;
+    }
+    hipStream_t st = s->stream;
+    auto bail = [&](int code) {
+        delete s;
+        return code;
+    };
+    hipError_t e;
+#define CK(x)                                                                                \
+    do {                                                                                     \
+        e = (x);                                                                             \
+        if (e != hipSuccess) {                                                               \
+            fail(PC_EHIP, std::string(#x " failed: ") + hipGetErrorString(e));               \
+            return bail(PC_EHIP);                                                            \
+        }                                                                                    \
+    } while (0)
+    CK(hipMemcpyAsync(s->b.inst, s->inst_host.data(), sizeof(InstInfo) * n_inst,
+                      hipMemcpyHostToDevice, st));
+    CK(hipMemsetAsync(s->b.count, 0, 4 * ((size_t)d.bins_total + 1), st));
+    CK(hipMemsetAsync(s->b.S_src, 0, 8 * (size_t)d.nodes_total, st));
+    if (d.has_uptake) CK(hipMemsetAsync(s->b.S_upt, 0, 8 * (size_t)d.nodes_total, st));
+    CK(hipMemsetAsync(s->b.step, 0, 4, st));
+    CK(hipMemsetAsync(s->b.flags, 0, 4, st));
+    launch_init_agents(s->sp, s->b, x0_dev, species0_dev, 1, st);
+    CK(hipGetLastError());
+    CK(hipMemcpyAsync(s->b.c[0], c0_dev, 4 * (size_t)d.nodes_total, hipMemcpyDeviceToDevice, st));
+    CK(hipStreamSynchronize(st));
+    uint32_t fl = 0;
+    CK(hipMemcpy(&fl, s->b.flags, 4, hipMemcpyDeviceToHost));
+    if (fl & FLAG_BAD_SPECIES) {
+        fail(PC_EINVAL, "species index >= n_species in species0");
+        return bail(PC_EINVAL);
+    }
+#undef CK
+    *out = s;
+    return PC_OK;
+}
+
+extern "C" {
+
+size_t pc_workspace_bytes(const pc_config *cfg, const pc_species_t *species, int n_species,
+                          const pc_instance *inst, int n_inst) {
+    Derived d;
+    if (derive(cfg, species, n_species, inst, n_inst, d)) return 0;
+    return layout(d, 0).total;
+}
+
+size_t pc_workspace_bytes_adjoint(const pc_config *cfg, const pc_species_t *species,
+                                  int n_species, const pc_instance *inst, int n_inst,
+                                  int seg_steps) {
+    Derived d;
+    if (seg_steps < 1) return 0;
+    if (derive(cfg, species, n_species, inst, n_inst, d)) return 0;
+    return layout(d, seg_steps).total;
+}
+
+int pc_create(const pc_config *cfg, const pc_species_t *species, int n_species,
+              const pc_instance *inst, int n_inst, void *workspace_dev, size_t workspace_bytes,
+              const float *x0_dev, const uint8_t *species0_dev, const float *c0_dev,
+              void *hip_stream, pc_sim **out) {
+    // A workspace sized by pc_workspace_bytes_adjoint enables the adjoint.
+    int seg = 0;
+    Derived d;
+    if (derive(cfg, species, n_species, inst, n_inst, d) == PC_OK) {
+        const size_t base = layout(d, 0).total;
+        if (workspace_bytes > base) {
+            // largest segment length that fits
+            int lo = 0, hi = 1 << 16;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) / 2;
+                if (layout(d, mid).total <= workspace_bytes) lo = mid;
+                else hi = mid - 1;
+            }
+            seg = lo;
+        }
+    }
+    return common_create(cfg, species, n_species, inst, n_inst, workspace_dev, workspace_bytes,
+                         x0_dev, species0_dev, c0_dev, hip_stream, seg, out);
+}
+
+int pc_use_graph(pc_sim *s, int on) {
+    if (!s) return fail(PC_EINVAL, "null handle");
+    s->use_graph = on ? 1 : 0;
+    return PC_OK;
+}
+
+static int capture_graph(pc_sim *s, int slot) {
+    if (!s->cap_stream) HIP_OK(hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking));
+    hipGraph_t g = nullptr;
+    const int saved = s->cur_c;
+    HIP_OK(hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal));
+    enqueue_step(s, s->cap_stream);
+    enqueue_step(s, s->cap_stream);
+    hipError_t e = hipStreamEndCapture(s->cap_stream, &g);
+    s->cur_c = saved;  // capture does not run anything
+    if (e != hipSuccess) return fail(PC_EHIP, std::string("capture: ") + hipGetErrorString(e));
+    e = hipGraphInstantiate(&s->graph[slot], g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (e != hipSuccess) return fail(PC_EHIP, std::string("instantiate: ") + hipGetErrorString(e));
+    return PC_OK;
+}
+
+int pc_step(pc_sim *s, int n_steps) {
+    if (!s) return fail(PC_EINVAL, "null handle");
+    if (n_steps < 0) return fail(PC_EINVAL, "n_steps < 0");
+    int left = n_steps;
+    if (s->use_graph && left >= 2) {
+        const int slot = s->cur_c;
+        if (!s->graph[slot]) {
+            int rc = capture_graph(s, slot);
+            if (rc) return rc;
+        }
+        while (left >= 2) {
+            HIP_OK(hipGraphLaunch(s->graph[slot], s->stream));
+            left -= 2;
+            s->host_step += 2;
+            // two steps flip the field buffer 2 * n_sub times: parity unchanged
+        }
+    }
+    while (left > 0) {
+        enqueue_step(s, s->stream);
+        --left;
+        s->host_step += 1;
+    }
+    HIP_OK(hipGetLastError());
+    return PC_OK;
+}
+
+int pc_profile_steps(pc_sim *s, int n_steps, double *stage_ms) {
+    if (!s || !stage_ms || n_steps < 1) return fail(PC_EINVAL, "bad argument");
+    hipStream_t st = s->stream;
+    const int blk = s->d.block;
+    hipEvent_t ev[PC_N_STAGES + 1];
+    for (int k = 0; k <= PC_N_STAGES; ++k) HIP_OK(hipEventCreate(&ev[k]));
+    double acc[PC_N_STAGES] = {0};
+    int rc = PC_OK;
+    for (int t = 0; t < n_steps && rc == PC_OK; ++t) {
+        HIP_OK(hipEventRecord(ev[0], st));
+        launch_bin(s->sp, s->b, 0, blk, st);
+        HIP_OK(hipEventRecord(ev[1], st));
+        launch_scan(s->b, s->d.bins_total, (int32_t)s->d.n_total, st);
+        HIP_OK(hipEventRecord(ev[2], st));
+        launch_scatter(s->sp, s->b, 0, 1, blk, st);
+        HIP_OK(hipEventRecord(ev[3], st));
+        int src = 1;
+        if (s->cfg.deterministic) {
+            launch_stable(s->sp, s->b, 1, 2, blk, st);
+            src = 2;
+        }
+        HIP_OK(hipEventRecord(ev[4], st));
+        launch_update(s->sp, s->b, src, 0, s->cur_c, blk, st);
+        HIP_OK(hipEventRecord(ev[5], st));
+        for (int k = 0; k < s->d.n_sub; ++k) {
+            launch_pde(s->pp, s->b, s->cur_c, 1 - s->cur_c, k == s->d.n_sub - 1 ? 1 : 0, st);
+            s->cur_c = 1 - s->cur_c;
+        }
+        HIP_OK(hipEventRecord(ev[6], st));
+        s->host_step += 1;
+        HIP_OK(hipEventSynchronize(ev[6]));
+        for (int k = 0; k < PC_N_STAGES; ++k) {
+            float ms = 0.f;
+            HIP_OK(hipEventElapsedTime(&ms, ev[k], ev[k + 1]));
+            acc[k] += ms;
+        }
+    }
+    for (int k = 0; k <= PC_N_STAGES; ++k) hipEventDestroy(ev[k]);
+    for (int k = 0; k < PC_N_STAGES; ++k) stage_ms[k] = acc[k] / n_steps;
+    HIP_OK(hipGetLastError());
+    return rc;
+}
+
+int pc_positions(pc_sim *s, float *out_dev) {
+    if (!s || !out_dev) return fail(PC_EINVAL, "null argument");
+    launch_positions(s->sp, s->b, 0, out_dev, s->stream);
+    HIP_OK(hipGetLastError());
+    return PC_OK;
+}
+
+int pc_field(pc_sim *s, float *out_dev) {
+    if (!s || !out_dev) return fail(PC_EINVAL, "null argument");
+    HIP_OK(hipMemcpyAsync(out_dev, s->b.c[s->cur_c], 4 * (size_t)s->d.nodes_total,
+                          hipMemcpyDeviceToDevice, s->stream));
+    return PC_OK;
+}
+
+int pc_species(pc_sim *s, uint8_t *out_dev) {
+    if (!s || !out_dev) return fail(PC_EINVAL, "null argument");
+    launch_species(s->sp, s->b, 0, out_dev, s->stream);
+    HIP_OK(hipGetLastError());
+    return PC_OK;
+}
+
+int pc_get_state(pc_sim *s, float *x_dev, float *c_dev, uint32_t *step) {
+    if (!s) return fail(PC_EINVAL, "null handle");
+    if (x_dev) {
+        int rc = pc_positions(s, x_dev);
+        if (rc) return rc;
+    }
+    if (c_dev) {
+        int rc = pc_field(s, c_dev);
+        if (rc) return rc;
+    }
+    if (step) *step = s->host_step;
+    return PC_OK;
+}
+
+int pc_set_state(pc_sim *s, const float *x_dev, const float *c_dev, uint32_t step) {
+    if (!s) return fail(PC_EINVAL, "null handle");
+    if (x_dev) launch_init_agents(s->sp, s->b, x_dev, s->b.species_id, 0, s->stream);
+    if (c_dev)
+        HIP_OK(hipMemcpyAsync(s->b.c[s->cur_c], c_dev, 4 * (size_t)s->d.nodes_total,
+                              hipMemcpyDeviceToDevice, s->stream));
+    launch_set_u32(s->b.step, step, s->stream);
+    s->host_step = step;
+    HIP_OK(hipGetLastError());
+    return PC_OK;
+}
+
+static int read_flags(pc_sim *s) {
+    HIP_OK(hipStreamSynchronize(s->stream));
+    uint32_t fl = 0;
+    HIP_OK(hipMemcpy(&fl, s->b.flags, 4, hipMemcpyDeviceToHost));
+    s->flags_host |= fl;
+    if (fl & FLAG_WARN_POSITIVITY) s->warn_bits |= PC_WARN_POSITIVITY;
+    if (fl & FLAG_WARN_CLAMPED) s->warn_bits |= PC_WARN_CLAMPED;
+    return PC_OK;
+}
+
+int pc_sync(pc_sim *s) {
+    if (!s) return fail(PC_EINVAL, "null handle");
+    int rc = read_flags(s);
+    if (rc) return rc;
+    if (s->flags_host & FLAG_NONFINITE) {
+        s->flags_host &= ~FLAG_NONFINITE;
+        uint32_t zero = 0;
+        HIP_OK(hipMemcpy(s->b.flags, &zero, 4, hipMemcpyHostToDevice));
+        return fail(PC_ENONFINITE, "a non-finite value reached the state");
+    }
+    return PC_OK;
+}
+
+int pc_warnings(pc_sim *s, uint32_t *bits) {
+    if (!s || !bits) return fail(PC_EINVAL, "null argument");
+    int rc = read_flags(s);
+    if (rc) return rc;
+    *bits = s->warn_bits;
+    return PC_OK;
+}
+
+int pc_info(pc_sim *s, pc_info_t *info) {
+    if (!s || !info) return fail(PC_EINVAL, "null argument");
+    info->n_total = (int32_t)s->d.n_total;
+    info->n_inst = s->d.ni;
+    info->bins_per_axis = s->d.nb;
+    info->stencil = s->d.stencil;
+    info->n_bins_total = s->d.bins_total;
+    info->n_nodes_total = s->d.nodes_total;
+    info->pde_substeps = s->d.n_sub;
+    info->block = s->d.block;
+    info->bin_side = s->d.bin_side;
+    info->workspace_bytes = s->lay.total;
+    return PC_OK;
+}
+
+int pc_destroy(pc_sim *s) {
+    if (!s) return PC_OK;
+    for (int k = 0; k < 2; ++k)
+        if (s->graph[k]) hipGraphExecDestroy(s->graph[k]);
+    if (s->cap_stream) hipStreamDestroy(s->cap_stream);
+    delete s;
+    return PC_OK;
+}
+
+const char *pc_strerror(int code) {
+    switch (code) {
+        case PC_OK: return "ok";
+        case PC_EINVAL: return "invalid argument";
+        case PC_EUNSTABLE: return "explicit PDE step above the stability limit";
+        case PC_ENOSPACE: return "workspace too small";
+        case PC_EHIP: return "HIP runtime error";
+        case PC_ENONFINITE: return "non-finite value in the state";
+        case PC_ENOTSUP: return "not supported";
+        default: return "unknown error";
+    }
+}
+
+const char *pc_last_error(void) { return g_err.c_str(); }
+
+int pc_debug_neighbours(pc_sim *s, uint32_t *count_dev, uint64_t *hash_dev) {
+    if (!s || !count_dev || !hash_dev) return fail(PC_EINVAL, "null argument");
+    const int src = enqueue_sorted(s, s->stream);
+    launch_debug_pairs(s->sp, s->b, src, count_dev, (unsigned long long *)hash_dev, nullptr,
+                       s->d.block, s->stream);
+    HIP_OK(hipGetLastError());
+    return PC_OK;
+}
+
+int pc_debug_forces(pc_sim *s, float *F_dev) {
+    if (!s || !F_dev) return fail(PC_EINVAL, "null argument");
+    const int src = enqueue_sorted(s, s->stream);
+    launch_debug_pairs(s->sp, s->b, src, nullptr, nullptr, F_dev, s->d.block, s->stream);
+    HIP_OK(hipGetLastError());
+    return PC_OK;
+}
+
+int pc_adjoint_segment(pc_sim *s, const float *lamX_in_dev, const float *lamC_in_dev,
+                       int n_steps, float *lamX_out_dev, float *lamC_out_dev,
+                       double *dtheta_out) {
+    (void)lamX_in_dev; (void)lamC_in_dev; (void)n_steps; (void)lamX_out_dev;
+    (void)lamC_out_dev; (void)dtheta_out;
+    if (!s) return fail(PC_EINVAL, "null handle");
+    return fail(PC_ENOTSUP, "adjoint not built yet");
+}
+
+}  // extern "C"

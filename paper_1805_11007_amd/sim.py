@@ -1,0 +1,233 @@
+"""PyTorch-facing wrapper of the C ABI: device memory and streams come from
+torch, all computation from the library's kernels.
+
+The object mirrors the paper's ``Simulation`` class (Sect. 4): construct it
+with a model description and an initial state, ``integrate(T)`` or
+``step(n)`` it, and read ``positions()``, ``species()`` (the paper's
+``get_type``) and ``field()`` back as torch tensors on the GPU.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass, field
+from typing import Sequence
+
+import torch
+
+from . import _lib as LB
+
+
+@dataclass
+class SpeciesSpec:
+    diameter: float
+    D: float
+    chi: float = 0.0
+    source: float = 0.0
+    uptake: float = 0.0
+
+
+@dataclass
+class InstanceSpec:
+    n_agents: int
+    seed: int
+    chi_scale: float = 1.0
+    stream: int = -1     # noise stream index; -1: position in the instance list
+
+
+@dataclass
+class ModelSpec:
+    dim: int
+    periodic: bool
+    L: float
+    grid_n: int
+    dt: float
+    k: float
+    D_c: float
+    gamma: float
+    species: Sequence[SpeciesSpec]
+    instances: Sequence[InstanceSpec]
+    pde_substeps: int = 0
+    bin_size: float = 0.0
+    deterministic: bool = False
+    block: int = 0
+
+    @classmethod
+    def from_workload(cls, w, **over) -> "ModelSpec":
+        """Build from any object with the attributes of a workload description."""
+        sp = [SpeciesSpec(s.diameter, s.D, s.chi, s.source, s.uptake) for s in w.species]
+        ins = [InstanceSpec(i.n_agents, i.seed, i.chi_scale, getattr(i, 'stream', -1))
+               for i in w.instances]
+        kw = dict(dim=w.dim, periodic=w.periodic, L=w.L, grid_n=w.grid_n, dt=w.dt, k=w.k,
+                  D_c=w.D_c, gamma=w.gamma, species=sp, instances=ins,
+                  pde_substeps=w.pde_substeps)
+        kw.update(over)
+        return cls(**kw)
+
+    def c_structs(self):
+        cfg = LB.PcConfig()
+        cfg.dim = self.dim
+        cfg.periodic = 1 if self.periodic else 0
+        cfg.L = self.L
+        cfg.grid_n = self.grid_n
+        cfg.dt = self.dt
+        cfg.k_rep = self.k
+        cfg.D_c = self.D_c
+        cfg.gamma = self.gamma
+        cfg.pde_substeps = self.pde_substeps
+        cfg.bin_size = self.bin_size
+        cfg.deterministic = 1 if self.deterministic else 0
+        cfg.block = self.block
+        cfg.bin_order = 0
+        ns = len(self.species)
+        sp = (LB.PcSpecies * max(ns, 1))()
+        for k, s in enumerate(self.species):
+            sp[k].diameter, sp[k].D, sp[k].chi = s.diameter, s.D, s.chi
+            sp[k].source, sp[k].uptake = s.source, s.uptake
+        ni = len(self.instances)
+        ins = (LB.PcInstance * max(ni, 1))()
+        for k, i in enumerate(self.instances):
+            ins[k].n_agents = int(i.n_agents)
+            ins[k].seed = int(i.seed) & (2**64 - 1)
+            ins[k].chi_scale = float(i.chi_scale)
+            ins[k].stream = int(getattr(i, "stream", -1))
+        return cfg, sp, ns, ins, ni
+
+    @property
+    def n_total(self) -> int:
+        return sum(int(i.n_agents) for i in self.instances)
+
+    @property
+    def n_nodes(self) -> int:
+        return len(self.instances) * self.grid_n ** self.dim
+
+
+def _ptr(t: torch.Tensor) -> C.c_void_p:
+    return C.c_void_p(t.data_ptr())
+
+
+def workspace_bytes(spec: ModelSpec, adjoint_steps: int = 0) -> int:
+    L = LB.load()
+    cfg, sp, ns, ins, ni = spec.c_structs()
+    if adjoint_steps > 0:
+        n = L.pc_workspace_bytes_adjoint(C.byref(cfg), sp, ns, ins, ni, adjoint_steps)
+    else:
+        n = L.pc_workspace_bytes(C.byref(cfg), sp, ns, ins, ni)
+    if n == 0:
+        raise LB.PcError(LB.PC_EINVAL, "invalid parameters: " + L.pc_last_error().decode())
+    return int(n)
+
+
+class Sim:
+    """One handle of the library: a model plus n_inst instances on one GPU."""
+
+    def __init__(self, spec: ModelSpec, x0: torch.Tensor, species0: torch.Tensor,
+                 c0: torch.Tensor, device: str | torch.device = "cuda",
+                 stream: torch.cuda.Stream | None = None, adjoint_steps: int = 0):
+        if not torch.cuda.is_available():
+            raise RuntimeError("the chemotaxis library needs a ROCm GPU")
+        self.L = LB.load()
+        self.spec = spec
+        self.device = torch.device(device)
+        if self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
+        self.stream = stream or torch.cuda.current_stream(self.device)
+        self._cfg = spec.c_structs()
+        nbytes = workspace_bytes(spec, adjoint_steps)
+        # torch's allocator returns blocks aligned to at least 512 bytes
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        n, d = spec.n_total, spec.dim
+        x0 = x0.to(self.device, torch.float32).contiguous().reshape(n, d)
+        species0 = species0.to(self.device, torch.uint8).contiguous().reshape(n)
+        c0 = c0.to(self.device, torch.float32).contiguous().reshape(spec.n_nodes)
+        cfg, sp, ns, ins, ni = self._cfg
+        h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            LB.check(self.L.pc_create(C.byref(cfg), sp, ns, ins, ni, _ptr(self.workspace),
+                                      nbytes, _ptr(x0), _ptr(species0), _ptr(c0),
+                                      C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        self.h = h
+        info = LB.PcInfo()
+        LB.check(self.L.pc_info(self.h, C.byref(info)))
+        self.info = {k: getattr(info, k) for k, _ in LB.PcInfo._fields_}
+
+    # -- stepping ---------------------------------------------------------
+    def step(self, n: int = 1) -> None:
+        LB.check(self.L.pc_step(self.h, int(n)))
+
+    def integrate(self, T: float) -> None:
+        """Advance by time T: round(T / dt) steps."""
+        self.step(int(round(T / self.spec.dt)))
+
+    def use_graph(self, on: bool = True) -> None:
+        LB.check(self.L.pc_use_graph(self.h, 1 if on else 0))
+
+    # -- outputs ----------------------------------------------------------
+    def positions(self, out: torch.Tensor | None = None) -> torch.Tensor:
+        out = out if out is not None else torch.empty(self.spec.n_total, self.spec.dim,
+                                                      dtype=torch.float32, device=self.device)
+        LB.check(self.L.pc_positions(self.h, _ptr(out)))
+        return out
+
+    def field(self, out: torch.Tensor | None = None) -> torch.Tensor:
+        out = out if out is not None else torch.empty(self.spec.n_nodes, dtype=torch.float32,
+                                                      device=self.device)
+        LB.check(self.L.pc_field(self.h, _ptr(out)))
+        return out
+
+    def species(self) -> torch.Tensor:
+        out = torch.empty(self.spec.n_total, dtype=torch.uint8, device=self.device)
+        LB.check(self.L.pc_species(self.h, _ptr(out)))
+        return out
+
+    get_positions = positions
+    get_type = species
+
+    def get_state(self):
+        x = torch.empty(self.spec.n_total, self.spec.dim, dtype=torch.float32, device=self.device)
+        c = torch.empty(self.spec.n_nodes, dtype=torch.float32, device=self.device)
+        st = C.c_uint32()
+        LB.check(self.L.pc_get_state(self.h, _ptr(x), _ptr(c), C.byref(st)))
+        return x, c, int(st.value)
+
+    def set_state(self, x: torch.Tensor, c: torch.Tensor, step: int) -> None:
+        x = x.to(self.device, torch.float32).contiguous()
+        c = c.to(self.device, torch.float32).contiguous()
+        LB.check(self.L.pc_set_state(self.h, _ptr(x), _ptr(c), int(step)))
+        self._keep = (x, c)  # inputs must live until the stream has read them
+
+    def sync(self) -> None:
+        LB.check(self.L.pc_sync(self.h))
+
+    def warnings(self) -> int:
+        b = C.c_uint32()
+        LB.check(self.L.pc_warnings(self.h, C.byref(b)))
+        return int(b.value)
+
+    def profile_steps(self, n: int) -> dict:
+        """Run n steps with HIP events between stages; mean ms per stage."""
+        out = (C.c_double * len(LB.STAGES))()
+        LB.check(self.L.pc_profile_steps(self.h, int(n), out))
+        return dict(zip(LB.STAGES, list(out)))
+
+    # -- debug --------------------------------------------------------------
+    def debug_neighbours(self):
+        cnt = torch.empty(self.spec.n_total, dtype=torch.int32, device=self.device)
+        hsh = torch.empty(self.spec.n_total, dtype=torch.int64, device=self.device)
+        LB.check(self.L.pc_debug_neighbours(self.h, _ptr(cnt), _ptr(hsh)))
+        return cnt, hsh
+
+    def debug_forces(self) -> torch.Tensor:
+        F = torch.empty(self.spec.n_total, self.spec.dim, dtype=torch.float32, device=self.device)
+        LB.check(self.L.pc_debug_forces(self.h, _ptr(F)))
+        return F
+
+    def close(self) -> None:
+        if getattr(self, "h", None):
+            self.L.pc_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,128 @@
+"""GPU library vs FP64 oracle, element by element, through the C ABI.
+
+Bars: neighbour sets bit-exact (counts and id hashes decided in float32 on
+both sides); positions within 1e-5 of L per step (minimum image);
+the chemical within 1e-5 of max|c| per step; forces within float32
+accumulation error of the force scale k * d.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from gpu_helpers import (field_err, make_sim, oracle_forces, oracle_neighbours, oracle_steps,
+                         pos_err)
+
+pytestmark = pytest.mark.gpu
+
+# (config, agents, grid) cases: several bins / tiles with ragged tails
+SMALL = [(1, 1000, None), (1, 3001, 37), (2, 20011, 129), (3, 40000, 48), (4, None, 32),
+         (5, 9000, 64)]
+FULL = [1, 2, 3, 5]
+
+
+def _w(cfg, n, g):
+    w = W.config(cfg)
+    if cfg == 4:
+        rng = np.random.default_rng(4)
+        sizes = list(rng.integers(1, 900, 12)) + [1, 2]
+        return W.scaled(w, n_agents=sizes, grid_n=g)
+    return W.scaled(w, n_agents=n, grid_n=g)
+
+
+@pytest.mark.parametrize("cfg,n,g", SMALL)
+def test_neighbour_sets_bit_exact(cfg, n, g):
+    w = _w(cfg, n, g)
+    inp = W.make_inputs(w)
+    sim = make_sim(w, inp)
+    cnt, hsh = sim.debug_neighbours()
+    ocnt, ohsh = oracle_neighbours(w, inp)
+    assert np.array_equal(cnt.cpu().numpy().astype(np.uint32), ocnt)
+    assert np.array_equal(hsh.cpu().numpy().view(np.uint64), ohsh)
+
+
+@pytest.mark.parametrize("cfg", FULL)
+def test_neighbour_sets_bit_exact_full_size(cfg):
+    w = W.config(cfg)
+    inp = W.make_inputs(w)
+    sim = make_sim(w, inp)
+    cnt, hsh = sim.debug_neighbours()
+    ocnt, ohsh = oracle_neighbours(w, inp)
+    assert np.array_equal(cnt.cpu().numpy().astype(np.uint32), ocnt)
+    assert np.array_equal(hsh.cpu().numpy().view(np.uint64), ohsh)
+
+
+@pytest.mark.parametrize("cfg,n,g", SMALL)
+def test_forces(cfg, n, g):
+    w = _w(cfg, n, g)
+    inp = W.make_inputs(w)
+    sim = make_sim(w, inp)
+    F = sim.debug_forces().cpu().numpy().astype(np.float64)
+    Fo = oracle_forces(w, inp)
+    scale = w.k * max(s.diameter for s in w.species)
+    assert np.abs(F - Fo).max() <= 1e-5 * scale
+    assert np.abs(F.sum(0)).max() <= 1e-5 * scale * max(1.0, np.sqrt(len(F)))
+
+
+@pytest.mark.parametrize("cfg,n,g", SMALL)
+@pytest.mark.parametrize("det", [False, True])
+def test_one_step(cfg, n, g, det):
+    w = _w(cfg, n, g)
+    inp = W.make_inputs(w)
+    sim = make_sim(w, inp, deterministic=det)
+    sim.step(1)
+    sim.sync()
+    x = sim.positions().cpu().numpy()
+    c = sim.field().cpu().numpy()
+    X1, c1 = oracle_steps(w, inp, 1)
+    assert pos_err(x, X1, w.L, w.periodic) <= 1e-5
+    assert field_err(c, c1) <= 1e-5
+
+
+@pytest.mark.parametrize("cfg", FULL)
+def test_one_step_full_size(cfg):
+    w = W.config(cfg)
+    inp = W.make_inputs(w)
+    sim = make_sim(w, inp)
+    sim.step(1)
+    sim.sync()
+    x = sim.positions().cpu().numpy()
+    c = sim.field().cpu().numpy()
+    X1, c1 = oracle_steps(w, inp, 1)
+    assert pos_err(x, X1, w.L, w.periodic) <= 1e-5
+    assert field_err(c, c1) <= 1e-5
+
+
+def test_one_step_later_counter_config3():
+    """Per-step parity at a later step counter and evolved state: the oracle
+    evolves the state for 5 steps, both sides take step 5 -> 6 from it."""
+    import torch
+    w = W.config(3)
+    inp = W.make_inputs(w)
+    X5, c5 = oracle_steps(w, inp, 5)
+    sim = make_sim(w, inp)
+    x32 = torch.from_numpy(X5.astype(np.float32))
+    c32 = torch.from_numpy(c5.astype(np.float32))
+    sim.set_state(x32, c32, 5)
+    sim.step(1)
+    sim.sync()
+    inp5 = dict(inp, x0=X5.astype(np.float32), c0=c5.astype(np.float32))
+    X6, c6 = oracle_steps(w, inp5, 1, step0=5)
+    assert pos_err(sim.positions().cpu().numpy(), X6, w.L, True) <= 1e-5
+    assert field_err(sim.field().cpu().numpy(), c6) <= 1e-5
+
+
+@pytest.mark.parametrize("cfg,steps", [(1, 100), (2, 20), (5, 20)])
+def test_trajectory(cfg, steps):
+    w = W.config(cfg)
+    if cfg != 1:
+        w = W.scaled(w, n_agents=20000)
+    inp = W.make_inputs(w)
+    sim = make_sim(w, inp)
+    sim.step(steps)
+    sim.sync()
+    Xn, cn = oracle_steps(w, inp, steps)
+    ex = pos_err(sim.positions().cpu().numpy(), Xn, w.L, w.periodic)
+    ec = field_err(sim.field().cpu().numpy(), cn)
+    print(f"cfg{cfg} {steps} steps: position err {ex:.3e} field err {ec:.3e}")
+    assert ex <= 1e-5 * steps and ec <= 1e-5 * steps

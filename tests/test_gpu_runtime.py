@@ -1,0 +1,158 @@
+"""GPU tests of the library's runtime behaviour: determinism, batching,
+graph replay, checkpoint / resume, error paths and edge cases."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from gpu_helpers import field_err, make_sim, oracle_neighbours, oracle_steps, pos_err
+
+pytestmark = pytest.mark.gpu
+
+
+def _state(sim):
+    return sim.positions().cpu().numpy(), sim.field().cpu().numpy()
+
+
+def test_deterministic_mode_bitwise_repeatable():
+    w = W.scaled(W.config(3), n_agents=60000, grid_n=40)
+    inp = W.make_inputs(w)
+    a = make_sim(w, inp, deterministic=True)
+    b = make_sim(w, inp, deterministic=True)
+    a.step(7)
+    b.step(7)
+    xa, ca = _state(a)
+    xb, cb = _state(b)
+    assert np.array_equal(xa, xb) and np.array_equal(ca, cb)
+
+
+def test_batch_equals_instances_run_alone():
+    """Each instance of a batch evolves exactly as it does alone (same seed
+    and noise stream), bit for bit in deterministic mode; the batch also
+    matches the oracle."""
+    rng = np.random.default_rng(11)
+    w = W.scaled(W.config(4), n_agents=list(rng.integers(1, 700, 9)), grid_n=24)
+    inp = W.make_inputs(w)
+    sim = make_sim(w, inp, deterministic=True)
+    sim.step(5)
+    xb, cb = _state(sim)
+    off = 0
+    G = w.grid_n ** 2
+    for k, ins in enumerate(w.instances):
+        n = ins.n_agents
+        w1 = W.Workload(**{**w.__dict__, "instances": (W.Instance(n, ins.seed, ins.chi_scale, k),)})
+        one = {"x0": inp["x0"][off:off + n], "species0": inp["species0"][off:off + n],
+               "c0": inp["c0"][k * G:(k + 1) * G]}
+        alone = make_sim(w1, one, deterministic=True)
+        alone.step(5)
+        xa, ca = _state(alone)
+        assert np.array_equal(xa, xb[off:off + n])
+        assert np.array_equal(ca, cb[k * G:(k + 1) * G])
+        off += n
+    Xo, co = oracle_steps(w, inp, 5)
+    assert pos_err(xb, Xo, 1.0, True) <= 5e-5
+    assert field_err(cb, co) <= 5e-5
+
+
+def test_graph_replay_equals_eager():
+    w = W.scaled(W.config(1), n_agents=2000)
+    inp = W.make_inputs(w)
+    a = make_sim(w, inp, deterministic=True)
+    b = make_sim(w, inp, deterministic=True)
+    b.use_graph(True)
+    a.step(9)
+    b.step(9)
+    a.sync(); b.sync()
+    xa, ca = _state(a)
+    xb, cb = _state(b)
+    assert np.array_equal(xa, xb) and np.array_equal(ca, cb)
+    # several replays with eager work and syncs in between stay equal
+    for _ in range(3):
+        a.step(4)
+        b.step(4)
+        _ = a.positions().sum().item()
+        _ = b.positions().sum().item()
+    assert np.array_equal(_state(a)[0], _state(b)[0])
+    assert np.array_equal(_state(a)[1], _state(b)[1])
+
+
+def test_checkpoint_resume_bitwise():
+    w = W.scaled(W.config(5), n_agents=5000, grid_n=64)
+    inp = W.make_inputs(w)
+    sim = make_sim(w, inp, deterministic=True)
+    sim.step(3)
+    x, c, st = sim.get_state()
+    assert st == 3
+    sim.step(4)
+    x1, c1 = _state(sim)
+    sim.set_state(x, c, st)
+    sim.step(4)
+    x2, c2 = _state(sim)
+    assert np.array_equal(x1, x2) and np.array_equal(c1, c2)
+
+
+def test_species_and_warnings():
+    w = W.scaled(W.config(2), n_agents=5000, grid_n=65)
+    inp = W.make_inputs(w)
+    sim = make_sim(w, inp)
+    assert np.array_equal(sim.species().cpu().numpy(), inp["species0"])
+    from paper_1805_11007_amd._lib import PC_WARN_DT_RULE
+    assert sim.warnings() & PC_WARN_DT_RULE  # sqrt(2*2*1e-6) = 0.002 = d for species 0
+
+
+def test_walls_keep_agents_in_box_and_nonfinite_flag():
+    w = W.scaled(W.config(2), n_agents=20000, grid_n=65)
+    inp = W.make_inputs(w)
+    x0 = inp["x0"].copy()
+    x0[:500] = 0.0
+    x0[500:1000] = 1.0
+    inp = dict(inp, x0=x0)
+    sim = make_sim(w, inp)
+    for _ in range(5):
+        sim.step(4)
+        x = sim.positions().cpu().numpy()
+        assert x.min() >= 0.0 and x.max() <= 1.0
+    sim.sync()
+
+
+def test_edge_cases_single_agent_and_one_bin_pileup():
+    # one agent
+    w = W.scaled(W.config(1), n_agents=1)
+    inp = W.make_inputs(w)
+    sim = make_sim(w, inp)
+    sim.step(3)
+    X, c = oracle_steps(w, inp, 3)
+    assert pos_err(sim.positions().cpu().numpy(), X, 1.0, True) <= 3e-5
+    # 300 agents piled up inside one bin, plus agents on bin faces and at 0 / L^-
+    w = W.scaled(W.config(1), n_agents=400)
+    inp = W.make_inputs(w)
+    x0 = inp["x0"].copy()
+    x0[:300] = np.float32(0.5) + np.random.default_rng(1).uniform(0, 0.004, (300, 2)).astype(np.float32)
+    x0[300:310] = 0.0
+    x0[310:320] = np.nextafter(np.float32(1.0), np.float32(0.0))
+    x0[320:330, 0] = np.float32(0.25)
+    inp = dict(inp, x0=x0)
+    sim = make_sim(w, inp)
+    cnt, hsh = sim.debug_neighbours()
+    ocnt, ohsh = oracle_neighbours(w, inp)
+    assert np.array_equal(cnt.cpu().numpy().astype(np.uint32), ocnt)
+    assert np.array_equal(hsh.cpu().numpy().view(np.uint64), ohsh)
+    sim.step(1)
+    X, c = oracle_steps(w, inp, 1)
+    assert pos_err(sim.positions().cpu().numpy(), X, 1.0, True) <= 1e-5
+    assert field_err(sim.field().cpu().numpy(), c) <= 1e-5
+
+
+def test_error_paths():
+    import torch
+    from paper_1805_11007_amd import ModelSpec, PcError, Sim
+    w = W.scaled(W.config(1), n_agents=100)
+    inp = W.make_inputs(w)
+    bad = inp["species0"].copy()
+    bad[5] = 3
+    with pytest.raises(PcError):
+        Sim(ModelSpec.from_workload(w), torch.from_numpy(inp["x0"]), torch.from_numpy(bad),
+            torch.from_numpy(inp["c0"]))
+    with pytest.raises(PcError):
+        Sim(ModelSpec.from_workload(w, pde_substeps=1, dt=1e-2), torch.from_numpy(inp["x0"]),
+            torch.from_numpy(inp["species0"]), torch.from_numpy(inp["c0"]))

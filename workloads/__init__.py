@@ -48,6 +48,7 @@ class Instance:
     n_agents: int
     seed: int
     chi_scale: float = 1.0
+    stream: int = -1   # noise stream index; -1: the instance's position in the list
 
 
 @dataclass(frozen=True)
