@@ -32,22 +32,25 @@ HBM_PEAK_GBS = 8000.0
 
 def algorithmic_bytes(stage: str, w, n_sub: int) -> float:
     """Bytes a stage must move per launch (per step), by definition of what it
-    computes, independent of how the kernels are built:
-      update:  per agent read position + id/species, write position
-               (8 dim + 4 bytes); per node read c once and write each
-               deposited field once (4 + 4 F bytes), F = fields deposited.
-      pde:     per node and substep read and write c (8 bytes), plus one read
-               of each deposited field (4 F bytes).
-      bin:     per agent read position, write bin and rank (4 dim + 8).
-      scatter: per agent read position/id/bin/rank, write position/id
-               (4 dim + 12 read, 4 dim + 4 write) -> 8 dim + 16.
-      scan:    per bin read count, write start (8 bytes).
+    computes, independent of how the kernels are built (N agents, G nodes,
+    d = dim, F = deposited fields, 1 without uptake, else 2):
+      update:  read position + id/species, write position (8d + 4 per agent);
+               read the chemical once (4 per node)
+      deposit: read position + species (4d + 1 per agent); write each
+               deposited field once (4F per node)
+      pde:     per substep read and write c (8 per node), read each deposited
+               field once (4F per node)
+      bin:     read position, write bin and rank (4d + 8 per agent)
+      scatter: read position/id/bin/rank, write position/id (8d + 16 per agent)
+      scan:    read count, write start (8 per bin)
     """
     N, d = w.n_total, w.dim
     G = w.n_inst * w.grid_n ** d
     F = 2 if any(s.uptake > 0 for s in w.species) else 1
     if stage == "update":
-        return N * (8 * d + 4) + G * (4 + 4 * F)
+        return N * (8 * d + 4) + G * 4
+    if stage == "deposit":
+        return N * (4 * d + 1) + G * 4 * F
     if stage == "pde":
         return G * (8 * n_sub + 4 * F)
     if stage == "bin":

@@ -185,9 +185,10 @@ int pc_info(pc_sim *sim, pc_info_t *info);
 /* Measurement: run n_steps steps eagerly with HIP events between the
  * stages of each step and return the mean milliseconds per step of every
  * stage in stage_ms[PC_N_STAGES] (host): bin, scan, scatter, stable order,
- * update, PDE.  Synchronises the stream; advances the state like pc_step. */
+ * update, deposit, PDE.  Synchronises the stream; advances the state like
+ * pc_step. */
 enum { PC_STAGE_BIN, PC_STAGE_SCAN, PC_STAGE_SCATTER, PC_STAGE_STABLE, PC_STAGE_UPDATE,
-       PC_STAGE_PDE, PC_N_STAGES };
+       PC_STAGE_DEPOSIT, PC_STAGE_PDE, PC_N_STAGES };
 int pc_profile_steps(pc_sim *sim, int n_steps, double *stage_ms);
 
 /* Release the handle (does not touch caller memory). */

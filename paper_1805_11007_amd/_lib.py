@@ -20,7 +20,7 @@ EXPORTS = (
     "pc_warnings", "pc_info", "pc_destroy", "pc_strerror", "pc_last_error",
     "pc_debug_neighbours", "pc_debug_forces", "pc_adjoint_segment", "pc_profile_steps",
 )
-STAGES = ("bin", "scan", "scatter", "stable", "update", "pde")
+STAGES = ("bin", "scan", "scatter", "stable", "update", "deposit", "pde")
 
 
 class PcConfig(C.Structure):

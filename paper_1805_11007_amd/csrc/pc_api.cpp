@@ -104,7 +104,11 @@ int derive(const pc_config *cfg, const pc_species_t *sp, int ns, const pc_instan
         nb = bins_for(d.cutoff * margin);
         int64_t b3 = 1;
         for (int a = 0; a < d.dim; ++a) b3 *= nb;
-        if ((int64_t)b3 * ni > 4 * d.n_total) {
+        // the 3^dim stencil at side ~cutoff tests the fewest candidates; only
+        // when its bin table dwarfs the agents and nodes use side >= 2 cutoff
+        int64_t g3 = 1;
+        for (int a = 0; a < d.dim; ++a) g3 *= cfg->grid_n;
+        if ((int64_t)b3 * ni > 16 * (d.n_total + g3 * ni)) {
             const int nb2 = bins_for(2 * d.cutoff * margin);
             if (nb2 >= 3) nb = nb2;
         }
@@ -195,6 +199,10 @@ struct pc_sim {
     hipGraphExec_t graph[2];  // two-step graphs, by starting field buffer
     int seg_steps;
     uint32_t flags_host;
+    // Pipeline state.  A step is: [bin] scan scatter [stable] update deposit pde.
+    // binned:  count/bin/rank hold the cell-list counts of the positions in P[0]
+    // sorted:  P[sorted_src] / start hold the cell-sorted current positions
+    int binned, sorted, sorted_src;
 };
 
 static void fill_params(pc_sim *s) {
@@ -281,36 +289,43 @@ static void carve(pc_sim *s, char *ws) {
     }
 }
 
-// Kernel sequence of one step (no memsets, so it can be graph-captured).
-static void enqueue_step(pc_sim *s, hipStream_t st) {
+// Cell-sort the current positions (scan of the counts, scatter, optional
+// id-stable order) unless already done.
+static void ensure_sorted(pc_sim *s, hipStream_t st) {
+    if (s->sorted) return;
     const int blk = s->d.block;
-    launch_bin(s->sp, s->b, 0, blk, st);
+    if (!s->binned) launch_bin(s->sp, s->b, 0, blk, st);
     launch_scan(s->b, s->d.bins_total, (int32_t)s->d.n_total, st);
+    s->binned = 0;
     launch_scatter(s->sp, s->b, 0, 1, blk, st);
-    int src = 1;
+    s->sorted_src = 1;
     if (s->cfg.deterministic) {
         launch_stable(s->sp, s->b, 1, 2, blk, st);
-        src = 2;
+        s->sorted_src = 2;
     }
-    launch_update(s->sp, s->b, src, 0, s->cur_c, blk, st);
+    s->sorted = 1;
+}
+
+// PDE substeps of a step after the deposit; the last one clears the deposits.
+static void enqueue_pde(pc_sim *s, hipStream_t st) {
     for (int k = 0; k < s->d.n_sub; ++k) {
         launch_pde(s->pp, s->b, s->cur_c, 1 - s->cur_c, k == s->d.n_sub - 1 ? 1 : 0, st);
         s->cur_c = 1 - s->cur_c;
     }
 }
 
-// Bin + sort the current state into the sorted buffer (debug entry points).
-static int enqueue_sorted(pc_sim *s, hipStream_t st) {
-    const int blk = s->d.block;
-    launch_bin(s->sp, s->b, 0, blk, st);
-    launch_scan(s->b, s->d.bins_total, (int32_t)s->d.n_total, st);
-    launch_scatter(s->sp, s->b, 0, 1, blk, st);
-    if (s->cfg.deterministic) {
-        launch_stable(s->sp, s->b, 1, 2, blk, st);
-        return 2;
-    }
-    return 1;
+// Kernel sequence of one step (kernels only, so it can be graph-captured).
+static void enqueue_step(pc_sim *s, hipStream_t st) {
+    ensure_sorted(s, st);
+    launch_update(s->sp, s->b, s->sorted_src, 0, s->cur_c, s->d.block, st);
+    launch_deposit(s->sp, s->b, 0, st);
+    enqueue_pde(s, st);
+    launch_step_inc(s->b, st);
+    s->binned = 1;
+    s->sorted = 0;
 }
+
+static int is_steady(const pc_sim *s) { return s->binned && !s->sorted; }
 
 static int common_create(const pc_config *cfg, const pc_species_t *species, int n_species,
                          const pc_instance *inst, int n_inst, void *workspace_dev,
@@ -344,7 +359,10 @@ static int common_create(const pc_config *cfg, const pc_species_t *species, int 
     s->warn_bits = d.warn;
     s->use_graph = 0;
     s->flags_host = 0;
-    hipGetDevice(&s->device);
+    s->binned = 0;
+    s->sorted = 0;
+    s->sorted_src = 1;
+    (void)hipGetDevice(&s->device);
     fill_params(s);
     carve(s, (char *)workspace_dev);
     s->inst_host.resize(n_inst);
@@ -386,6 +404,8 @@ static int common_create(const pc_config *cfg, const pc_species_t *species, int 
     launch_init_agents(s->sp, s->b, x0_dev, species0_dev, 1, st);
     CK(hipGetLastError());
     CK(hipMemcpyAsync(s->b.c[0], c0_dev, 4 * (size_t)d.nodes_total, hipMemcpyDeviceToDevice, st));
+    launch_bin(s->sp, s->b, 0, d.block, st);
+    s->binned = 1;
     CK(hipStreamSynchronize(st));
     uint32_t fl = 0;
     CK(hipMemcpy(&fl, s->b.flags, 4, hipMemcpyDeviceToHost));
@@ -449,15 +469,17 @@ int pc_use_graph(pc_sim *s, int on) {
 static int capture_graph(pc_sim *s, int slot) {
     if (!s->cap_stream) HIP_OK(hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking));
     hipGraph_t g = nullptr;
-    const int saved = s->cur_c;
+    const int saved_c = s->cur_c;
     HIP_OK(hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal));
     enqueue_step(s, s->cap_stream);
     enqueue_step(s, s->cap_stream);
     hipError_t e = hipStreamEndCapture(s->cap_stream, &g);
-    s->cur_c = saved;  // capture does not run anything
+    // capture runs nothing: a steady step leaves the state flags steady, and
+    // two steps flip the field buffer 2 * n_sub times
+    s->cur_c = saved_c;
     if (e != hipSuccess) return fail(PC_EHIP, std::string("capture: ") + hipGetErrorString(e));
     e = hipGraphInstantiate(&s->graph[slot], g, nullptr, nullptr, 0);
-    hipGraphDestroy(g);
+    (void)hipGraphDestroy(g);
     if (e != hipSuccess) return fail(PC_EHIP, std::string("instantiate: ") + hipGetErrorString(e));
     return PC_OK;
 }
@@ -466,17 +488,23 @@ int pc_step(pc_sim *s, int n_steps) {
     if (!s) return fail(PC_EINVAL, "null handle");
     if (n_steps < 0) return fail(PC_EINVAL, "n_steps < 0");
     int left = n_steps;
-    if (s->use_graph && left >= 2) {
-        const int slot = s->cur_c;
-        if (!s->graph[slot]) {
-            int rc = capture_graph(s, slot);
-            if (rc) return rc;
+    if (s->use_graph) {
+        while (left > 0 && !is_steady(s)) {
+            enqueue_step(s, s->stream);
+            --left;
+            s->host_step += 1;
         }
-        while (left >= 2) {
-            HIP_OK(hipGraphLaunch(s->graph[slot], s->stream));
-            left -= 2;
-            s->host_step += 2;
-            // two steps flip the field buffer 2 * n_sub times: parity unchanged
+        if (left >= 2) {
+            const int slot = s->cur_c;
+            if (!s->graph[slot]) {
+                int rc = capture_graph(s, slot);
+                if (rc) return rc;
+            }
+            while (left >= 2) {
+                HIP_OK(hipGraphLaunch(s->graph[slot], s->stream));
+                left -= 2;
+                s->host_step += 2;
+            }
         }
     }
     while (left > 0) {
@@ -495,40 +523,51 @@ int pc_profile_steps(pc_sim *s, int n_steps, double *stage_ms) {
     hipEvent_t ev[PC_N_STAGES + 1];
     for (int k = 0; k <= PC_N_STAGES; ++k) HIP_OK(hipEventCreate(&ev[k]));
     double acc[PC_N_STAGES] = {0};
-    int rc = PC_OK;
-    for (int t = 0; t < n_steps && rc == PC_OK; ++t) {
-        HIP_OK(hipEventRecord(ev[0], st));
-        launch_bin(s->sp, s->b, 0, blk, st);
-        HIP_OK(hipEventRecord(ev[1], st));
-        launch_scan(s->b, s->d.bins_total, (int32_t)s->d.n_total, st);
-        HIP_OK(hipEventRecord(ev[2], st));
-        launch_scatter(s->sp, s->b, 0, 1, blk, st);
-        HIP_OK(hipEventRecord(ev[3], st));
-        int src = 1;
-        if (s->cfg.deterministic) {
+    for (int t = 0; t < n_steps; ++t) {
+        HIP_OK(hipEventRecord(ev[PC_STAGE_BIN], st));
+        const int was_sorted = s->sorted;
+        if (!was_sorted && !s->binned) {
+            launch_bin(s->sp, s->b, 0, blk, st);
+            s->binned = 1;
+        }
+        HIP_OK(hipEventRecord(ev[PC_STAGE_SCAN], st));
+        if (!was_sorted) {
+            launch_scan(s->b, s->d.bins_total, (int32_t)s->d.n_total, st);
+            s->binned = 0;
+        }
+        HIP_OK(hipEventRecord(ev[PC_STAGE_SCATTER], st));
+        if (!was_sorted) {
+            launch_scatter(s->sp, s->b, 0, 1, blk, st);
+            s->sorted_src = 1;
+        }
+        HIP_OK(hipEventRecord(ev[PC_STAGE_STABLE], st));
+        if (!was_sorted && s->cfg.deterministic) {
             launch_stable(s->sp, s->b, 1, 2, blk, st);
-            src = 2;
+            s->sorted_src = 2;
         }
-        HIP_OK(hipEventRecord(ev[4], st));
-        launch_update(s->sp, s->b, src, 0, s->cur_c, blk, st);
-        HIP_OK(hipEventRecord(ev[5], st));
-        for (int k = 0; k < s->d.n_sub; ++k) {
-            launch_pde(s->pp, s->b, s->cur_c, 1 - s->cur_c, k == s->d.n_sub - 1 ? 1 : 0, st);
-            s->cur_c = 1 - s->cur_c;
-        }
-        HIP_OK(hipEventRecord(ev[6], st));
+        s->sorted = 1;
+        HIP_OK(hipEventRecord(ev[PC_STAGE_UPDATE], st));
+        launch_update(s->sp, s->b, s->sorted_src, 0, s->cur_c, blk, st);
+        HIP_OK(hipEventRecord(ev[PC_STAGE_DEPOSIT], st));
+        launch_deposit(s->sp, s->b, 0, st);
+        HIP_OK(hipEventRecord(ev[PC_STAGE_PDE], st));
+        enqueue_pde(s, st);
+        launch_step_inc(s->b, st);
+        s->binned = 1;
+        s->sorted = 0;
+        HIP_OK(hipEventRecord(ev[PC_N_STAGES], st));
         s->host_step += 1;
-        HIP_OK(hipEventSynchronize(ev[6]));
+        HIP_OK(hipEventSynchronize(ev[PC_N_STAGES]));
         for (int k = 0; k < PC_N_STAGES; ++k) {
             float ms = 0.f;
             HIP_OK(hipEventElapsedTime(&ms, ev[k], ev[k + 1]));
             acc[k] += ms;
         }
     }
-    for (int k = 0; k <= PC_N_STAGES; ++k) hipEventDestroy(ev[k]);
+    for (int k = 0; k <= PC_N_STAGES; ++k) (void)hipEventDestroy(ev[k]);
     for (int k = 0; k < PC_N_STAGES; ++k) stage_ms[k] = acc[k] / n_steps;
     HIP_OK(hipGetLastError());
-    return rc;
+    return PC_OK;
 }
 
 int pc_positions(pc_sim *s, float *out_dev) {
@@ -568,7 +607,13 @@ int pc_get_state(pc_sim *s, float *x_dev, float *c_dev, uint32_t *step) {
 
 int pc_set_state(pc_sim *s, const float *x_dev, const float *c_dev, uint32_t step) {
     if (!s) return fail(PC_EINVAL, "null handle");
-    if (x_dev) launch_init_agents(s->sp, s->b, x_dev, s->b.species_id, 0, s->stream);
+    if (x_dev) {
+        if (s->binned) launch_zero_u32(s->b.count, s->d.bins_total + 1, s->stream);
+        launch_init_agents(s->sp, s->b, x_dev, s->b.species_id, 0, s->stream);
+        launch_bin(s->sp, s->b, 0, s->d.block, s->stream);
+        s->binned = 1;
+        s->sorted = 0;
+    }
     if (c_dev)
         HIP_OK(hipMemcpyAsync(s->b.c[s->cur_c], c_dev, 4 * (size_t)s->d.nodes_total,
                               hipMemcpyDeviceToDevice, s->stream));
@@ -627,8 +672,8 @@ int pc_info(pc_sim *s, pc_info_t *info) {
 int pc_destroy(pc_sim *s) {
     if (!s) return PC_OK;
     for (int k = 0; k < 2; ++k)
-        if (s->graph[k]) hipGraphExecDestroy(s->graph[k]);
-    if (s->cap_stream) hipStreamDestroy(s->cap_stream);
+        if (s->graph[k]) (void)hipGraphExecDestroy(s->graph[k]);
+    if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
     delete s;
     return PC_OK;
 }
@@ -650,8 +695,8 @@ const char *pc_last_error(void) { return g_err.c_str(); }
 
 int pc_debug_neighbours(pc_sim *s, uint32_t *count_dev, uint64_t *hash_dev) {
     if (!s || !count_dev || !hash_dev) return fail(PC_EINVAL, "null argument");
-    const int src = enqueue_sorted(s, s->stream);
-    launch_debug_pairs(s->sp, s->b, src, count_dev, (unsigned long long *)hash_dev, nullptr,
+    ensure_sorted(s, s->stream);
+    launch_debug_pairs(s->sp, s->b, s->sorted_src, count_dev, (unsigned long long *)hash_dev, nullptr,
                        s->d.block, s->stream);
     HIP_OK(hipGetLastError());
     return PC_OK;
@@ -659,8 +704,8 @@ int pc_debug_neighbours(pc_sim *s, uint32_t *count_dev, uint64_t *hash_dev) {
 
 int pc_debug_forces(pc_sim *s, float *F_dev) {
     if (!s || !F_dev) return fail(PC_EINVAL, "null argument");
-    const int src = enqueue_sorted(s, s->stream);
-    launch_debug_pairs(s->sp, s->b, src, nullptr, nullptr, F_dev, s->d.block, s->stream);
+    ensure_sorted(s, s->stream);
+    launch_debug_pairs(s->sp, s->b, s->sorted_src, nullptr, nullptr, F_dev, s->d.block, s->stream);
     HIP_OK(hipGetLastError());
     return PC_OK;
 }

@@ -94,8 +94,11 @@ void launch_stable(const StepParams &p, const Buffers &b, int src, int dst, int 
                    hipStream_t s);
 void launch_update(const StepParams &p, const Buffers &b, int src, int dst, int cbuf, int block,
                    hipStream_t s);
+void launch_deposit(const StepParams &p, const Buffers &b, int src, hipStream_t s);
 void launch_pde(const PdeParams &q, const Buffers &b, int cin, int cout, int last,
                 hipStream_t s);
+void launch_step_inc(const Buffers &b, hipStream_t s);
+void launch_zero_u32(uint32_t *d, int64_t n, hipStream_t s);
 void launch_positions(const StepParams &p, const Buffers &b, int src, float *out,
                       hipStream_t s);
 void launch_species(const StepParams &p, const Buffers &b, int src, uint8_t *out, hipStream_t s);

@@ -125,12 +125,65 @@ __device__ __forceinline__ uint32_t agent_bin(const StepParams &p, float4 x) {
     return (uint32_t)(bx + p.nb * (by + p.nb * bz));
 }
 
+// Candidates j in [a, e) of one contiguous bin range.  The neighbour test is
+// the float32 r^2 < d_ij^2 on dx = (x_j - x_i) (+ seam shift); the force
+// k (d - r) / r is evaluated as k d / r - k.  In debug mode the neighbour
+// count and the id hash are accumulated as well (self excluded).
+template <int DIM, int NS, bool DBG, bool SHIFT>
+__device__ __forceinline__ void pair_range(const StepParams &p, const SpTab &tab,
+                                           const float4 *__restrict__ Ps,
+                                           const uint32_t *__restrict__ Is, uint32_t a,
+                                           uint32_t e, const float4 &pi, int si, float sx,
+                                           float sy, float sz, const float c2row[2],
+                                           const float kdrow[2], uint32_t self, float F[3],
+                                           uint32_t &cnt, unsigned long long &hs) {
+    const float kk = p.k;
+    for (uint32_t j = a; j < e; ++j) {
+        const float4 q = Ps[j];
+        float dx = q.x - pi.x, dy = q.y - pi.y, dz = 0.0f;
+        if (SHIFT) {
+            dx = dx + sx;
+            dy = dy + sy;
+        }
+        float r2 = dx * dx + dy * dy;
+        if (DIM == 3) {
+            dz = q.z - pi.z;
+            if (SHIFT) dz = dz + sz;
+            r2 = r2 + dz * dz;
+        }
+        float c2, kd;
+        if (NS == 1) {
+            c2 = c2row[0];
+            kd = kdrow[0];
+        } else if (NS == 2) {
+            const bool s1 = species_of(q.w) != 0;
+            c2 = s1 ? c2row[1] : c2row[0];
+            kd = s1 ? kdrow[1] : kdrow[0];
+        } else {
+            const int sj = species_of(q.w);
+            c2 = tab.cut2[si * p.n_species + sj];
+            kd = kk * tab.dij[si * p.n_species + sj];
+        }
+        if (DBG && r2 < c2 && j != self) {
+            cnt += 1;
+            hs += splitmix64((unsigned long long)Is[j]);
+        }
+        if (r2 < c2 && r2 > 0.0f) {
+            const float f = fmaf(kd, rsqrtf(r2), -kk);
+            F[0] = fmaf(-f, dx, F[0]);
+            F[1] = fmaf(-f, dy, F[1]);
+            if (DIM == 3) F[2] = fmaf(-f, dz, F[2]);
+        }
+    }
+}
+
 // Pair loop over the neighbour bins of agent `self` (cell-sorted index) at
-// position pi.  Accumulates the repulsion F_i = -sum k (d_ij - r) dx / r
-// over neighbours with r > 0 and, in debug mode, the neighbour count and id
-// hash.  dx = x_j - x_i, plus -L / +L for bins reached through the periodic
-// seam: for every pair closer than the cutoff this is exactly the minimum
-// image, because the seam is crossed iff |x_j - x_i| > L/2 for such pairs.
+// position pi: F_i = -sum k (d_ij - r) dx / r over neighbours with r > 0.
+// dx = x_j - x_i, plus -L / +L for bins reached through the periodic seam:
+// for every pair closer than the cutoff this is exactly the minimum image,
+// because the seam is crossed iff |x_j - x_i| > L/2 for such pairs.
+// Along x, neighbouring bins are adjacent in memory, so each (y, z) row of
+// the stencil is one contiguous agent range (two at the seam).
 template <int DIM, int NS, int STENCIL, bool DBG>
 __device__ __forceinline__ void pair_loop(const StepParams &p, const SpTab &tab,
                                           const float4 *__restrict__ Ps,
@@ -141,6 +194,9 @@ __device__ __forceinline__ void pair_loop(const StepParams &p, const SpTab &tab,
     const int nb = p.nb;
     const float pc[3] = {pi.x, pi.y, pi.z};
     int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+    // squared distance from x_i to the lower / upper face of its own bin
+    float glo2[3] = {0.f, 0.f, 0.f}, ghi2[3] = {0.f, 0.f, 0.f};
+    const float side = p.L / (float)nb;
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
         const float s = fmaxf(pc[a] * p.inv_bin, 0.0f);
@@ -148,66 +204,39 @@ __device__ __forceinline__ void pair_loop(const StepParams &p, const SpTab &tab,
         if (STENCIL == 3) {
             lo[a] = b - 1;
             hi[a] = b + 1;
+            const float f = fminf(fmaxf(s - (float)b, 0.0f), 1.0f);
+            glo2[a] = (f * side) * (f * side);
+            ghi2[a] = ((1.0f - f) * side) * ((1.0f - f) * side);
         } else {
             const int up = (s - (float)b) >= 0.5f ? 1 : 0;
             lo[a] = b - 1 + up;
             hi[a] = lo[a] + 1;
         }
     }
-    // contact tables of species si
-    float c2row[2] = {0.f, 0.f}, drow[2] = {0.f, 0.f};
+    float c2row[2] = {0.f, 0.f}, kdrow[2] = {0.f, 0.f};
     if (NS == 1) {
         c2row[0] = p.cut2[0];
-        drow[0] = p.dij[0];
+        kdrow[0] = p.k * p.dij[0];
     } else if (NS == 2) {
         c2row[0] = p.cut2[si * 2 + 0];
         c2row[1] = p.cut2[si * 2 + 1];
-        drow[0] = p.dij[si * 2 + 0];
-        drow[1] = p.dij[si * 2 + 1];
+        kdrow[0] = p.k * p.dij[si * 2 + 0];
+        kdrow[1] = p.k * p.dij[si * 2 + 1];
     }
+    // Bins whose nearest face is farther than the largest contact distance
+    // of species si cannot hold a neighbour (3^dim stencil only).  The
+    // threshold carries a 1e-3 margin over float32 rounding of the faces.
+    float cmax2;
+    if (NS == 1) {
+        cmax2 = c2row[0];
+    } else if (NS == 2) {
+        cmax2 = fmaxf(c2row[0], c2row[1]);
+    } else {
+        cmax2 = 0.0f;
+        for (int t = 0; t < p.n_species; ++t) cmax2 = fmaxf(cmax2, tab.cut2[si * p.n_species + t]);
+    }
+    cmax2 *= 1.001f;
     const float L = p.L;
-    const float kk = p.k;
-
-    auto scan = [&](uint32_t a, uint32_t e, float sx, float sy, float sz) {
-        for (uint32_t j = a; j < e; ++j) {
-            const float4 q = Ps[j];
-            const float dx = (q.x - pi.x) + sx;
-            const float dy = (q.y - pi.y) + sy;
-            float r2 = dx * dx + dy * dy;
-            float dz = 0.0f;
-            if (DIM == 3) {
-                dz = (q.z - pi.z) + sz;
-                r2 = r2 + dz * dz;
-            }
-            float c2, dd;
-            if (NS == 1) {
-                c2 = c2row[0];
-                dd = drow[0];
-            } else if (NS == 2) {
-                const int sj = species_of(q.w);
-                c2 = sj ? c2row[1] : c2row[0];
-                dd = sj ? drow[1] : drow[0];
-            } else {
-                const int sj = species_of(q.w);
-                c2 = tab.cut2[si * p.n_species + sj];
-                dd = tab.dij[si * p.n_species + sj];
-            }
-            if (r2 < c2 && j != self) {
-                if (DBG) {
-                    cnt += 1;
-                    hsum += splitmix64((unsigned long long)Is[j]);
-                }
-                if (r2 > 0.0f) {
-                    const float r = sqrtf(r2);
-                    const float f = kk * (dd - r) / r;
-                    F[0] -= f * dx;
-                    F[1] -= f * dy;
-                    if (DIM == 3) F[2] -= f * dz;
-                }
-            }
-        }
-    };
-
     const int zlo = DIM == 3 ? lo[2] : 0, zhi = DIM == 3 ? hi[2] : 0;
     for (int oz = zlo; oz <= zhi; ++oz) {
         int qz = oz;
@@ -235,12 +264,32 @@ __device__ __forceinline__ void pair_loop(const StepParams &p, const SpTab &tab,
                 qy -= nb;
                 sy = L;
             }
+            int xlo = lo[0], xhi = hi[0];
+            if (STENCIL == 3) {
+                float d2 = oy < lo[1] + 1 ? glo2[1] : (oy > lo[1] + 1 ? ghi2[1] : 0.0f);
+                if (DIM == 3) d2 += oz < lo[2] + 1 ? glo2[2] : (oz > lo[2] + 1 ? ghi2[2] : 0.0f);
+                if (d2 >= cmax2) continue;
+                if (d2 + glo2[0] >= cmax2) xlo += 1;
+                if (d2 + ghi2[0] >= cmax2) xhi -= 1;
+            }
             const uint32_t row = bin_base + (uint32_t)((qz * nb + qy) * nb);
-            const int m0 = max(lo[0], 0), m1 = min(hi[0], nb - 1);
-            scan(start[row + m0], start[row + m1 + 1], 0.0f, sy, sz);
+            const int m0 = max(xlo, 0), m1 = min(xhi, nb - 1);
+            const uint32_t a0 = start[row + m0], e0 = start[row + m1 + 1];
+            if (sy == 0.0f && sz == 0.0f)
+                pair_range<DIM, NS, DBG, false>(p, tab, Ps, Is, a0, e0, pi, si, 0.f, 0.f, 0.f,
+                                                c2row, kdrow, self, F, cnt, hsum);
+            else
+                pair_range<DIM, NS, DBG, true>(p, tab, Ps, Is, a0, e0, pi, si, 0.f, sy, sz,
+                                               c2row, kdrow, self, F, cnt, hsum);
             if (p.periodic) {
-                if (lo[0] < 0) scan(start[row + lo[0] + nb], start[row + nb], -L, sy, sz);
-                if (hi[0] > nb - 1) scan(start[row], start[row + hi[0] - nb + 1], L, sy, sz);
+                if (xlo < 0)
+                    pair_range<DIM, NS, DBG, true>(p, tab, Ps, Is, start[row + xlo + nb],
+                                                   start[row + nb], pi, si, -L, sy, sz, c2row,
+                                                   kdrow, self, F, cnt, hsum);
+                if (xhi > nb - 1)
+                    pair_range<DIM, NS, DBG, true>(p, tab, Ps, Is, start[row],
+                                                   start[row + xhi - nb + 1], pi, si, L, sy,
+                                                   sz, c2row, kdrow, self, F, cnt, hsum);
             }
         }
     }
@@ -329,27 +378,6 @@ __device__ __forceinline__ void grad_interp(const StepParams &p, const float *__
     }
 }
 
-// Piecewise-linear deposit of q (fixed point) at x into S.
-template <int DIM>
-__device__ __forceinline__ void deposit(const StepParams &p, unsigned long long *__restrict__ S,
-                                        float q, const Cell *cc) {
-    const int n = p.grid_n;
-#pragma unroll
-    for (int m = 0; m < (1 << DIM); ++m) {
-        float w = q;
-        int idx = 0, stride = 1;
-#pragma unroll
-        for (int a = 0; a < DIM; ++a) {
-            const int up = (m >> a) & 1;
-            w *= up ? cc[a].t : 1.0f - cc[a].t;
-            idx += (up ? cc[a].i1 : cc[a].i0) * stride;
-            stride *= n;
-        }
-        const unsigned long long v = (unsigned long long)__float2ull_rn(w);
-        if (v) atomicAdd(S + idx, v);
-    }
-}
-
 __device__ __forceinline__ float boundary(const StepParams &p, float x, uint32_t &flag) {
     const float L = p.L;
     if (p.periodic) {
@@ -433,14 +461,28 @@ __device__ __forceinline__ uint32_t block_exscan256(uint32_t v, uint32_t *lds, u
     return base + x - v;
 }
 
+// 8 consecutive counts starting at base (a multiple of 8): two 16-byte
+// loads when the whole group is in range.
+__device__ __forceinline__ void load8(const uint32_t *__restrict__ a, int64_t base, int64_t n,
+                                      uint32_t v[8]) {
+    if (base + 8 <= n) {
+        const uint4 *p4 = reinterpret_cast<const uint4 *>(a + base);
+        const uint4 x = p4[0], y = p4[1];
+        v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
+        v[4] = y.x; v[5] = y.y; v[6] = y.z; v[7] = y.w;
+    } else {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = base + k < n ? a[base + k] : 0u;
+    }
+}
+
 __global__ void __launch_bounds__(256) k_tile_sums(const uint32_t *__restrict__ count,
                                                    int64_t n, uint32_t *__restrict__ tile_sum) {
     __shared__ uint32_t lds[4];
     const int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x * 8;
-    uint32_t s = 0;
-#pragma unroll
-    for (int k = 0; k < 8; ++k)
-        if (base + k < n) s += count[base + k];
+    uint32_t v[8];
+    load8(count, base, n, v);
+    const uint32_t s = ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]));
     uint32_t tot;
     block_exscan256(s, lds, tot);
     if (threadIdx.x == 0) tile_sum[blockIdx.x] = tot;
@@ -479,21 +521,30 @@ __global__ void __launch_bounds__(256) k_scan_apply(uint32_t *__restrict__ count
     __shared__ uint32_t lds[4];
     const int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x * 8;
     uint32_t v[8];
-    uint32_t s = 0;
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        v[k] = base + k < n ? count[base + k] : 0u;
-        s += v[k];
-    }
+    load8(count, base, n, v);
+    const uint32_t s = ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]));
     uint32_t tot;
     uint32_t run = block_exscan256(s, lds, tot) + tile_sum[blockIdx.x];
+    uint32_t o[8];
 #pragma unroll
-    for (int k = 0; k < 8; ++k)
-        if (base + k < n) {
-            start[base + k] = run;
-            count[base + k] = 0u;
-            run += v[k];
-        }
+    for (int k = 0; k < 8; ++k) {
+        o[k] = run;
+        run += v[k];
+    }
+    if (base + 8 <= n) {
+        uint4 *st4 = reinterpret_cast<uint4 *>(start + base);
+        st4[0] = make_uint4(o[0], o[1], o[2], o[3]);
+        st4[1] = make_uint4(o[4], o[5], o[6], o[7]);
+        uint4 *c4 = reinterpret_cast<uint4 *>(count + base);
+        c4[0] = make_uint4(0u, 0u, 0u, 0u);
+        c4[1] = make_uint4(0u, 0u, 0u, 0u);
+    } else {
+        for (int k = 0; k < 8; ++k)
+            if (base + k < n) {
+                start[base + k] = o[k];
+                count[base + k] = 0u;
+            }
+    }
 }
 
 __global__ void k_scatter(int n, const float4 *__restrict__ P, const uint32_t *__restrict__ I,
@@ -529,13 +580,14 @@ __global__ void k_stable(StepParams p, const InstInfo *__restrict__ inst,
 
 // The fused particle update of one step, one thread per cell-sorted agent:
 // pair repulsion at X^n, chemotactic drift from c^n at X^n, Euler-Maruyama
-// with Philox normals, boundary closure, deposit at X^{n+1}.
+// with Philox normals, boundary closure; then the cell-list bin of X^{n+1}
+// and the agent's rank in it (the counting sort of the next step).
 template <int DIM, int NS, int STENCIL>
 __global__ void __launch_bounds__(1024)
 k_update(StepParams p, const InstInfo *__restrict__ inst, const float4 *__restrict__ Ps,
          const uint32_t *__restrict__ Is, const uint32_t *__restrict__ start,
          const float *__restrict__ c, float4 *__restrict__ Pout, uint32_t *__restrict__ Iout,
-         unsigned long long *__restrict__ Ssrc, unsigned long long *__restrict__ Supt,
+         uint32_t *__restrict__ bin, uint32_t *__restrict__ rank, uint32_t *__restrict__ count,
          const uint32_t *__restrict__ stepc, uint32_t *__restrict__ flags) {
     __shared__ SpTab tab;
     if (NS == 0) {
@@ -548,8 +600,7 @@ k_update(StepParams p, const InstInfo *__restrict__ inst, const float4 *__restri
     const float4 pi = Ps[i];
     const uint32_t id = Is[i];
     const int si = species_of(pi.w);
-    const uint32_t k = inst_of(pi.w);
-    const InstInfo ii = inst[k];
+    const InstInfo ii = inst[inst_of(pi.w)];
 
     float F[3] = {0.f, 0.f, 0.f};
     uint32_t cnt = 0;
@@ -580,50 +631,33 @@ k_update(StepParams p, const InstInfo *__restrict__ inst, const float4 *__restri
     if (!(isfinite(xn.x) && isfinite(xn.y) && isfinite(xn.z))) flag |= FLAG_NONFINITE;
     Pout[i] = xn;
     Iout[i] = id;
-
-    Cell cc[3];
-    cc[0] = cell_of(p, xn.x);
-    cc[1] = cell_of(p, xn.y);
-    if (DIM == 3) cc[2] = cell_of(p, xn.z);
-    const float qs = sel<NS>(p.src_fx, tab.src, si);
-    if (qs != 0.0f) deposit<DIM>(p, Ssrc + ii.node_base, qs, cc);
-    if (p.has_uptake) {
-        const float qu = sel<NS>(p.upt_fx, tab.upt, si);
-        if (qu != 0.0f) deposit<DIM>(p, Supt + ii.node_base, qu, cc);
-    }
+    const uint32_t b = ii.bin_base + agent_bin<DIM>(p, xn);
+    bin[i] = b;
+    rank[i] = atomicAdd(count + b, 1u);
     if (flag) atomicOr(flags, flag);
 }
 
-// Forward-Euler substep of the chemical with the centred Laplacian (periodic
-// wrap or mirror ghost nodes), fixed-point deposits converted to number
-// densities with the node control volumes.  The last substep clears the
-// deposits and advances the step counter.
+// Forward-Euler update of node l with the centred Laplacian (periodic wrap
+// or mirror ghost nodes); sigma and upsilon are the number densities of the
+// fixed-point deposits (divided by the node control volume).
 template <int DIM>
-__global__ void k_pde(PdeParams q, const float *__restrict__ cin, float *__restrict__ cout,
-                      unsigned long long *__restrict__ Ssrc, unsigned long long *__restrict__ Supt,
-                      int last, uint32_t *__restrict__ stepc, uint32_t *__restrict__ flags) {
-    const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (last && l == 0) *stepc += 1u;
-    if (l >= q.n_nodes_total) return;
-    const int n = q.grid_n;
-    const int64_t G = q.nodes_per_inst;
-    const int64_t base = (l / G) * G;
-    const int loc = (int)(l - base);
-    const int ix = loc % n, iy = (loc / n) % n, iz = DIM == 3 ? loc / (n * n) : 0;
-    auto nb = [&](int i, int off) {
-        int r = i + off;
+__device__ __forceinline__ float pde_node(const PdeParams &q, const float *__restrict__ cb,
+                                          const int ic[3], unsigned long long sS,
+                                          unsigned long long sU, uint32_t &flag) {
+    const int n = q.grid_n, nn = n * n;
+    auto nbr = [&](int i, int off) {
+        const int r = i + off;
         if (q.periodic) return r < 0 ? r + n : (r >= n ? r - n : r);
         return r < 0 ? 1 : (r >= n ? n - 2 : r);
     };
-    const float *cb = cin + base;
-    const float c0 = cb[loc];
-    const int nn = n * n;
+    const int ix = ic[0], iy = ic[1], iz = ic[2];
+    const float c0 = cb[iz * nn + iy * n + ix];
     const int rowo = iz * nn + iy * n;
-    float lap = (cb[rowo + nb(ix, 1)] + cb[rowo + nb(ix, -1)]) +
-                (cb[iz * nn + nb(iy, 1) * n + ix] + cb[iz * nn + nb(iy, -1) * n + ix]);
+    float lap = (cb[rowo + nbr(ix, 1)] + cb[rowo + nbr(ix, -1)]) +
+                (cb[iz * nn + nbr(iy, 1) * n + ix] + cb[iz * nn + nbr(iy, -1) * n + ix]);
     float diag = 4.0f;
     if (DIM == 3) {
-        lap += cb[nb(iz, 1) * nn + iy * n + ix] + cb[nb(iz, -1) * nn + iy * n + ix];
+        lap += cb[nbr(iz, 1) * nn + iy * n + ix] + cb[nbr(iz, -1) * nn + iy * n + ix];
         diag = 6.0f;
     }
     lap = (lap - diag * c0) * q.inv_h2;
@@ -634,19 +668,126 @@ __global__ void k_pde(PdeParams q, const float *__restrict__ cin, float *__restr
         if (DIM == 3 && (iz == 0 || iz == n - 1)) inv_v *= 2.0f;
     }
     const float dens = q.fx_to_density * inv_v;
-    const float sigma = (float)Ssrc[l] * dens;
-    float ups = 0.0f;
-    if (q.has_uptake) ups = (float)Supt[l] * dens;
+    const float sigma = (float)sS * dens;
+    const float ups = q.has_uptake ? (float)sU * dens : 0.0f;
     const float cn = c0 + q.dts * (q.D_c * lap + sigma - ups * c0 - q.gamma * c0);
-    cout[l] = cn;
-    uint32_t flag = 0;
     if (!isfinite(cn)) flag |= FLAG_NONFINITE;
     if (q.dts * (q.gamma + ups) >= 1.0f) flag |= FLAG_WARN_POSITIVITY;
-    if (flag) atomicOr(flags, flag);
-    if (last) {
-        Ssrc[l] = 0ull;
-        if (q.has_uptake) Supt[l] = 0ull;
+    return cn;
+}
+
+// Piecewise-linear deposit (fixed point, 2^-32 units) of every agent at its
+// new position, one thread per agent.  The 2^dim corner contributions of a
+// work-group's agents (contiguous in cell-sorted order, hence spatially
+// close) are first summed in an LDS hash table keyed by node, then flushed
+// with one device atomic per distinct node.  Integer sums make the result
+// independent of the summation order.
+constexpr int kDepSlots = 2048;
+constexpr uint32_t kEmpty = 0xFFFFFFFFu;
+
+template <int DIM, int NS, bool UPT>
+__global__ void __launch_bounds__(256)
+k_deposit(StepParams p, const InstInfo *__restrict__ inst, const float4 *__restrict__ P,
+          unsigned long long *__restrict__ Ssrc, unsigned long long *__restrict__ Supt) {
+    __shared__ uint32_t keys[kDepSlots];
+    __shared__ unsigned long long vs[kDepSlots];
+    __shared__ unsigned long long vu[UPT ? kDepSlots : 1];
+    __shared__ SpTab tab;
+    for (int q = threadIdx.x; q < kDepSlots; q += blockDim.x) {
+        keys[q] = kEmpty;
+        vs[q] = 0ull;
+        if (UPT) vu[q] = 0ull;
     }
+    if (NS == 0) load_tab(p, tab);
+    __syncthreads();
+    const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
+    const int i = blk * blockDim.x + threadIdx.x;
+    if (i < p.n_total) {
+        const float4 x = P[i];
+        const int s = species_of(x.w);
+        const uint32_t base = inst[inst_of(x.w)].node_base;
+        const float qs = sel<NS>(p.src_fx, tab.src, s);
+        const float qu = UPT ? sel<NS>(p.upt_fx, tab.upt, s) : 0.0f;
+        if (qs != 0.0f || qu != 0.0f) {
+            Cell cc[3];
+            cc[0] = cell_of(p, x.x);
+            cc[1] = cell_of(p, x.y);
+            if (DIM == 3) cc[2] = cell_of(p, x.z);
+            const int n = p.grid_n;
+#pragma unroll
+            for (int m = 0; m < (1 << DIM); ++m) {
+                float ws = qs, wu = qu;
+                uint32_t idx = 0, stride = 1;
+#pragma unroll
+                for (int a = 0; a < DIM; ++a) {
+                    const int up = (m >> a) & 1;
+                    const float f = up ? cc[a].t : 1.0f - cc[a].t;
+                    ws *= f;
+                    if (UPT) wu *= f;
+                    idx += (uint32_t)(up ? cc[a].i1 : cc[a].i0) * stride;
+                    stride *= (uint32_t)n;
+                }
+                const unsigned long long vs_ = (unsigned long long)__float2ull_rn(ws);
+                const unsigned long long vu_ = UPT ? (unsigned long long)__float2ull_rn(wu) : 0ull;
+                if (vs_ == 0ull && vu_ == 0ull) continue;
+                const uint32_t key = base + idx;
+                uint32_t h = (key * 2654435761u) >> 21;  // 11 bits: kDepSlots = 2048
+                bool done = false;
+                for (int probe = 0; probe < 16; ++probe) {
+                    const uint32_t old = atomicCAS(&keys[h], kEmpty, key);
+                    if (old == kEmpty || old == key) {
+                        if (vs_) atomicAdd(&vs[h], vs_);
+                        if (UPT && vu_) atomicAdd(&vu[h], vu_);
+                        done = true;
+                        break;
+                    }
+                    h = (h + 1) & (kDepSlots - 1);
+                }
+                if (!done) {
+                    if (vs_) atomicAdd(Ssrc + key, vs_);
+                    if (UPT && vu_) atomicAdd(Supt + key, vu_);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < kDepSlots; q += blockDim.x) {
+        const uint32_t key = keys[q];
+        if (key == kEmpty) continue;
+        if (vs[q]) atomicAdd(Ssrc + key, vs[q]);
+        if (UPT && vu[q]) atomicAdd(Supt + key, vu[q]);
+    }
+}
+
+// PDE substep, one thread per node; the last substep of a step clears the
+// deposits for the next step.
+template <int DIM>
+__global__ void __launch_bounds__(256)
+k_pde(PdeParams q, const float *__restrict__ cin, float *__restrict__ cout,
+      unsigned long long *__restrict__ Ssrc, unsigned long long *__restrict__ Supt, int last,
+      uint32_t *__restrict__ flags) {
+    const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= q.n_nodes_total) return;
+    const int n = q.grid_n;
+    const int64_t G = q.nodes_per_inst;
+    const int64_t k = l / G;
+    const int loc = (int)(l - k * G);
+    const int ic[3] = {loc % n, (loc / n) % n, DIM == 3 ? loc / (n * n) : 0};
+    uint32_t flag = 0;
+    const unsigned long long sS = Ssrc[l], sU = q.has_uptake ? Supt[l] : 0ull;
+    cout[l] = pde_node<DIM>(q, cin + k * G, ic, sS, sU, flag);
+    if (last) {
+        if (sS) Ssrc[l] = 0ull;
+        if (sU) Supt[l] = 0ull;
+    }
+    if (flag) atomicOr(flags, flag);
+}
+
+__global__ void k_step_inc(uint32_t *stepc) { *stepc += 1u; }
+
+__global__ void k_zero_u32(uint32_t *__restrict__ d, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) d[i] = 0u;
 }
 
 __global__ void k_positions(StepParams p, const InstInfo *__restrict__ inst,
@@ -757,7 +898,7 @@ static void upd(const StepParams &p, const Buffers &b, int src, int dst, int cbu
                 hipStream_t s) {
     hipLaunchKernelGGL((k_update<DIM, NS, ST>), dim3(grid_for(p.n_total, block)), dim3(block), 0,
                        s, p, b.inst, b.P[src], b.I[src], b.start, b.c[cbuf], b.P[dst], b.I[dst],
-                       b.S_src, b.S_upt, b.step, b.flags);
+                       b.bin, b.rank, b.count, b.step, b.flags);
 }
 
 template <int DIM, int NS, int ST>
@@ -803,15 +944,49 @@ void launch_debug_pairs(const StepParams &p, const Buffers &b, int src, uint32_t
     PC_DISPATCH(dbg, p, b, src, count, hash, F, block, s);
 }
 
+template <int DIM, int NS, bool UPT>
+static void dep(const StepParams &p, const Buffers &b, int src, hipStream_t s) {
+    hipLaunchKernelGGL((k_deposit<DIM, NS, UPT>), dim3(grid_for(p.n_total, 256)), dim3(256), 0, s,
+                       p, b.inst, b.P[src], b.S_src, b.S_upt);
+}
+
+void launch_deposit(const StepParams &p, const Buffers &b, int src, hipStream_t s) {
+    const int ns = p.n_species == 1 ? 1 : (p.n_species == 2 ? 2 : 0);
+#define PC_DEP(D, N)                                  \
+    do {                                              \
+        if (p.has_uptake) dep<D, N, true>(p, b, src, s);  \
+        else dep<D, N, false>(p, b, src, s);          \
+    } while (0)
+    if (p.dim == 2) {
+        if (ns == 1) PC_DEP(2, 1);
+        else if (ns == 2) PC_DEP(2, 2);
+        else PC_DEP(2, 0);
+    } else {
+        if (ns == 1) PC_DEP(3, 1);
+        else if (ns == 2) PC_DEP(3, 2);
+        else PC_DEP(3, 0);
+    }
+#undef PC_DEP
+}
+
 void launch_pde(const PdeParams &q, const Buffers &b, int cin, int cout, int last,
                 hipStream_t s) {
     const dim3 g(grid_for(q.n_nodes_total, 256)), t(256);
     if (q.dim == 2)
         hipLaunchKernelGGL(k_pde<2>, g, t, 0, s, q, b.c[cin], b.c[cout], b.S_src, b.S_upt, last,
-                           b.step, b.flags);
+                           b.flags);
     else
         hipLaunchKernelGGL(k_pde<3>, g, t, 0, s, q, b.c[cin], b.c[cout], b.S_src, b.S_upt, last,
-                           b.step, b.flags);
+                           b.flags);
+}
+
+void launch_step_inc(const Buffers &b, hipStream_t s) {
+    hipLaunchKernelGGL(k_step_inc, dim3(1), dim3(1), 0, s, b.step);
+}
+
+void launch_zero_u32(uint32_t *d, int64_t n, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_zero_u32, dim3(grid_for(n, 256)), dim3(256), 0, s, d, n);
 }
 
 void launch_positions(const StepParams &p, const Buffers &b, int src, float *out,
