@@ -78,6 +78,106 @@ def cpu_baseline(w, inp, budget_s: float = 12.0, max_steps: int = 40):
                       f"{el:.1f} s"}
 
 
+def _timed(fn) -> float:
+    import torch
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1)
+
+
+def ensemble_leg(steps: int = 500, plain_steps: int = 50) -> dict:
+    """256 independent 2D instances of uneven size stepped together (one launch
+    per stage, HIP-graph replay, autotuned bin side and work-group size) vs the
+    same instances stepped one after another as single-instance handles."""
+    import dataclasses
+    import torch
+    import workloads as W
+    from paper_1805_11007_amd import ModelSpec, Sim
+    from paper_1805_11007_amd.autotune import tune
+    w = W.config(4)
+    inp = W.make_inputs(w)
+    x0, s0, c0 = (torch.from_numpy(inp[k]).cuda() for k in ("x0", "species0", "c0"))
+    spec, rep = tune(ModelSpec.from_workload(w), x0, s0, c0)
+    sim = Sim(spec, x0, s0, c0)
+    sim.use_graph(True)
+    sim.step(4)
+    sim.set_state(x0, c0, 0)
+    ms = _timed(lambda: sim.step(steps))
+    sim.sync()
+    batched = w.n_total * steps / (ms / 1e3)
+    sim.close()
+    # plain: every instance alone (its own handle, same seed and noise stream)
+    G = w.grid_n ** w.dim
+    tot_ms, tot_ps, off = 0.0, 0, 0
+    for k, ins in enumerate(w.instances):
+        n = ins.n_agents
+        one = dataclasses.replace(spec, instances=[dataclasses.replace(spec.instances[k],
+                                                                       stream=k)])
+        s1 = Sim(one, x0[off:off + n], s0[off:off + n], c0[k * G:(k + 1) * G])
+        s1.use_graph(True)
+        s1.step(2)
+        s1.set_state(x0[off:off + n], c0[k * G:(k + 1) * G], 0)
+        tot_ms += _timed(lambda: s1.step(plain_steps))
+        tot_ps += n * plain_steps
+        s1.close()
+        off += n
+    plain = tot_ps / (tot_ms / 1e3)
+    return {"workload": w.name, "instances": w.n_inst, "agents_total": w.n_total,
+            "batched_particle_steps_per_s": batched, "batched_steps": steps,
+            "plain_particle_steps_per_s": plain, "plain_steps_per_instance": plain_steps,
+            "speedup_vs_plain": batched / plain,
+            "tuned": {"bin_size": spec.bin_size, "block": spec.block}}
+
+
+def adjoint_leg(steps: int = 200, K: int = 20) -> dict:
+    """Forward with checkpoints every K steps plus the reverse sweep (which
+    recomputes each segment) on the 50k-agent differentiation workload, vs
+    the plain forward of the same steps; rates count each step once."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_1805_11007_amd import ModelSpec, Sim
+    from paper_1805_11007_amd.adjoint import density_loss_run
+    w = W.config5()
+    inp = W.make_inputs(w)
+    x0, s0, c0 = (torch.from_numpy(inp[k]).cuda() for k in ("x0", "species0", "c0"))
+    base = ModelSpec.from_workload(w)
+    # target: a run at theta* = (1.5, 800, 0.8) with another noise key
+    tw = W.config5(chi=1.5, k=800, D=0.8, seed=2005)
+    tsim = Sim(ModelSpec.from_workload(tw), x0, s0, c0)
+    tsim.step(steps)
+    target = tsim.density_hist(64, 2.0)
+    tsim.close()
+    plain = Sim(base, x0, s0, c0)
+    plain.use_graph(True)
+    plain.step(2)
+    plain.set_state(x0, c0, 0)
+    ms_plain = _timed(lambda: plain.step(steps))
+    plain.close()
+    theta = torch.tensor([1.0, 100.0, 1.0], dtype=torch.float64, requires_grad=True)
+    out = {}
+
+    def fwd_bwd():
+        loss = density_loss_run(theta, base, x0, s0, c0, target, steps, K, 64, 2.0)
+        loss.backward()
+        out["loss"] = float(loss.detach())
+
+    density_loss_run(theta.detach().requires_grad_(True), base, x0, s0, c0, target, 20, K,
+                     64, 2.0).backward()  # warm-up
+    ms_fb = _timed(fwd_bwd)
+    n = w.n_total
+    return {"workload": w.name, "agents": n, "steps": steps, "checkpoint_every": K,
+            "plain_particle_steps_per_s": n * steps / (ms_plain / 1e3),
+            "fwd_bwd_particle_steps_per_s": n * steps / (ms_fb / 1e3),
+            "fwd_bwd_over_plain_time": ms_fb / ms_plain, "loss": out["loss"],
+            "grad_theta": theta.grad.tolist()}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -85,6 +185,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--config", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the ensemble and forward+backward legs")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--deterministic", action="store_true")
     ap.add_argument("--bin-size", type=float, default=0.0)
@@ -167,11 +269,18 @@ def main() -> int:
                      "launch_ms": prof[dom]},
         "stage_ms": prof,
     }
+    sim.close()
+    if not args.no_extras:
+        print("[bench] ensemble leg", file=sys.stderr, flush=True)
+        res["ensemble"] = ensemble_leg()
+        print(f"[bench] ensemble: {json.dumps(res['ensemble'])}", file=sys.stderr, flush=True)
+        print("[bench] forward+backward leg", file=sys.stderr, flush=True)
+        res["fwd_bwd"] = adjoint_leg()
+        print(f"[bench] fwd_bwd: {json.dumps(res['fwd_bwd'])}", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
         res["cpu_baseline"] = cpu_baseline(w, inp)
     print(json.dumps(res), flush=True)
-    sim.close()
     return 0
 
 

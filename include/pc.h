@@ -209,22 +209,51 @@ int pc_debug_neighbours(pc_sim *sim, uint32_t *count_dev, uint64_t *hash_dev);
 /* Pair forces of the current state (float32, sum(N) x dim, id order). */
 int pc_debug_forces(pc_sim *sim, float *F_dev);
 
-/* --- differentiation (reverse mode through the step) ---
- * Adjoint of n_steps steps starting from the current state with its noise
- * fixed by the Philox keys.  lamX_in_dev (sum(N) x dim) and lamC_in_dev
- * (n_inst x G) are the loss gradients with respect to the positions and
- * field after the n_steps steps; lamX_out_dev / lamC_out_dev receive the
- * gradients with respect to the current positions and field; dtheta_out
- * (host, 3 doubles per instance) receives dL/d(chi_scale), dL/dk and dL/dD
- * (D of every species scaled together).  The current state is left as it
- * was.  Positions are not changed by the call.  Requires n_steps >= 1 and
- * a workspace created with pc_workspace_bytes_adjoint. */
+/* --- differentiation (reverse mode through the step; not in the paper) ---
+ *
+ * pc_adjoint_segment: reverse sweep over n_steps steps starting from the
+ * current state, with the noise of every step fixed by the Philox keys.
+ *   lamX_in_dev  (float32, sum(N) x dim, id order) and lamC_in_dev (float32,
+ *                n_inst x G): dL/dX and dL/dc after the n_steps steps;
+ *   lamX_out_dev, lamC_out_dev: receive dL/dX and dL/dc of the current state;
+ *   dtheta_out   (host, 3 doubles per instance): dL/ds for multiplicative
+ *                scales s of every species' chi, of k and of every species'
+ *                D, taken at s = 1 (so dL/dk = dtheta[1] / k, etc.).
+ * The segment is recomputed forward inside the call (checkpointing); the
+ * state is restored to what it was, and the call synchronises the stream.
+ * Needs a workspace of pc_workspace_bytes_adjoint(..., seg_steps) bytes with
+ * 1 <= n_steps <= seg_steps.  Errors: PC_ENOTSUP without segment storage,
+ * PC_EINVAL for bad arguments, PC_EHIP. */
 size_t pc_workspace_bytes_adjoint(const pc_config *cfg, const pc_species_t *species,
                                   int n_species, const pc_instance *inst, int n_inst,
                                   int seg_steps);
 int pc_adjoint_segment(pc_sim *sim, const float *lamX_in_dev, const float *lamC_in_dev,
                        int n_steps, float *lamX_out_dev, float *lamC_out_dev,
                        double *dtheta_out);
+
+/* Density-mismatch loss of the current positions, per instance, on a
+ * periodic histogram grid of hist_n nodes per axis (spacing L / hist_n):
+ * rho = piecewise-linear (cloud-in-cell) histogram divided by the instance's
+ * agent count, smoothed by a separable periodic Gaussian of width
+ * sigma_bins bins truncated at round(3 sigma_bins) bins (taps normalised
+ * to 1), loss_k = sum_l (rho_s,l - target_l)^2.  The paper analyses its
+ * runs with histograms of the cell positions; this smooth version is the
+ * differentiable one.
+ *   target_dev: float32, n_inst x hist_n^dim (x fastest);
+ *   work_dev:   caller scratch of pc_density_loss_work_bytes bytes, 256-byte
+ *               aligned;
+ *   loss_out:   host, n_inst doubles;
+ *   dLdX_dev:   NULL or float32 sum(N) x dim, receives dL/dX (id order).
+ * Periodic boxes only (PC_ENOTSUP otherwise).  Synchronises the stream. */
+size_t pc_density_loss_work_bytes(pc_sim *sim, int hist_n);
+int pc_density_loss(pc_sim *sim, const float *target_dev, int hist_n, double sigma_bins,
+                    void *work_dev, size_t work_bytes, double *loss_out, float *dLdX_dev);
+
+/* The smoothed histogram rho_s of the loss above (float32, n_inst x
+ * hist_n^dim) into rho_out_dev, e.g. to build a target from a reference run.
+ * Same arguments and errors as pc_density_loss. */
+int pc_density_hist(pc_sim *sim, int hist_n, double sigma_bins, void *work_dev,
+                    size_t work_bytes, float *rho_out_dev);
 
 #ifdef __cplusplus
 }

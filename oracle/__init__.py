@@ -85,6 +85,9 @@ def lib():
             "orc_pde": ([P, vp, vp, vp], None),
             "orc_step": ([P, i64, vp, vp, vp, vp, vp], None),
             "orc_run": ([P, i64, vp, vp, vp, vp, vp, C.c_int], None),
+            "orc_density_loss": ([C.c_int, C.c_double, i64, vp, C.c_int, C.c_double, vp, vp],
+                                 C.c_double),
+            "orc_density_hist": ([C.c_int, C.c_double, i64, vp, C.c_int, C.c_double, vp], None),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -258,6 +261,58 @@ def run(p: Params, X: np.ndarray, sp: np.ndarray, c: np.ndarray, step: int, n_st
 
 def step(p: Params, X, sp, c, step_no: int, ids=None):
     return run(p, X, sp, c, step_no, 1, ids)
+
+
+def density_loss(dim: int, L: float, X: np.ndarray, target: np.ndarray, hist_n: int = 64,
+                 sigma_bins: float = 2.0, grad: bool = False):
+    """Smoothed-histogram mismatch of one instance's positions (FP64)."""
+    X = _c(X, np.float64)
+    target = _c(target, np.float64)
+    g = np.empty_like(X) if grad else None
+    loss = lib().orc_density_loss(dim, L, len(X), _ptr(X), hist_n, sigma_bins, _ptr(target),
+                                  _ptr(g) if grad else None)
+    return (loss, g) if grad else loss
+
+
+def density_hist(dim: int, L: float, X: np.ndarray, hist_n: int = 64, sigma_bins: float = 2.0):
+    X = _c(X, np.float64)
+    out = np.empty(hist_n ** dim, np.float64)
+    lib().orc_density_hist(dim, L, len(X), _ptr(X), hist_n, sigma_bins, _ptr(out))
+    return out
+
+
+def target_hist(w, inputs: dict, n_steps: int, hist_n: int = 64, sigma_bins: float = 2.0):
+    """Smoothed histograms (all instances) after an oracle run of a workload."""
+    X, _ = run_workload(w, inputs, n_steps)
+    out, off = [], 0
+    for ins in w.instances:
+        out.append(density_hist(w.dim, w.L, X[off:off + ins.n_agents], hist_n, sigma_bins))
+        off += ins.n_agents
+    return np.concatenate(out)
+
+
+def workload_at(w, theta):
+    """The workload with chi of the chemotactic species, k and every
+    species' D replaced by theta = (chi, k, D)."""
+    import dataclasses
+    chi, k, D = (float(v) for v in theta)
+    sp = tuple(dataclasses.replace(s, D=D, chi=chi if s.chi != 0.0 else 0.0) for s in w.species)
+    return dataclasses.replace(w, species=sp, k=k)
+
+
+def loss_at(w, inputs: dict, theta, target: np.ndarray, n_steps: int, hist_n: int = 64,
+            sigma_bins: float = 2.0) -> float:
+    """FP64 loss after n_steps from `inputs` at theta (summed over instances)."""
+    wt = workload_at(w, theta)
+    X, _ = run_workload(wt, inputs, n_steps)
+    H = hist_n ** w.dim
+    tot, off = 0.0, 0
+    for k, ins in enumerate(w.instances):
+        n = ins.n_agents
+        tot += density_loss(w.dim, w.L, X[off:off + n], target[k * H:(k + 1) * H], hist_n,
+                            sigma_bins)
+        off += n
+    return tot
 
 
 def run_workload(w, inputs: dict, n_steps: int, mode: int = 1, step0: int = 0):

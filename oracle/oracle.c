@@ -627,3 +627,167 @@ void orc_run(const orc_params *p, int64_t n, double *X, const uint8_t *sp, const
              double *c, uint32_t *step, int n_steps) {
     for (int s = 0; s < n_steps; ++s) orc_step(p, n, X, sp, ids, c, step);
 }
+
+/* ------------------------------------------------------------------------
+ * Density-mismatch loss (used to check the reverse mode).  The paper
+ * analyses its runs through histograms of the cell positions (Sect. 4); the
+ * loss below uses a smooth version of such a histogram:
+ *   rho   = cloud-in-cell histogram of the positions on a periodic grid of
+ *           m nodes per axis (spacing L/m, node i at i L/m), divided by n;
+ *   rho_s = separable periodic Gaussian smoothing, taps exp(-k^2 / 2 s^2)
+ *           for |k| <= round(3 s), normalised to sum 1;
+ *   loss  = sum (rho_s - target)^2.
+ * grad (n x dim, may be NULL) receives d loss / d X.
+ * ------------------------------------------------------------------------ */
+static void orc_smooth_axis(int dim, int m, const double *taps, int R, int axis, const double *in,
+                            double *out) {
+    int64_t H = 1, stride = 1;
+    for (int a = 0; a < dim; ++a) H *= m;
+    for (int a = 0; a < axis; ++a) stride *= m;
+    for (int64_t l = 0; l < H; ++l) {
+        int i = (int)((l / stride) % m);
+        int64_t base = l - (int64_t)i * stride;
+        double s = 0.0;
+        for (int q = -R; q <= R; ++q) {
+            int ii = ((i + q) % m + m) % m;
+            s += taps[q + R] * in[base + (int64_t)ii * stride];
+        }
+        out[l] = s;
+    }
+}
+
+double orc_density_loss(int dim, double L, int64_t n, const double *X, int m, double sigma,
+                        const double *target, double *grad) {
+    int64_t H = 1;
+    for (int a = 0; a < dim; ++a) H *= m;
+    const double hh = L / m;
+    int R = (int)floor(3.0 * sigma + 0.5);
+    double *taps = (double *)malloc(sizeof(double) * (size_t)(2 * R + 1));
+    double tot = 0.0;
+    for (int k = -R; k <= R; ++k) tot += (taps[k + R] = exp(-0.5 * k * k / (sigma * sigma)));
+    for (int k = 0; k <= 2 * R; ++k) taps[k] /= tot;
+    double *rho = (double *)calloc((size_t)H, sizeof(double));
+    double *tmp = (double *)malloc(sizeof(double) * (size_t)H);
+    for (int64_t i = 0; i < n; ++i) {
+        int i0[3] = {0, 0, 0}, i1[3] = {0, 0, 0};
+        double t[3] = {0, 0, 0};
+        for (int a = 0; a < dim; ++a) {
+            double s = X[i * dim + a] / hh;
+            int c = (int)floor(s);
+            if (c > m - 1) c = m - 1;
+            if (c < 0) c = 0;
+            i0[a] = c;
+            t[a] = s - c;
+            i1[a] = (c + 1) % m;
+        }
+        for (int mm = 0; mm < (1 << dim); ++mm) {
+            double w = 1.0;
+            int64_t idx = 0, stride = 1;
+            for (int a = 0; a < dim; ++a) {
+                int up = (mm >> a) & 1;
+                w *= up ? t[a] : 1.0 - t[a];
+                idx += (up ? i1[a] : i0[a]) * stride;
+                stride *= m;
+            }
+            rho[idx] += w / (double)n;
+        }
+    }
+    for (int a = 0; a < dim; ++a) {
+        orc_smooth_axis(dim, m, taps, R, a, rho, tmp);
+        memcpy(rho, tmp, sizeof(double) * (size_t)H);
+    }
+    double loss = 0.0;
+    for (int64_t l = 0; l < H; ++l) {
+        double d = rho[l] - target[l];
+        loss += d * d;
+        rho[l] = 2.0 * d;  /* reuse as dloss / drho_s */
+    }
+    if (grad) {
+        for (int a = 0; a < dim; ++a) {
+            orc_smooth_axis(dim, m, taps, R, a, rho, tmp);
+            memcpy(rho, tmp, sizeof(double) * (size_t)H);
+        }
+        for (int64_t i = 0; i < n; ++i) {
+            int i0[3] = {0, 0, 0}, i1[3] = {0, 0, 0};
+            double t[3] = {0, 0, 0};
+            for (int a = 0; a < dim; ++a) {
+                double s = X[i * dim + a] / hh;
+                int c = (int)floor(s);
+                if (c > m - 1) c = m - 1;
+                if (c < 0) c = 0;
+                i0[a] = c;
+                t[a] = s - c;
+                i1[a] = (c + 1) % m;
+            }
+            double g[3] = {0, 0, 0};
+            for (int mm = 0; mm < (1 << dim); ++mm) {
+                double w[3], dw[3];
+                int64_t idx = 0, stride = 1;
+                for (int a = 0; a < dim; ++a) {
+                    int up = (mm >> a) & 1;
+                    w[a] = up ? t[a] : 1.0 - t[a];
+                    dw[a] = (up ? 1.0 : -1.0) / hh;
+                    idx += (up ? i1[a] : i0[a]) * stride;
+                    stride *= m;
+                }
+                for (int b = 0; b < dim; ++b) {
+                    double d = dw[b];
+                    for (int a = 0; a < dim; ++a)
+                        if (a != b) d *= w[a];
+                    g[b] += rho[idx] * d;
+                }
+            }
+            for (int b = 0; b < dim; ++b) grad[i * dim + b] = g[b] / (double)n;
+        }
+    }
+    free(taps);
+    free(rho);
+    free(tmp);
+    return loss;
+}
+
+/* The smoothed histogram rho_s of the loss above, e.g. to build a target
+ * from a reference run (same steps as the loss). */
+void orc_density_hist(int dim, double L, int64_t n, const double *X, int m, double sigma,
+                      double *out) {
+    int64_t H = 1;
+    for (int a = 0; a < dim; ++a) H *= m;
+    const double hh = L / m;
+    int R = (int)floor(3.0 * sigma + 0.5);
+    double *taps = (double *)malloc(sizeof(double) * (size_t)(2 * R + 1));
+    double tot = 0.0;
+    for (int k = -R; k <= R; ++k) tot += (taps[k + R] = exp(-0.5 * k * k / (sigma * sigma)));
+    for (int k = 0; k <= 2 * R; ++k) taps[k] /= tot;
+    double *tmp = (double *)malloc(sizeof(double) * (size_t)H);
+    memset(out, 0, sizeof(double) * (size_t)H);
+    for (int64_t i = 0; i < n; ++i) {
+        int i0[3] = {0, 0, 0}, i1[3] = {0, 0, 0};
+        double t[3] = {0, 0, 0};
+        for (int a = 0; a < dim; ++a) {
+            double s = X[i * dim + a] / hh;
+            int c = (int)floor(s);
+            if (c > m - 1) c = m - 1;
+            if (c < 0) c = 0;
+            i0[a] = c;
+            t[a] = s - c;
+            i1[a] = (c + 1) % m;
+        }
+        for (int mm = 0; mm < (1 << dim); ++mm) {
+            double w = 1.0;
+            int64_t idx = 0, stride = 1;
+            for (int a = 0; a < dim; ++a) {
+                int up = (mm >> a) & 1;
+                w *= up ? t[a] : 1.0 - t[a];
+                idx += (up ? i1[a] : i0[a]) * stride;
+                stride *= m;
+            }
+            out[idx] += w / (double)n;
+        }
+    }
+    for (int a = 0; a < dim; ++a) {
+        orc_smooth_axis(dim, m, taps, R, a, out, tmp);
+        memcpy(out, tmp, sizeof(double) * (size_t)H);
+    }
+    free(taps);
+    free(tmp);
+}

@@ -19,6 +19,7 @@ EXPORTS = (
     "pc_positions", "pc_field", "pc_species", "pc_get_state", "pc_set_state", "pc_sync",
     "pc_warnings", "pc_info", "pc_destroy", "pc_strerror", "pc_last_error",
     "pc_debug_neighbours", "pc_debug_forces", "pc_adjoint_segment", "pc_profile_steps",
+    "pc_density_loss_work_bytes", "pc_density_loss", "pc_density_hist",
 )
 STAGES = ("bin", "scan", "scatter", "stable", "update", "deposit", "pde")
 
@@ -90,6 +91,10 @@ def load() -> C.CDLL:
         "pc_debug_forces": ([vp, vp], i32),
         "pc_adjoint_segment": ([vp, vp, vp, i32, vp, vp, C.POINTER(C.c_double)], i32),
         "pc_profile_steps": ([vp, i32, C.POINTER(C.c_double)], i32),
+        "pc_density_loss_work_bytes": ([vp, i32], C.c_size_t),
+        "pc_density_loss": ([vp, vp, i32, C.c_double, vp, C.c_size_t, C.POINTER(C.c_double),
+                             vp], i32),
+        "pc_density_hist": ([vp, i32, C.c_double, vp, C.c_size_t, vp], i32),
     }
     for name, (args, res) in sigs.items():
         f = getattr(L, name)

@@ -42,7 +42,7 @@ struct Derived {
 
 struct Layout {
     size_t P[3], I[3], bin, rank, count, start, tile_sum, c[2], S_src, S_upt, inst, species_id,
-        step, flags, seg_x, seg_c, adj[8], adj_red;
+        step, flags, seg_x, seg_c, lamX[2], lamY, lamC[2], aSrc, aUpt, lamG, csub, dth;
     size_t total;
 };
 
@@ -167,11 +167,19 @@ Layout layout(const Derived &d, int seg_steps) {
     L.step = take(cur, 4);
     L.flags = take(cur, 4);
     if (seg_steps > 0) {
-        L.seg_x = take(cur, 4 * (size_t)seg_steps * N * d.dim);
-        L.seg_c = take(cur, 4 * (size_t)seg_steps * (size_t)d.nodes_total);
-        for (int k = 0; k < 4; ++k) L.adj[k] = take(cur, 4 * N * 4);
-        for (int k = 4; k < 8; ++k) L.adj[k] = take(cur, 4 * (size_t)d.nodes_total * 4);
-        L.adj_red = take(cur, 8 * 64 * (size_t)d.ni);
+        const size_t G = (size_t)d.nodes_total, XD = N * d.dim;
+        L.seg_x = take(cur, 4 * ((size_t)seg_steps + 1) * XD);
+        L.seg_c = take(cur, 4 * (size_t)seg_steps * G);
+        L.lamX[0] = take(cur, 4 * XD);
+        L.lamX[1] = take(cur, 4 * XD);
+        L.lamY = take(cur, 4 * XD);
+        L.lamC[0] = take(cur, 4 * G);
+        L.lamC[1] = take(cur, 4 * G);
+        L.aSrc = take(cur, 4 * G);
+        L.aUpt = take(cur, 4 * G);
+        L.lamG = take(cur, 4 * G * d.dim);
+        L.csub = take(cur, 4 * G * d.n_sub);
+        L.dth = take(cur, 8 * 3 * (size_t)d.ni);
     }
     L.total = take(cur, 0) + 256;
     return L;
@@ -257,6 +265,7 @@ static void fill_params(pc_sim *s) {
     double hd = 1.0;
     for (int a = 0; a < d.dim; ++a) hd *= d.h;
     q.fx_to_density = (float)(1.0 / (4294967296.0 * hd));
+    q.inv_hd = (float)(1.0 / hd);
     q.has_uptake = d.has_uptake;
 }
 
@@ -284,8 +293,16 @@ static void carve(pc_sim *s, char *ws) {
     if (s->seg_steps > 0) {
         b.seg_x = (float *)(ws + L.seg_x);
         b.seg_c = (float *)(ws + L.seg_c);
-        for (int k = 0; k < 8; ++k) b.adj[k] = (float *)(ws + L.adj[k]);
-        b.adj_red = (double *)(ws + L.adj_red);
+        b.lamX[0] = (float *)(ws + L.lamX[0]);
+        b.lamX[1] = (float *)(ws + L.lamX[1]);
+        b.lamY = (float *)(ws + L.lamY);
+        b.lamC[0] = (float *)(ws + L.lamC[0]);
+        b.lamC[1] = (float *)(ws + L.lamC[1]);
+        b.aSrc = (float *)(ws + L.aSrc);
+        b.aUpt = (float *)(ws + L.aUpt);
+        b.lamG = (float *)(ws + L.lamG);
+        b.csub = (float *)(ws + L.csub);
+        b.dth = (double *)(ws + L.dth);
     }
 }
 
@@ -710,13 +727,147 @@ int pc_debug_forces(pc_sim *s, float *F_dev) {
     return PC_OK;
 }
 
+// Load positions (id order, device) into P[0] without touching the field.
+static void load_positions(pc_sim *s, const float *x, hipStream_t st) {
+    if (s->binned) launch_zero_u32(s->b.count, s->d.bins_total + 1, st);
+    launch_init_agents(s->sp, s->b, x, s->b.species_id, 0, st);
+    s->binned = 0;
+    s->sorted = 0;
+}
+
 int pc_adjoint_segment(pc_sim *s, const float *lamX_in_dev, const float *lamC_in_dev,
                        int n_steps, float *lamX_out_dev, float *lamC_out_dev,
                        double *dtheta_out) {
-    (void)lamX_in_dev; (void)lamC_in_dev; (void)n_steps; (void)lamX_out_dev;
-    (void)lamC_out_dev; (void)dtheta_out;
-    if (!s) return fail(PC_EINVAL, "null handle");
-    return fail(PC_ENOTSUP, "adjoint not built yet");
+    if (!s || !lamX_in_dev || !lamC_in_dev || !lamX_out_dev || !lamC_out_dev || !dtheta_out)
+        return fail(PC_EINVAL, "null argument");
+    if (s->seg_steps < 1) return fail(PC_ENOTSUP, "workspace holds no adjoint segment");
+    if (n_steps < 1 || n_steps > s->seg_steps)
+        return fail(PC_EINVAL, "n_steps must be in [1, segment capacity]");
+    hipStream_t st = s->stream;
+    const Buffers &b = s->b;
+    const size_t XD = (size_t)s->d.n_total * s->d.dim;
+    const int64_t G = s->d.nodes_total;
+    const uint32_t t0 = s->host_step;
+    const int ns = s->d.n_sub;
+    // 1) recompute the forward segment, keeping X^t (t = 0..n) and c^t (t < n)
+    for (int t = 0; t < n_steps; ++t) {
+        launch_positions(s->sp, b, 0, b.seg_x + t * XD, st);
+        HIP_OK(hipMemcpyAsync(b.seg_c + t * G, b.c[s->cur_c], 4 * G, hipMemcpyDeviceToDevice, st));
+        enqueue_step(s, st);
+        s->host_step += 1;
+    }
+    launch_positions(s->sp, b, 0, b.seg_x + (size_t)n_steps * XD, st);
+    // 2) reverse sweep
+    HIP_OK(hipMemcpyAsync(b.lamX[0], lamX_in_dev, 4 * XD, hipMemcpyDeviceToDevice, st));
+    HIP_OK(hipMemcpyAsync(b.lamC[0], lamC_in_dev, 4 * G, hipMemcpyDeviceToDevice, st));
+    launch_zero_f64(b.dth, 3 * (int64_t)s->d.ni, st);
+    int cx = 0, cc = 0;
+    for (int t = n_steps - 1; t >= 0; --t) {
+        // deposit of X^{t+1}
+        load_positions(s, b.seg_x + (size_t)(t + 1) * XD, st);
+        launch_deposit(s->sp, b, 0, st);
+        // forward PDE substeps from c^t (inputs of the reversed substeps)
+        HIP_OK(hipMemcpyAsync(b.csub, b.seg_c + t * G, 4 * G, hipMemcpyDeviceToDevice, st));
+        for (int m = 1; m < ns; ++m)
+            launch_pde_ptr(s->pp, b.csub + (m - 1) * G, b.csub + m * G, b.S_src, b.S_upt, 0,
+                           b.flags, st);
+        // reversed substeps: lamC[cc] -> ... -> mu^(0)
+        for (int m = ns; m >= 1; --m) {
+            launch_adj_pde(s->pp, b.lamC[cc], b.lamC[1 - cc], b.csub + (m - 1) * G, b, b.aSrc,
+                           b.aUpt, m == ns ? 1 : 0, m == 1 ? 1 : 0, st);
+            cc = 1 - cc;
+        }
+        // agents at X^t, cell-sorted
+        load_positions(s, b.seg_x + (size_t)t * XD, st);
+        ensure_sorted(s, st);
+        launch_zero_f32(b.lamG, G * s->d.dim, st);
+        AdjArgs A;
+        A.xnext = b.seg_x + (size_t)(t + 1) * XD;
+        A.lamX_in = b.lamX[cx];
+        A.aSrc = b.aSrc;
+        A.aUpt = b.aUpt;
+        A.lamY = b.lamY;
+        A.lamX_out = b.lamX[1 - cx];
+        A.lamG = b.lamG;
+        A.dth = b.dth;
+        A.nodes_total = G;
+        A.step = t0 + (uint32_t)t;
+        launch_adj_agent(s->sp, A, b, s->sorted_src, b.seg_c + t * G, st);
+        launch_adj_pair(s->sp, b, s->sorted_src, b.lamY, b.lamX[1 - cx], st);
+        launch_adj_grad(s->pp, s->sp.inv_2h, b.lamC[cc], b.lamG, b.lamC[1 - cc], st);
+        cc = 1 - cc;
+        cx = 1 - cx;
+    }
+    HIP_OK(hipMemcpyAsync(lamX_out_dev, b.lamX[cx], 4 * XD, hipMemcpyDeviceToDevice, st));
+    HIP_OK(hipMemcpyAsync(lamC_out_dev, b.lamC[cc], 4 * G, hipMemcpyDeviceToDevice, st));
+    HIP_OK(hipMemcpyAsync(dtheta_out, b.dth, 8 * 3 * (size_t)s->d.ni, hipMemcpyDeviceToHost, st));
+    // 3) leave the state as it was at the start of the segment
+    int rc = pc_set_state(s, b.seg_x, b.seg_c, t0);
+    if (rc) return rc;
+    HIP_OK(hipStreamSynchronize(st));
+    HIP_OK(hipGetLastError());
+    return PC_OK;
+}
+
+size_t pc_density_loss_work_bytes(pc_sim *s, int hist_n) {
+    if (!s || hist_n < 2) return 0;
+    size_t H = 1;
+    for (int a = 0; a < s->d.dim; ++a) H *= (size_t)hist_n;
+    const size_t HN = H * (size_t)s->d.ni;
+    return 8 * HN + 4 * HN * 2 + 8 * (size_t)s->d.ni + 1024;
+}
+
+static int density_common(pc_sim *s, const float *target_dev, int hist_n, double sigma_bins,
+                          void *work_dev, size_t work_bytes, double *loss_out, float *dLdX_dev,
+                          float *rho_out) {
+    if (!s->d.periodic) return fail(PC_ENOTSUP, "the density loss is defined on the torus");
+    if (hist_n < 2) return fail(PC_EINVAL, "hist_n must be >= 2");
+    const int R = (int)floor(3.0 * sigma_bins + 0.5);
+    if (!(sigma_bins > 0) || 2 * R + 1 > 65 || 2 * R + 1 > hist_n)
+        return fail(PC_EINVAL, "sigma_bins out of range");
+    if (work_bytes < pc_density_loss_work_bytes(s, hist_n) || ((uintptr_t)work_dev & 255))
+        return fail(PC_ENOSPACE, "loss work buffer too small or misaligned");
+    LossArgs a;
+    memset(&a, 0, sizeof(a));
+    a.m = hist_n;
+    a.dim = s->d.dim;
+    a.radius = R;
+    a.n_taps = 2 * R + 1;
+    a.L = (float)s->cfg.L;
+    a.inv_hh = (float)(hist_n / s->cfg.L);
+    a.H = 1;
+    for (int k = 0; k < a.dim; ++k) a.H *= hist_n;
+    double tot = 0.0, w[65];
+    for (int k = -R; k <= R; ++k) tot += (w[k + R] = exp(-0.5 * k * k / (sigma_bins * sigma_bins)));
+    for (int k = 0; k < a.n_taps; ++k) a.taps[k] = (float)(w[k] / tot);
+    const size_t HN = (size_t)a.H * s->d.ni;
+    char *wp = (char *)work_dev;
+    unsigned long long *hist = (unsigned long long *)wp;
+    float *b0 = (float *)(wp + 8 * HN);
+    float *b1 = b0 + HN;
+    double *loss = (double *)(((uintptr_t)(b1 + HN) + 255) & ~(uintptr_t)255);
+    launch_loss(a, s->sp, s->b, s->d.ni, target_dev, hist, b0, b1, loss, dLdX_dev, rho_out,
+                s->stream);
+    if (loss_out)
+        HIP_OK(hipMemcpyAsync(loss_out, loss, 8 * (size_t)s->d.ni, hipMemcpyDeviceToHost,
+                              s->stream));
+    HIP_OK(hipStreamSynchronize(s->stream));
+    HIP_OK(hipGetLastError());
+    return PC_OK;
+}
+
+int pc_density_loss(pc_sim *s, const float *target_dev, int hist_n, double sigma_bins,
+                    void *work_dev, size_t work_bytes, double *loss_out, float *dLdX_dev) {
+    if (!s || !target_dev || !work_dev || !loss_out) return fail(PC_EINVAL, "null argument");
+    return density_common(s, target_dev, hist_n, sigma_bins, work_dev, work_bytes, loss_out,
+                          dLdX_dev, nullptr);
+}
+
+int pc_density_hist(pc_sim *s, int hist_n, double sigma_bins, void *work_dev, size_t work_bytes,
+                    float *rho_out_dev) {
+    if (!s || !work_dev || !rho_out_dev) return fail(PC_EINVAL, "null argument");
+    return density_common(s, nullptr, hist_n, sigma_bins, work_dev, work_bytes, nullptr,
+                          nullptr, rho_out_dev);
 }
 
 }  // extern "C"

@@ -1,0 +1,413 @@
+// Device-side building blocks shared by the step kernels (pc_kernels.hip)
+// and the reverse-mode kernels (pc_adjoint.hip): block mapping, Philox
+// noise, species tables, cell-list bins and pair loop, grid geometry,
+// gradient interpolation and the boundary map.
+#pragma once
+
+#include "pc_internal.h"
+
+namespace pc {
+
+// ---------------------------------------------------------------------------
+// Launch helpers
+// ---------------------------------------------------------------------------
+
+// Work-groups are dealt to the 8 XCDs round robin.  Give each XCD one
+// contiguous chunk of logical blocks, so that spatially adjacent agents
+// (adjacent in cell-sorted order) share an XCD's L2.
+__device__ __forceinline__ uint32_t xcd_block(uint32_t bid, uint32_t nblocks) {
+    const uint32_t nx = 8;
+    const uint32_t per = nblocks / nx, rem = nblocks % nx;
+    const uint32_t x = bid % nx, k = bid / nx;
+    return (x < rem ? x * (per + 1) : rem * (per + 1) + (x - rem) * per) + k;
+}
+
+__device__ __forceinline__ uint32_t inst_of(float w) { return __float_as_uint(w) >> 8; }
+__device__ __forceinline__ int species_of(float w) { return (int)(__float_as_uint(w) & 0xffu); }
+
+// ---------------------------------------------------------------------------
+// Counter-based noise: Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11).
+// ---------------------------------------------------------------------------
+struct U4 { uint32_t v[4]; };
+
+__device__ __forceinline__ U4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                            uint32_t k0, uint32_t k1) {
+    const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+    const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t hi0 = __umulhi(M0, c0), lo0 = M0 * c0;
+        const uint32_t hi1 = __umulhi(M1, c2), lo1 = M1 * c2;
+        const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+        k0 += W0; k1 += W1;
+    }
+    U4 o;
+    o.v[0] = c0; o.v[1] = c1; o.v[2] = c2; o.v[3] = c3;
+    return o;
+}
+
+// Uniform in (0,1): top 24 bits with the last kept bit set, times 2^-24.
+__device__ __forceinline__ float uniform24(uint32_t w) {
+    return (float)((w >> 8) | 1u) * 5.9604644775390625e-8f;
+}
+
+// Box-Muller normals: (xi0, xi1) from words 0, 1 and xi2 from words 2, 3.
+template <int DIM>
+__device__ __forceinline__ void normals(const U4 &w, float xi[3]) {
+    const float u0 = uniform24(w.v[0]), u1 = uniform24(w.v[1]);
+    const float r0 = sqrtf(-2.0f * logf(u0));
+    float s1, c1;
+    sincospif(2.0f * u1, &s1, &c1);
+    xi[0] = r0 * c1;
+    xi[1] = r0 * s1;
+    xi[2] = 0.0f;
+    if (DIM == 3) {
+        const float u2 = uniform24(w.v[2]), u3 = uniform24(w.v[3]);
+        const float r1 = sqrtf(-2.0f * logf(u2));
+        xi[2] = r1 * cospif(2.0f * u3);
+    }
+}
+
+__device__ __forceinline__ unsigned long long splitmix64(unsigned long long x) {
+    unsigned long long z = x + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// ---------------------------------------------------------------------------
+// Species tables: NS = 1 or 2 select from registers, otherwise LDS.
+// ---------------------------------------------------------------------------
+struct SpTab {
+    float cut2[kMaxSpecies * kMaxSpecies];
+    float dij[kMaxSpecies * kMaxSpecies];
+    float amp[kMaxSpecies], chi[kMaxSpecies], src[kMaxSpecies], upt[kMaxSpecies];
+};
+
+__device__ __forceinline__ void load_tab(const StepParams &p, SpTab &t) {
+    const int n2 = p.n_species * p.n_species;
+    for (int q = threadIdx.x; q < n2; q += blockDim.x) {
+        t.cut2[q] = p.cut2[q];
+        t.dij[q] = p.dij[q];
+    }
+    for (int q = threadIdx.x; q < p.n_species; q += blockDim.x) {
+        t.amp[q] = p.amp[q];
+        t.chi[q] = p.chi[q];
+        t.src[q] = p.src_fx[q];
+        t.upt[q] = p.upt_fx[q];
+    }
+}
+
+template <int NS>
+__device__ __forceinline__ float sel(const float *kern, const float *lds, int s) {
+    if (NS == 1) return kern[0];
+    if (NS == 2) return s ? kern[1] : kern[0];
+    return lds[s];
+}
+
+// ---------------------------------------------------------------------------
+// Cell-list bins.  nb bins per axis of side L / nb; global bin =
+// instance bin base + bx + nb (by + nb bz).
+// ---------------------------------------------------------------------------
+template <int DIM>
+__device__ __forceinline__ uint32_t agent_bin(const StepParams &p, float4 x) {
+    const float top = (float)(p.nb - 1);
+    const int bx = (int)fminf(fmaxf(x.x * p.inv_bin, 0.0f), top);
+    const int by = (int)fminf(fmaxf(x.y * p.inv_bin, 0.0f), top);
+    int bz = 0;
+    if (DIM == 3) bz = (int)fminf(fmaxf(x.z * p.inv_bin, 0.0f), top);
+    return (uint32_t)(bx + p.nb * (by + p.nb * bz));
+}
+
+// Candidates j in [a, e) of one contiguous bin range.  dx = (x_j - x_i)
+// (+ seam shift), r2 = dx.dx in plain float32 operations left to right; the
+// visitor receives every candidate with its squared contact distance c2 and
+// contact distance dd and decides what a neighbour is (r2 < c2).
+template <int DIM, int NS, bool SHIFT, class V>
+__device__ __forceinline__ void pair_range(const StepParams &p, const SpTab &tab,
+                                           const float4 *__restrict__ Ps, uint32_t a,
+                                           uint32_t e, const float4 &pi, int si, float sx,
+                                           float sy, float sz, const float c2row[2],
+                                           const float drow[2], V &v) {
+    for (uint32_t j = a; j < e; ++j) {
+        const float4 q = Ps[j];
+        float dx = q.x - pi.x, dy = q.y - pi.y, dz = 0.0f;
+        if (SHIFT) {
+            dx = dx + sx;
+            dy = dy + sy;
+        }
+        float r2 = dx * dx + dy * dy;
+        if (DIM == 3) {
+            dz = q.z - pi.z;
+            if (SHIFT) dz = dz + sz;
+            r2 = r2 + dz * dz;
+        }
+        float c2, dd;
+        if (NS == 1) {
+            c2 = c2row[0];
+            dd = drow[0];
+        } else if (NS == 2) {
+            const bool s1 = species_of(q.w) != 0;
+            c2 = s1 ? c2row[1] : c2row[0];
+            dd = s1 ? drow[1] : drow[0];
+        } else {
+            const int sj = species_of(q.w);
+            c2 = tab.cut2[si * p.n_species + sj];
+            dd = tab.dij[si * p.n_species + sj];
+        }
+        v(j, dx, dy, dz, r2, c2, dd);
+    }
+}
+
+// Repulsion F_i = -sum k (d_ij - r) dx / r over neighbours with r > 0,
+// evaluated as k d / r - k.
+struct ForceVisitor {
+    float k;
+    float F[3];
+    __device__ __forceinline__ void operator()(uint32_t, float dx, float dy, float dz, float r2,
+                                               float c2, float dd) {
+        if (r2 < c2 && r2 > 0.0f) {
+            const float f = fmaf(k * dd, rsqrtf(r2), -k);
+            F[0] = fmaf(-f, dx, F[0]);
+            F[1] = fmaf(-f, dy, F[1]);
+            F[2] = fmaf(-f, dz, F[2]);
+        }
+    }
+};
+
+// Forces plus the neighbour count and id hash (self excluded).
+struct DebugVisitor {
+    ForceVisitor fv;
+    uint32_t self;
+    const uint32_t *Is;
+    uint32_t cnt;
+    unsigned long long hs;
+    __device__ __forceinline__ void operator()(uint32_t j, float dx, float dy, float dz, float r2,
+                                               float c2, float dd) {
+        if (r2 < c2 && j != self) {
+            cnt += 1;
+            hs += splitmix64((unsigned long long)Is[j]);
+        }
+        fv(j, dx, dy, dz, r2, c2, dd);
+    }
+};
+
+// Pair loop over the neighbour bins of an agent at position pi.
+// dx = x_j - x_i, plus -L / +L for bins reached through the periodic seam:
+// for every pair closer than the cutoff this is exactly the minimum image,
+// because the seam is crossed iff |x_j - x_i| > L/2 for such pairs.
+// Along x, neighbouring bins are adjacent in memory, so each (y, z) row of
+// the stencil is one contiguous agent range (two at the seam).
+template <int DIM, int NS, int STENCIL, class V>
+__device__ __forceinline__ void pair_loop(const StepParams &p, const SpTab &tab,
+                                          const float4 *__restrict__ Ps,
+                                          const uint32_t *__restrict__ start, uint32_t bin_base,
+                                          float4 pi, int si, V &v) {
+    const int nb = p.nb;
+    const float pc[3] = {pi.x, pi.y, pi.z};
+    int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+    // squared distance from x_i to the lower / upper face of its own bin
+    float glo2[3] = {0.f, 0.f, 0.f}, ghi2[3] = {0.f, 0.f, 0.f};
+    const float side = p.L / (float)nb;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        const float s = fmaxf(pc[a] * p.inv_bin, 0.0f);
+        const int b = min((int)s, nb - 1);
+        if (STENCIL == 3) {
+            lo[a] = b - 1;
+            hi[a] = b + 1;
+            const float f = fminf(fmaxf(s - (float)b, 0.0f), 1.0f);
+            glo2[a] = (f * side) * (f * side);
+            ghi2[a] = ((1.0f - f) * side) * ((1.0f - f) * side);
+        } else {
+            const int up = (s - (float)b) >= 0.5f ? 1 : 0;
+            lo[a] = b - 1 + up;
+            hi[a] = lo[a] + 1;
+        }
+    }
+    float c2row[2] = {0.f, 0.f}, drow[2] = {0.f, 0.f};
+    if (NS == 1) {
+        c2row[0] = p.cut2[0];
+        drow[0] = p.dij[0];
+    } else if (NS == 2) {
+        c2row[0] = p.cut2[si * 2 + 0];
+        c2row[1] = p.cut2[si * 2 + 1];
+        drow[0] = p.dij[si * 2 + 0];
+        drow[1] = p.dij[si * 2 + 1];
+    }
+    // Bins whose nearest face is farther than the largest contact distance
+    // of species si cannot hold a neighbour (3^dim stencil only).  The
+    // threshold carries a 1e-3 margin over float32 rounding of the faces.
+    float cmax2;
+    if (NS == 1) {
+        cmax2 = c2row[0];
+    } else if (NS == 2) {
+        cmax2 = fmaxf(c2row[0], c2row[1]);
+    } else {
+        cmax2 = 0.0f;
+        for (int t = 0; t < p.n_species; ++t) cmax2 = fmaxf(cmax2, tab.cut2[si * p.n_species + t]);
+    }
+    cmax2 *= 1.001f;
+    const float L = p.L;
+    const int zlo = DIM == 3 ? lo[2] : 0, zhi = DIM == 3 ? hi[2] : 0;
+    for (int oz = zlo; oz <= zhi; ++oz) {
+        int qz = oz;
+        float sz = 0.0f;
+        if (DIM == 3) {
+            if (qz < 0) {
+                if (!p.periodic) continue;
+                qz += nb;
+                sz = -L;
+            } else if (qz >= nb) {
+                if (!p.periodic) continue;
+                qz -= nb;
+                sz = L;
+            }
+        }
+        for (int oy = lo[1]; oy <= hi[1]; ++oy) {
+            int qy = oy;
+            float sy = 0.0f;
+            if (qy < 0) {
+                if (!p.periodic) continue;
+                qy += nb;
+                sy = -L;
+            } else if (qy >= nb) {
+                if (!p.periodic) continue;
+                qy -= nb;
+                sy = L;
+            }
+            int xlo = lo[0], xhi = hi[0];
+            if (STENCIL == 3) {
+                float d2 = oy < lo[1] + 1 ? glo2[1] : (oy > lo[1] + 1 ? ghi2[1] : 0.0f);
+                if (DIM == 3) d2 += oz < lo[2] + 1 ? glo2[2] : (oz > lo[2] + 1 ? ghi2[2] : 0.0f);
+                if (d2 >= cmax2) continue;
+                if (d2 + glo2[0] >= cmax2) xlo += 1;
+                if (d2 + ghi2[0] >= cmax2) xhi -= 1;
+            }
+            const uint32_t row = bin_base + (uint32_t)((qz * nb + qy) * nb);
+            const int m0 = max(xlo, 0), m1 = min(xhi, nb - 1);
+            const uint32_t a0 = start[row + m0], e0 = start[row + m1 + 1];
+            if (sy == 0.0f && sz == 0.0f)
+                pair_range<DIM, NS, false>(p, tab, Ps, a0, e0, pi, si, 0.f, 0.f, 0.f, c2row, drow,
+                                           v);
+            else
+                pair_range<DIM, NS, true>(p, tab, Ps, a0, e0, pi, si, 0.f, sy, sz, c2row, drow,
+                                          v);
+            if (p.periodic) {
+                if (xlo < 0)
+                    pair_range<DIM, NS, true>(p, tab, Ps, start[row + xlo + nb], start[row + nb],
+                                              pi, si, -L, sy, sz, c2row, drow, v);
+                if (xhi > nb - 1)
+                    pair_range<DIM, NS, true>(p, tab, Ps, start[row], start[row + xhi - nb + 1],
+                                              pi, si, L, sy, sz, c2row, drow, v);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Grid geometry.  Periodic: spacing L/n, nodes i*h, upper corner wraps.
+// Walls: spacing L/(n-1), nodes on both walls, lower corner <= n-2.
+// ---------------------------------------------------------------------------
+struct Cell { int i0, i1; float t; };
+
+__device__ __forceinline__ Cell cell_of(const StepParams &p, float x) {
+    const float s = fmaxf(x * p.inv_h, 0.0f);
+    const float fi = fminf(floorf(s), p.cell_top);
+    Cell c;
+    c.i0 = (int)fi;
+    c.t = s - fi;
+    c.i1 = c.i0 + 1;
+    if (p.periodic && c.i1 == p.grid_n) c.i1 = 0;
+    return c;
+}
+
+// index at offset -1 / +2 of a cell's lower corner, periodic wrap or mirror
+__device__ __forceinline__ int idx_m1(const StepParams &p, int i0) {
+    if (i0 > 0) return i0 - 1;
+    return p.periodic ? p.grid_n - 1 : 1;
+}
+__device__ __forceinline__ int idx_p2(const StepParams &p, int i0) {
+    const int q = i0 + 2;
+    if (q < p.grid_n) return q;
+    return p.periodic ? q - p.grid_n : p.grid_n - 2;
+}
+
+// Multilinear interpolation at x of the centred-difference gradient of c,
+// computed on the fly from the 4^dim-minus-corners stencil of c around the
+// agent's cell (the node gradient field itself is never stored).
+template <int DIM>
+__device__ __forceinline__ void grad_interp(const StepParams &p, const float *__restrict__ c,
+                                            float4 x, float g[3]) {
+    const Cell cx = cell_of(p, x.x), cy = cell_of(p, x.y);
+    const int n = p.grid_n;
+    const int X4[4] = {idx_m1(p, cx.i0), cx.i0, cx.i1, idx_p2(p, cx.i0)};
+    const int Y4[4] = {idx_m1(p, cy.i0), cy.i0, cy.i1, idx_p2(p, cy.i0)};
+    const float wx[2] = {1.0f - cx.t, cx.t}, wy[2] = {1.0f - cy.t, cy.t};
+    const float ih2 = p.inv_2h;
+    if (DIM == 2) {
+        float gx = 0.f, gy = 0.f;
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+                const int ry = Y4[b + 1] * n, rx = X4[a + 1];
+                const float ddx = c[ry + X4[a + 2]] - c[ry + X4[a]];
+                const float ddy = c[Y4[b + 2] * n + rx] - c[Y4[b] * n + rx];
+                const float w = wx[a] * wy[b];
+                gx = fmaf(w, ddx, gx);
+                gy = fmaf(w, ddy, gy);
+            }
+        g[0] = gx * ih2;
+        g[1] = gy * ih2;
+        g[2] = 0.f;
+    } else {
+        const Cell cz = cell_of(p, x.z);
+        const int Z4[4] = {idx_m1(p, cz.i0), cz.i0, cz.i1, idx_p2(p, cz.i0)};
+        const float wz[2] = {1.0f - cz.t, cz.t};
+        const int nn = n * n;
+        float gx = 0.f, gy = 0.f, gz = 0.f;
+#pragma unroll
+        for (int e = 0; e < 2; ++e)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int a = 0; a < 2; ++a) {
+                    const int zo = Z4[e + 1] * nn, yo = Y4[b + 1] * n, xo = X4[a + 1];
+                    const float ddx = c[zo + yo + X4[a + 2]] - c[zo + yo + X4[a]];
+                    const float ddy = c[zo + Y4[b + 2] * n + xo] - c[zo + Y4[b] * n + xo];
+                    const float ddz = c[Z4[e + 2] * nn + yo + xo] - c[Z4[e] * nn + yo + xo];
+                    const float w = wx[a] * wy[b] * wz[e];
+                    gx = fmaf(w, ddx, gx);
+                    gy = fmaf(w, ddy, gy);
+                    gz = fmaf(w, ddz, gz);
+                }
+        g[0] = gx * ih2;
+        g[1] = gy * ih2;
+        g[2] = gz * ih2;
+    }
+}
+
+__device__ __forceinline__ float boundary(const StepParams &p, float x, uint32_t &flag) {
+    const float L = p.L;
+    if (p.periodic) {
+        x = x - L * floorf(x / L);
+        if (x >= L) x -= L;
+        if (!(x >= 0.0f)) {
+            x = 0.0f;
+            flag |= FLAG_WARN_CLAMPED;
+        }
+        return x;
+    }
+    if (x < 0.0f) x = -x;
+    else if (x > L) x = 2.0f * L - x;
+    if (x < 0.0f || x > L) {
+        x = fminf(fmaxf(x, 0.0f), L);
+        flag |= FLAG_WARN_CLAMPED;
+    }
+    return x;
+}
+
+
+}  // namespace pc

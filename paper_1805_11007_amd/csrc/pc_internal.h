@@ -51,6 +51,7 @@ struct PdeParams {
     int64_t n_nodes_total;
     float dts, D_c, gamma, inv_h2;
     float fx_to_density;   // 2^-32 / h^dim
+    float inv_hd;          // 1 / h^dim
     int32_t has_uptake;
 };
 
@@ -76,12 +77,37 @@ struct Buffers {
     uint8_t *species_id;   // species in id order (for set_state)
     uint32_t *step;        // device step counter
     uint32_t *flags;
-    // adjoint segment storage (optional)
-    float *seg_x;          // seg_steps x n_total x dim, id order
+    // reverse mode (present when the workspace holds a segment)
+    float *seg_x;          // (seg_steps + 1) x n_total x dim, id order
     float *seg_c;          // seg_steps x nodes_total
-    float *adj[8];         // adjoint work arrays
-    double *adj_red;       // reductions
+    float *lamX[2];        // n_total x dim
+    float *lamY;           // n_total x dim
+    float *lamC[2];        // nodes_total
+    float *aSrc, *aUpt;    // dL/dS at nodes
+    float *lamG;           // dim x nodes_total
+    float *csub;           // n_sub x nodes_total
+    double *dth;           // 3 x n_inst
 };
+
+struct AdjArgs {
+    const float *xnext;    // X^{n+1}, id order, n_total x dim
+    const float *lamX_in;  // dL/dX^{n+1}
+    const float *aSrc, *aUpt;  // dL/dS at nodes
+    float *lamY;           // dL/dy (pre-boundary), id order
+    float *lamX_out;       // dL/dX^n (drift and identity terms; pair term added later)
+    float *lamG;           // dL/d(node gradient), dim x nodes_total
+    double *dth;           // 3 per instance: d/d scale of chi, k, D
+    int64_t nodes_total;
+    uint32_t step;         // step counter of X^n
+};
+
+struct LossArgs {
+    int m, dim, n_taps, radius;
+    float L, inv_hh;       // histogram spacing L/m and its inverse
+    int64_t H;             // m^dim
+    float taps[65];
+};
+
 
 // Launch wrappers implemented in pc_kernels.hip.
 void launch_init_agents(const StepParams &p, const Buffers &b, const float *x, const uint8_t *sp,
@@ -104,7 +130,25 @@ void launch_positions(const StepParams &p, const Buffers &b, int src, float *out
 void launch_species(const StepParams &p, const Buffers &b, int src, uint8_t *out, hipStream_t s);
 void launch_debug_pairs(const StepParams &p, const Buffers &b, int src, uint32_t *count,
                         unsigned long long *hash, float *F, int block, hipStream_t s);
+void launch_pde_ptr(const PdeParams &q, const float *cin, float *cout, unsigned long long *Ssrc,
+                    unsigned long long *Supt, int last, uint32_t *flags, hipStream_t s);
 void launch_set_u32(uint32_t *ptr, uint32_t v, hipStream_t s);
+// reverse mode and loss (pc_adjoint.hip)
+void launch_adj_pde(const PdeParams &q, const float *mu_in, float *mu_out, const float *cprev,
+                    const Buffers &b, float *aSrc, float *aUpt, int first, int last,
+                    hipStream_t s);
+void launch_adj_agent(const StepParams &p, const AdjArgs &A, const Buffers &b, int src,
+                      const float *c, hipStream_t s);
+void launch_adj_pair(const StepParams &p, const Buffers &b, int src, const float *lamY,
+                     float *lamX_out, hipStream_t s);
+void launch_adj_grad(const PdeParams &q, float inv_2h, const float *mu0, const float *lamG,
+                     float *lamC_out, hipStream_t s);
+void launch_zero_f32(float *d, int64_t n, hipStream_t s);
+void launch_zero_f64(double *d, int64_t n, hipStream_t s);
+void launch_zero_u64(unsigned long long *d, int64_t n, hipStream_t s);
+void launch_loss(const LossArgs &a, const StepParams &p, const Buffers &b, int n_inst,
+                 const float *target, unsigned long long *hist, float *buf0, float *buf1,
+                 double *loss, float *dLdX, float *rho_out, hipStream_t s);
 void launch_copy_f32(float *dst, const float *src, int64_t n, hipStream_t s);
 
 }  // namespace pc

@@ -209,6 +209,54 @@ class Sim:
         LB.check(self.L.pc_profile_steps(self.h, int(n), out))
         return dict(zip(LB.STAGES, list(out)))
 
+    # -- reverse mode ---------------------------------------------------------
+    def adjoint_segment(self, lamX: torch.Tensor, lamC: torch.Tensor, n: int):
+        """Reverse sweep over n steps from the current state (see pc.h).
+
+        Returns (dL/dX, dL/dc) of the current state and an (n_inst, 3) array
+        of derivatives with respect to scales of chi, k and D."""
+        import numpy as np
+        lamX = lamX.to(self.device, torch.float32).contiguous()
+        lamC = lamC.to(self.device, torch.float32).contiguous()
+        ox = torch.empty_like(lamX)
+        oc = torch.empty_like(lamC)
+        ni = len(self.spec.instances)
+        dth = (C.c_double * (3 * ni))()
+        LB.check(self.L.pc_adjoint_segment(self.h, _ptr(lamX), _ptr(lamC), int(n), _ptr(ox),
+                                           _ptr(oc), dth))
+        return ox, oc, np.array(list(dth), dtype=np.float64).reshape(ni, 3)
+
+    def density_loss(self, target: torch.Tensor, hist_n: int = 64, sigma_bins: float = 2.0,
+                     grad: bool = True):
+        """Smoothed-histogram loss of the current positions per instance, and
+        optionally its gradient with respect to the positions (id order)."""
+        import numpy as np
+        target = target.to(self.device, torch.float32).contiguous()
+        nb = int(self.L.pc_density_loss_work_bytes(self.h, int(hist_n)))
+        if nb == 0:
+            raise LB.PcError(LB.PC_EINVAL, "bad histogram size")
+        work = torch.empty(nb, dtype=torch.uint8, device=self.device)
+        ni = len(self.spec.instances)
+        loss = (C.c_double * ni)()
+        g = torch.empty(self.spec.n_total, self.spec.dim, dtype=torch.float32,
+                        device=self.device) if grad else None
+        LB.check(self.L.pc_density_loss(self.h, _ptr(target), int(hist_n), float(sigma_bins),
+                                        _ptr(work), nb, loss,
+                                        _ptr(g) if grad else C.c_void_p(0)))
+        return np.array(list(loss)), g
+
+    def density_hist(self, hist_n: int = 64, sigma_bins: float = 2.0) -> torch.Tensor:
+        """Smoothed position histogram of the loss (n_inst x hist_n^dim)."""
+        nb = int(self.L.pc_density_loss_work_bytes(self.h, int(hist_n)))
+        if nb == 0:
+            raise LB.PcError(LB.PC_EINVAL, "bad histogram size")
+        work = torch.empty(nb, dtype=torch.uint8, device=self.device)
+        out = torch.empty(len(self.spec.instances) * hist_n ** self.spec.dim,
+                          dtype=torch.float32, device=self.device)
+        LB.check(self.L.pc_density_hist(self.h, int(hist_n), float(sigma_bins), _ptr(work), nb,
+                                        _ptr(out)))
+        return out
+
     # -- debug --------------------------------------------------------------
     def debug_neighbours(self):
         cnt = torch.empty(self.spec.n_total, dtype=torch.int32, device=self.device)

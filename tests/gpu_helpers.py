@@ -7,12 +7,12 @@ import oracle
 import workloads as W
 
 
-def make_sim(w, inp, **over):
+def make_sim(w, inp, adjoint_steps=0, **over):
     import torch
     from paper_1805_11007_amd import ModelSpec, Sim
     spec = ModelSpec.from_workload(w, **over)
     return Sim(spec, torch.from_numpy(inp["x0"]), torch.from_numpy(inp["species0"]),
-               torch.from_numpy(inp["c0"]), device="cuda:0")
+               torch.from_numpy(inp["c0"]), device="cuda:0", adjoint_steps=adjoint_steps)
 
 
 def pos_err(x_gpu, x_ref, L, periodic):
