@@ -125,38 +125,60 @@ __device__ __forceinline__ uint32_t agent_bin(const StepParams &p, float4 x) {
 // visitor receives every candidate with its squared contact distance c2 and
 // contact distance dd and decides what a neighbour is (r2 < c2).
 template <int DIM, int NS, bool SHIFT, class V>
+__device__ __forceinline__ void pair_one(const StepParams &p, const SpTab &tab, uint32_t j,
+                                         const float4 &q, const float4 &pi, int si, float sx,
+                                         float sy, float sz, const float c2row[2],
+                                         const float drow[2], V &v) {
+    float dx = q.x - pi.x, dy = q.y - pi.y, dz = 0.0f;
+    if (SHIFT) {
+        dx = dx + sx;
+        dy = dy + sy;
+    }
+    float r2 = dx * dx + dy * dy;
+    if (DIM == 3) {
+        dz = q.z - pi.z;
+        if (SHIFT) dz = dz + sz;
+        r2 = r2 + dz * dz;
+    }
+    float c2, dd;
+    if (NS == 1) {
+        c2 = c2row[0];
+        dd = drow[0];
+    } else if (NS == 2) {
+        const bool s1 = species_of(q.w) != 0;
+        c2 = s1 ? c2row[1] : c2row[0];
+        dd = s1 ? drow[1] : drow[0];
+    } else {
+        const int sj = species_of(q.w);
+        c2 = tab.cut2[si * p.n_species + sj];
+        dd = tab.dij[si * p.n_species + sj];
+    }
+    v(j, dx, dy, dz, r2, c2, dd);
+}
+
+// Candidates j in [a, e) of one contiguous bin range.  dx = (x_j - x_i)
+// (+ seam shift), r2 = dx.dx in plain float32 operations left to right; the
+// visitor receives every candidate with its squared contact distance c2 and
+// contact distance dd and decides what a neighbour is (r2 < c2).  Loads are
+// issued four candidates ahead of the arithmetic so that one wave keeps
+// several memory requests in flight.
+template <int DIM, int NS, bool SHIFT, class V>
 __device__ __forceinline__ void pair_range(const StepParams &p, const SpTab &tab,
                                            const float4 *__restrict__ Ps, uint32_t a,
                                            uint32_t e, const float4 &pi, int si, float sx,
                                            float sy, float sz, const float c2row[2],
                                            const float drow[2], V &v) {
-    for (uint32_t j = a; j < e; ++j) {
+    uint32_t j = a;
+    for (; j + 4 <= e; j += 4) {
+        const float4 q0 = Ps[j], q1 = Ps[j + 1], q2 = Ps[j + 2], q3 = Ps[j + 3];
+        pair_one<DIM, NS, SHIFT>(p, tab, j, q0, pi, si, sx, sy, sz, c2row, drow, v);
+        pair_one<DIM, NS, SHIFT>(p, tab, j + 1, q1, pi, si, sx, sy, sz, c2row, drow, v);
+        pair_one<DIM, NS, SHIFT>(p, tab, j + 2, q2, pi, si, sx, sy, sz, c2row, drow, v);
+        pair_one<DIM, NS, SHIFT>(p, tab, j + 3, q3, pi, si, sx, sy, sz, c2row, drow, v);
+    }
+    for (; j < e; ++j) {
         const float4 q = Ps[j];
-        float dx = q.x - pi.x, dy = q.y - pi.y, dz = 0.0f;
-        if (SHIFT) {
-            dx = dx + sx;
-            dy = dy + sy;
-        }
-        float r2 = dx * dx + dy * dy;
-        if (DIM == 3) {
-            dz = q.z - pi.z;
-            if (SHIFT) dz = dz + sz;
-            r2 = r2 + dz * dz;
-        }
-        float c2, dd;
-        if (NS == 1) {
-            c2 = c2row[0];
-            dd = drow[0];
-        } else if (NS == 2) {
-            const bool s1 = species_of(q.w) != 0;
-            c2 = s1 ? c2row[1] : c2row[0];
-            dd = s1 ? drow[1] : drow[0];
-        } else {
-            const int sj = species_of(q.w);
-            c2 = tab.cut2[si * p.n_species + sj];
-            dd = tab.dij[si * p.n_species + sj];
-        }
-        v(j, dx, dy, dz, r2, c2, dd);
+        pair_one<DIM, NS, SHIFT>(p, tab, j, q, pi, si, sx, sy, sz, c2row, drow, v);
     }
 }
 

@@ -1,0 +1,58 @@
+"""The C ABI library (CPU side only): it loads, exports every entry point
+that include/pc.h declares, and its host-only calls validate parameters."""
+import ctypes as C
+import re
+from pathlib import Path
+
+import pytest
+
+ROOT = Path(__file__).resolve().parent.parent
+HEADER = ROOT / "include" / "pc.h"
+
+
+def _declared():
+    text = HEADER.read_text()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pc_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_and_binding_agree():
+    from paper_1805_11007_amd import _lib
+    assert set(_declared()) == set(_lib.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1805_11007_amd import _lib
+    if not _lib.LIB_PATH.exists():
+        pytest.skip("libpc.so not built")
+    lib = C.CDLL(str(_lib.LIB_PATH))
+    missing = [n for n in _declared() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def _spec(**over):
+    from paper_1805_11007_amd import InstanceSpec, ModelSpec, SpeciesSpec
+    kw = dict(dim=2, periodic=True, L=1.0, grid_n=64, dt=1e-5, k=100.0, D_c=1.0, gamma=0.1,
+              species=[SpeciesSpec(0.01, 1.0, 1.0, 1.0, 0.0)],
+              instances=[InstanceSpec(1000, 1)])
+    kw.update(over)
+    return ModelSpec(**kw)
+
+
+def test_workspace_bytes_and_validation():
+    from paper_1805_11007_amd import InstanceSpec, PcError, SpeciesSpec, workspace_bytes
+    from paper_1805_11007_amd import _lib
+    if not _lib.LIB_PATH.exists():
+        pytest.skip("libpc.so not built")
+    n1 = workspace_bytes(_spec())
+    n2 = workspace_bytes(_spec(instances=[InstanceSpec(1000, 1)] * 3))
+    assert 0 < n1 < n2
+    assert workspace_bytes(_spec(), adjoint_steps=10) > n1
+    bad = [dict(dim=4), dict(grid_n=2), dict(species=[SpeciesSpec(0.0, 1.0)]),
+           dict(species=[SpeciesSpec(0.6, 1.0)]), dict(instances=[InstanceSpec(0, 1)]),
+           dict(pde_substeps=1, dt=1e-2), dict(bin_size=0.001), dict(block=100)]
+    for over in bad:
+        with pytest.raises(PcError):
+            workspace_bytes(_spec(**over))
+    L = _lib.load()
+    assert L.pc_strerror(-2).decode().startswith("explicit PDE")
