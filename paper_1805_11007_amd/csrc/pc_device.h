@@ -272,6 +272,75 @@ __device__ __forceinline__ void pair_loop(const StepParams &p, const SpTab &tab,
     }
     cmax2 *= 1.001f;
     const float L = p.L;
+    // When every lane of the wave sits in the same bin (the rule in dense
+    // clusters), the stencil rows and candidate ranges are the same for all
+    // lanes: the loop runs on wave-uniform indices (scalar registers), and a
+    // row or edge bin is skipped only if no lane of the wave can reach it.
+    const uint32_t own = (uint32_t)(lo[0] + 1) + 1024u * (uint32_t)(lo[1] + 1) +
+                         1048576u * (uint32_t)(DIM == 3 ? lo[2] + 1 : 0);
+    const bool uniform = STENCIL == 3 && __all(own == __builtin_amdgcn_readfirstlane(own));
+    if (uniform) {
+        const int zlo = DIM == 3 ? __builtin_amdgcn_readfirstlane(lo[2]) : 0;
+        const int zhi = DIM == 3 ? zlo + 2 : 0;
+        const int ylo = __builtin_amdgcn_readfirstlane(lo[1]);
+        const int xb = __builtin_amdgcn_readfirstlane(lo[0]) + 1;
+        for (int oz = zlo; oz <= zhi; ++oz) {
+            int qz = oz;
+            float sz = 0.0f;
+            if (DIM == 3) {
+                if (qz < 0) {
+                    if (!p.periodic) continue;
+                    qz += nb;
+                    sz = -L;
+                } else if (qz >= nb) {
+                    if (!p.periodic) continue;
+                    qz -= nb;
+                    sz = L;
+                }
+            }
+            for (int oy = ylo; oy <= ylo + 2; ++oy) {
+                int qy = oy;
+                float sy = 0.0f;
+                if (qy < 0) {
+                    if (!p.periodic) continue;
+                    qy += nb;
+                    sy = -L;
+                } else if (qy >= nb) {
+                    if (!p.periodic) continue;
+                    qy -= nb;
+                    sy = L;
+                }
+                float d2 = oy < ylo + 1 ? glo2[1] : (oy > ylo + 1 ? ghi2[1] : 0.0f);
+                if (DIM == 3) d2 += oz < zlo + 1 ? glo2[2] : (oz > zlo + 1 ? ghi2[2] : 0.0f);
+                if (!__any(d2 < cmax2)) continue;
+                const int xlo = __any(d2 + glo2[0] < cmax2) ? xb - 1 : xb;
+                const int xhi = __any(d2 + ghi2[0] < cmax2) ? xb + 1 : xb;
+                const uint32_t row = bin_base + (uint32_t)((qz * nb + qy) * nb);
+                const int m0 = max(xlo, 0), m1 = min(xhi, nb - 1);
+                const uint32_t a0 = __builtin_amdgcn_readfirstlane(start[row + m0]);
+                const uint32_t e0 = __builtin_amdgcn_readfirstlane(start[row + m1 + 1]);
+                if (sy == 0.0f && sz == 0.0f)
+                    pair_range<DIM, NS, false>(p, tab, Ps, a0, e0, pi, si, 0.f, 0.f, 0.f, c2row,
+                                               drow, v);
+                else
+                    pair_range<DIM, NS, true>(p, tab, Ps, a0, e0, pi, si, 0.f, sy, sz, c2row,
+                                              drow, v);
+                if (p.periodic) {
+                    if (xlo < 0)
+                        pair_range<DIM, NS, true>(
+                            p, tab, Ps, __builtin_amdgcn_readfirstlane(start[row + xlo + nb]),
+                            __builtin_amdgcn_readfirstlane(start[row + nb]), pi, si, -L, sy, sz,
+                            c2row, drow, v);
+                    if (xhi > nb - 1)
+                        pair_range<DIM, NS, true>(
+                            p, tab, Ps, __builtin_amdgcn_readfirstlane(start[row]),
+                            __builtin_amdgcn_readfirstlane(start[row + xhi - nb + 1]), pi, si, L,
+                            sy, sz, c2row, drow, v);
+                }
+            }
+        }
+        return;
+    }
     const int zlo = DIM == 3 ? lo[2] : 0, zhi = DIM == 3 ? hi[2] : 0;
     for (int oz = zlo; oz <= zhi; ++oz) {
         int qz = oz;

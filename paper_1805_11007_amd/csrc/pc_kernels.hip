@@ -298,6 +298,25 @@ __device__ __forceinline__ float pde_node(const PdeParams &q, const float *__res
 constexpr int kDepSlots = 2048;
 constexpr uint32_t kEmpty = 0xFFFFFFFFu;
 
+__device__ __forceinline__ void lds_insert(uint32_t *keys, unsigned long long *vs,
+                                           unsigned long long *vu, bool upt, uint32_t key,
+                                           unsigned long long a, unsigned long long b,
+                                           unsigned long long *Ssrc,
+                                           unsigned long long *Supt) {
+    uint32_t h = (key * 2654435761u) >> 21;  // 11 bits: kDepSlots = 2048
+    for (int probe = 0; probe < 16; ++probe) {
+        const uint32_t old = atomicCAS(&keys[h], kEmpty, key);
+        if (old == kEmpty || old == key) {
+            if (a) atomicAdd(&vs[h], a);
+            if (upt && b) atomicAdd(&vu[h], b);
+            return;
+        }
+        h = (h + 1) & (kDepSlots - 1);
+    }
+    if (a) atomicAdd(Ssrc + key, a);
+    if (upt && b) atomicAdd(Supt + key, b);
+}
+
 template <int DIM, int NS, bool UPT>
 __global__ void __launch_bounds__(256)
 k_deposit(StepParams p, const InstInfo *__restrict__ inst, const float4 *__restrict__ P,
@@ -315,60 +334,73 @@ k_deposit(StepParams p, const InstInfo *__restrict__ inst, const float4 *__restr
     __syncthreads();
     const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
     const int i = blk * blockDim.x + threadIdx.x;
+    // corner keys and fixed-point contributions (zero for idle lanes)
+    uint32_t key[1 << DIM];
+    unsigned long long cs[1 << DIM], cu[1 << DIM];
+    bool valid = false;
     if (i < p.n_total) {
         const float4 x = P[i];
         const int s = species_of(x.w);
         const uint32_t base = inst[inst_of(x.w)].node_base;
         const float qs = sel<NS>(p.src_fx, tab.src, s);
         const float qu = UPT ? sel<NS>(p.upt_fx, tab.upt, s) : 0.0f;
-        if (qs != 0.0f || qu != 0.0f) {
-            Cell cc[3];
-            cc[0] = cell_of(p, x.x);
-            cc[1] = cell_of(p, x.y);
-            if (DIM == 3) cc[2] = cell_of(p, x.z);
-            const int n = p.grid_n;
+        valid = qs != 0.0f || qu != 0.0f;
+        Cell cc[3];
+        cc[0] = cell_of(p, x.x);
+        cc[1] = cell_of(p, x.y);
+        if (DIM == 3) cc[2] = cell_of(p, x.z);
+        const int n = p.grid_n;
 #pragma unroll
-            for (int m = 0; m < (1 << DIM); ++m) {
-                float ws = qs, wu = qu;
-                uint32_t idx = 0, stride = 1;
+        for (int m = 0; m < (1 << DIM); ++m) {
+            float ws = qs, wu = qu;
+            uint32_t idx = 0, stride = 1;
 #pragma unroll
-                for (int a = 0; a < DIM; ++a) {
-                    const int up = (m >> a) & 1;
-                    const float f = up ? cc[a].t : 1.0f - cc[a].t;
-                    ws *= f;
-                    if (UPT) wu *= f;
-                    idx += (uint32_t)(up ? cc[a].i1 : cc[a].i0) * stride;
-                    stride *= (uint32_t)n;
-                }
-                const unsigned long long vs_ = (unsigned long long)__float2ull_rn(ws);
-                const unsigned long long vu_ = UPT ? (unsigned long long)__float2ull_rn(wu) : 0ull;
-                if (vs_ == 0ull && vu_ == 0ull) continue;
-                const uint32_t key = base + idx;
-                uint32_t h = (key * 2654435761u) >> 21;  // 11 bits: kDepSlots = 2048
-                bool done = false;
-                for (int probe = 0; probe < 16; ++probe) {
-                    const uint32_t old = atomicCAS(&keys[h], kEmpty, key);
-                    if (old == kEmpty || old == key) {
-                        if (vs_) atomicAdd(&vs[h], vs_);
-                        if (UPT && vu_) atomicAdd(&vu[h], vu_);
-                        done = true;
-                        break;
-                    }
-                    h = (h + 1) & (kDepSlots - 1);
-                }
-                if (!done) {
-                    if (vs_) atomicAdd(Ssrc + key, vs_);
-                    if (UPT && vu_) atomicAdd(Supt + key, vu_);
-                }
+            for (int a = 0; a < DIM; ++a) {
+                const int up = (m >> a) & 1;
+                const float f = up ? cc[a].t : 1.0f - cc[a].t;
+                ws *= f;
+                if (UPT) wu *= f;
+                idx += (uint32_t)(up ? cc[a].i1 : cc[a].i0) * stride;
+                stride *= (uint32_t)n;
             }
+            key[m] = base + idx;
+            cs[m] = valid ? (unsigned long long)__float2ull_rn(ws) : 0ull;
+            cu[m] = valid && UPT ? (unsigned long long)__float2ull_rn(wu) : 0ull;
         }
+    } else {
+#pragma unroll
+        for (int m = 0; m < (1 << DIM); ++m) {
+            key[m] = kEmpty;
+            cs[m] = cu[m] = 0ull;
+        }
+    }
+    // In dense clusters every lane of the wave often deposits into the same
+    // 2^dim nodes: sum over the wave first and insert once per node.
+    const uint32_t k0 = valid ? key[0] : kEmpty;
+    const uint32_t f0 = __builtin_amdgcn_readfirstlane(k0);
+    const bool uniform = f0 != kEmpty && __all(!valid || k0 == f0);
+    if (uniform) {
+#pragma unroll
+        for (int m = 0; m < (1 << DIM); ++m) {
+            unsigned long long a = cs[m], b = cu[m];
+#pragma unroll
+            for (int d = 32; d >= 1; d >>= 1) {
+                a += __shfl_xor(a, d, 64);
+                if (UPT) b += __shfl_xor(b, d, 64);
+            }
+            if ((threadIdx.x & 63) == 0) lds_insert(keys, vs, vu, UPT, key[m], a, b, Ssrc, Supt);
+        }
+    } else if (valid) {
+#pragma unroll
+        for (int m = 0; m < (1 << DIM); ++m)
+            if (cs[m] || cu[m]) lds_insert(keys, vs, vu, UPT, key[m], cs[m], cu[m], Ssrc, Supt);
     }
     __syncthreads();
     for (int q = threadIdx.x; q < kDepSlots; q += blockDim.x) {
-        const uint32_t key = keys[q];
-        if (key == kEmpty) continue;
-        if (vs[q]) atomicAdd(Ssrc + key, vs[q]);
-        if (UPT && vu[q]) atomicAdd(Supt + key, vu[q]);
+        const uint32_t k = keys[q];
+        if (k == kEmpty) continue;
+        if (vs[q]) atomicAdd(Ssrc + k, vs[q]);
+        if (UPT && vu[q]) atomicAdd(Supt + k, vu[q]);
     }
 }
 
