@@ -52,7 +52,9 @@ class Params(C.Structure):
                 ("gamma", C.c_double), ("n_species", C.c_int32), ("mode", C.c_int32),
                 ("diam", C.c_double * MAX_SPECIES), ("D", C.c_double * MAX_SPECIES),
                 ("chi", C.c_double * MAX_SPECIES), ("source", C.c_double * MAX_SPECIES),
-                ("uptake", C.c_double * MAX_SPECIES), ("seed", C.c_uint64),
+                ("uptake", C.c_double * MAX_SPECIES), ("react_to", C.c_int32 * MAX_SPECIES),
+                ("react_rate", C.c_double * MAX_SPECIES),
+                ("react_rate_c", C.c_double * MAX_SPECIES), ("seed", C.c_uint64),
                 ("inst", C.c_uint32), ("chi_scale", C.c_double)]
 
 
@@ -83,6 +85,7 @@ def lib():
             "orc_drift": ([P, vp, i64, vp, vp, vp], None),
             "orc_deposit": ([P, i64, vp, vp, vp, vp], None),
             "orc_pde": ([P, vp, vp, vp], None),
+            "orc_react": ([P, i64, vp, vp, vp, vp, C.c_uint32, vp], None),
             "orc_step": ([P, i64, vp, vp, vp, vp, vp], None),
             "orc_run": ([P, i64, vp, vp, vp, vp, vp, C.c_int], None),
             "orc_density_loss": ([C.c_int, C.c_double, i64, vp, C.c_int, C.c_double, vp, vp],
@@ -123,9 +126,14 @@ def params(w, inst: int = 0, mode: int = 1, **over) -> Params:
     p.n_sub = w.pde_substeps or auto_substeps(w.dim, w.periodic, w.L, w.grid_n, w.dt, w.D_c)
     p.dt, p.k, p.D_c, p.gamma = w.dt, w.k, w.D_c, w.gamma
     p.n_species = len(w.species)
+    for s in range(MAX_SPECIES):
+        p.react_to[s] = -1
     for s, sp in enumerate(w.species):
         p.diam[s], p.D[s], p.chi[s] = sp.diameter, sp.D, sp.chi
         p.source[s], p.uptake[s] = sp.source, sp.uptake
+        p.react_to[s] = getattr(sp, "react_to", -1)
+        p.react_rate[s] = getattr(sp, "react_rate", 0.0)
+        p.react_rate_c[s] = getattr(sp, "react_rate_c", 0.0)
     ins = w.instances[inst]
     p.seed = ins.seed & (2**64 - 1)
     p.inst = ins.stream if getattr(ins, "stream", -1) >= 0 else inst
@@ -248,19 +256,31 @@ def pde(p: Params, c: np.ndarray, S_src: np.ndarray, S_upt: np.ndarray) -> np.nd
 
 
 def run(p: Params, X: np.ndarray, sp: np.ndarray, c: np.ndarray, step: int, n_steps: int,
-        ids: np.ndarray | None = None):
-    """Advance one instance by n_steps; returns (X, c, step) as new arrays."""
+        ids: np.ndarray | None = None, return_species: bool = False):
+    """Advance one instance by n_steps; returns (X, c, step[, species]) as new arrays."""
     X = _c(X, np.float64).copy()
     c = _c(c, np.float64).copy()
-    sp = _c(sp, np.uint8)
+    sp = _c(sp, np.uint8).copy()
     ids = np.arange(len(X), dtype=np.uint32) if ids is None else _c(ids, np.uint32)
     st = C.c_uint32(step)
     lib().orc_run(C.byref(p), len(X), _ptr(X), _ptr(sp), _ptr(ids), _ptr(c), C.byref(st), n_steps)
-    return X, c, st.value
+    return (X, c, st.value, sp) if return_species else (X, c, st.value)
 
 
-def step(p: Params, X, sp, c, step_no: int, ids=None):
-    return run(p, X, sp, c, step_no, 1, ids)
+def step(p: Params, X, sp, c, step_no: int, ids=None, return_species: bool = False):
+    return run(p, X, sp, c, step_no, 1, ids, return_species)
+
+
+def react(p: Params, X: np.ndarray, sp: np.ndarray, c: np.ndarray, step_no: int,
+          ids: np.ndarray | None = None) -> np.ndarray:
+    """Species after the type-switching draw of step `step_no` (eq. Chemo_reactions)."""
+    X = _c(X, np.float64)
+    sp = _c(sp, np.uint8)
+    c = _c(c, np.float64)
+    ids = np.arange(len(X), dtype=np.uint32) if ids is None else _c(ids, np.uint32)
+    out = np.empty(len(X), np.uint8)
+    lib().orc_react(C.byref(p), len(X), _ptr(X), _ptr(sp), _ptr(ids), _ptr(c), step_no, _ptr(out))
+    return out
 
 
 def density_loss(dim: int, L: float, X: np.ndarray, target: np.ndarray, hist_n: int = 64,
@@ -315,17 +335,20 @@ def loss_at(w, inputs: dict, theta, target: np.ndarray, n_steps: int, hist_n: in
     return tot
 
 
-def run_workload(w, inputs: dict, n_steps: int, mode: int = 1, step0: int = 0):
+def run_workload(w, inputs: dict, n_steps: int, mode: int = 1, step0: int = 0,
+                 return_species: bool = False):
     """Advance every instance of a workload from `inputs` (workloads.make_inputs)."""
-    xs, cs = [], []
+    xs, cs, ss = [], [], []
     off = 0
     G = w.grid_n ** w.dim
     for k, ins in enumerate(w.instances):
         n = ins.n_agents
         p = params(w, k, mode=mode)
-        X, c, _ = run(p, inputs["x0"][off:off + n], inputs["species0"][off:off + n],
-                      inputs["c0"][k * G:(k + 1) * G], step0, n_steps)
+        X, c, _, s = run(p, inputs["x0"][off:off + n], inputs["species0"][off:off + n],
+                         inputs["c0"][k * G:(k + 1) * G], step0, n_steps, return_species=True)
         xs.append(X)
         cs.append(c)
+        ss.append(s)
         off += n
-    return np.concatenate(xs, 0), np.concatenate(cs, 0)
+    out = (np.concatenate(xs, 0), np.concatenate(cs, 0))
+    return out + (np.concatenate(ss, 0),) if return_species else out

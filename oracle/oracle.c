@@ -37,6 +37,10 @@ typedef struct {
     int32_t mode;         /* 0: all-pairs neighbour search ; 1: cell list */
     double diam[ORC_MAX_SPECIES], D[ORC_MAX_SPECIES], chi[ORC_MAX_SPECIES];
     double source[ORC_MAX_SPECIES], uptake[ORC_MAX_SPECIES];
+    /* type switching (eq. Chemo_reactions): species s becomes react_to[s]
+     * at rate react_rate[s] + react_rate_c[s] * c(X); react_to < 0: none */
+    int32_t react_to[ORC_MAX_SPECIES];
+    double react_rate[ORC_MAX_SPECIES], react_rate_c[ORC_MAX_SPECIES];
     uint64_t seed;        /* Philox key = (lo32(seed), hi32(seed) ^ inst) */
     uint32_t inst;
     double chi_scale;     /* per-instance multiplier of chi */
@@ -591,17 +595,42 @@ void orc_drift(const orc_params *p, const double *c, int64_t n, const double *X,
 /* One time step of the hybrid model in the order of the listings of
  * Sect. 3 (Lie splitting): node gradient of c^n; drift chi grad c at X^n;
  * pair forces at X^n; Euler-Maruyama update (eq. sde_EM, with the drift of
- * eq. sde_beta for chemotactic species); boundary closure; deposit of the
- * new positions; PDE update of c (eq. pde_c); step counter + 1.
- * X, c are updated in place; `ids` are the stable agent ids. */
-void orc_step(const orc_params *p, int64_t n, double *X, const uint8_t *sp, const uint32_t *ids,
+ * eq. sde_beta for chemotactic species) with the species held at the start
+ * of the step; type switching; boundary closure; deposit of the new
+ * positions with the new types; PDE update of c (eq. pde_c); step + 1.
+ * X, sp, c are updated in place; `ids` are the stable agent ids. */
+/* Fixed-step type switching (Sect. 2.1 and the reaction listing of
+ * Sect. 3.4): during [t, t + dt) agent i of species s switches to
+ * react_to[s] iff zeta < (react_rate[s] + react_rate_c[s] c(X_i)) dt, with
+ * zeta the 24-bit uniform of word 0 of the agent's Philox block with
+ * counter word 3 = 1 (the switching stream), and c(X_i) the multilinear
+ * interpolation of c^n at X^n.  new_sp receives the species after the step. */
+void orc_react(const orc_params *p, int64_t n, const double *X, const uint8_t *sp,
+               const uint32_t *ids, const double *c, uint32_t step, uint8_t *new_sp) {
+    for (int64_t i = 0; i < n; ++i) {
+        int s = sp[i];
+        new_sp[i] = (uint8_t)s;
+        if (p->react_to[s] < 0) continue;
+        double rate = p->react_rate[s];
+        if (p->react_rate_c[s] != 0.0) rate += p->react_rate_c[s] * orc_interp_one(p, c, X + i * p->dim);
+        uint32_t ctr[4] = {step, ids[i], p->inst, 1u};
+        uint32_t key[2] = {(uint32_t)p->seed, (uint32_t)(p->seed >> 32) ^ p->inst};
+        uint32_t w[4];
+        orc_philox(ctr, key, w);
+        if (orc_uniform(w[0]) < rate * p->dt) new_sp[i] = (uint8_t)p->react_to[s];
+    }
+}
+
+void orc_step(const orc_params *p, int64_t n, double *X, uint8_t *sp, const uint32_t *ids,
               double *c, uint32_t *step) {
     const int dim = p->dim;
     const int64_t G = orc_nodes(p);
     double *F = (double *)malloc(sizeof(double) * (size_t)(n * dim > 0 ? n * dim : 1));
     double *drift = (double *)malloc(sizeof(double) * (size_t)(n * dim > 0 ? n * dim : 1));
+    uint8_t *nsp = (uint8_t *)malloc((size_t)(n > 0 ? n : 1));
     orc_forces(p, n, X, sp, F);
     orc_drift(p, c, n, X, sp, drift);
+    orc_react(p, n, X, sp, ids, c, *step, nsp);
 #pragma omp parallel for
     for (int64_t i = 0; i < n; ++i) {
         double xi[3];
@@ -612,6 +641,7 @@ void orc_step(const orc_params *p, int64_t n, double *X, const uint8_t *sp, cons
             X[i * dim + a] = orc_boundary(p, x);
         }
     }
+    memcpy(sp, nsp, (size_t)n);  /* the deposit sees the switched types */
     double *Ss = (double *)malloc(sizeof(double) * (size_t)G);
     double *Su = (double *)malloc(sizeof(double) * (size_t)G);
     orc_deposit(p, n, X, sp, Ss, Su);
@@ -621,9 +651,10 @@ void orc_step(const orc_params *p, int64_t n, double *X, const uint8_t *sp, cons
     free(Su);
     free(F);
     free(drift);
+    free(nsp);
 }
 
-void orc_run(const orc_params *p, int64_t n, double *X, const uint8_t *sp, const uint32_t *ids,
+void orc_run(const orc_params *p, int64_t n, double *X, uint8_t *sp, const uint32_t *ids,
              double *c, uint32_t *step, int n_steps) {
     for (int s = 0; s < n_steps; ++s) orc_step(p, n, X, sp, ids, c, step);
 }

@@ -40,6 +40,9 @@ class Species:
     chi: float        # chemotactic sensitivity (eq. sde_beta); 0 = no drift
     source: float     # secretion rate k_alpha (eq. pde_c)
     uptake: float     # consumption rate k_beta (eq. pde_c)
+    react_to: int = -1        # type this species switches to (eq. Chemo_reactions); -1 none
+    react_rate: float = 0.0   # switching rate: react_rate + react_rate_c * c(X)
+    react_rate_c: float = 0.0
 
 
 @dataclass(frozen=True)
