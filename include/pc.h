@@ -64,7 +64,9 @@ enum {
 enum {
     PC_WARN_DT_RULE = 1u,      /* sqrt(2 (D_i + D_j) dt) >= contact distance (Sect. 2.2) */
     PC_WARN_POSITIVITY = 2u,   /* dt' (gamma + uptake density) >= 1 at some node        */
-    PC_WARN_CLAMPED = 4u       /* a position was clamped into the domain                */
+    PC_WARN_CLAMPED = 4u,      /* a position was clamped into the domain                */
+    PC_WARN_REACTION = 8u      /* a switching probability rate dt reached 1 (Sect. 2.1
+                                  needs rate dt << 1; the switch was then certain)     */
 };
 
 #define PC_MAX_SPECIES 8
@@ -93,13 +95,27 @@ typedef struct {
     int32_t reserved;
 } pc_config;
 
-/* One agent species (the paper's cell type). */
+/* One agent species (the paper's cell type).
+ *
+ * Type switching (eq. Chemo_reactions, simulated with the fixed-step rule of
+ * Sect. 2.1): an agent of this species switches to species react_to during
+ * a step with probability min(1, (react_rate + react_rate_c c(X)) dt), where
+ * c(X) is the multilinear interpolation of the field at the start of the
+ * step at the agent's position at the start of the step.  The draw is word
+ * 0 of the agent's Philox block with counter (step, id, stream, 1).  The
+ * switch takes effect for the deposit of the same step; drift and noise of
+ * the step use the species held at its start.  A species switches only if
+ * react_to >= 0 and a rate is > 0, so a zero-filled struct has no reaction. */
 typedef struct {
     double diameter;  /* contact distance of a pair = mean of the two diameters */
     double D;         /* diffusion coefficient                                  */
     double chi;       /* chemotactic sensitivity (0: no drift)                  */
     double source;    /* secretion rate k_alpha into the chemical               */
     double uptake;    /* consumption rate k_beta (per unit concentration)       */
+    int32_t react_to;     /* species switched to (0..n_species-1, not itself)   */
+    int32_t reserved;
+    double react_rate;    /* constant switching rate (>= 0)                     */
+    double react_rate_c;  /* switching rate per unit concentration (>= 0)       */
 } pc_species_t;
 
 /* One independent instance. */
@@ -157,8 +173,17 @@ int pc_species(pc_sim *sim, uint8_t *out_dev);
 int pc_get_state(pc_sim *sim, float *x_dev, float *c_dev, uint32_t *step);
 
 /* Restore a checkpoint; the noise of later steps is that of the restored
- * step counter (Philox is keyed by step, id and instance). */
+ * step counter (Philox is keyed by step, id and instance).  Agents take the
+ * species last given to pc_create or pc_set_species (switches made by steps
+ * since then are undone); x_dev or c_dev may be NULL to keep that part. */
 int pc_set_state(pc_sim *sim, const float *x_dev, const float *c_dev, uint32_t step);
+
+/* Set the species of every agent (uint8, sum(N), id order, each below
+ * n_species) and make them the species pc_set_state restores; positions,
+ * field and step counter are kept.  Values >= n_species are replaced by 0
+ * and reported as PC_EINVAL by the next pc_sync.  Stream-ordered; the
+ * caller's array may be reused once the stream has passed this point. */
+int pc_set_species(pc_sim *sim, const uint8_t *species_dev);
 
 /* Wait for the stream; report PC_ENONFINITE if a non-finite value reached
  * the state since the last call, else PC_OK. */
@@ -222,8 +247,9 @@ int pc_debug_forces(pc_sim *sim, float *F_dev);
  * The segment is recomputed forward inside the call (checkpointing); the
  * state is restored to what it was, and the call synchronises the stream.
  * Needs a workspace of pc_workspace_bytes_adjoint(..., seg_steps) bytes with
- * 1 <= n_steps <= seg_steps.  Errors: PC_ENOTSUP without segment storage,
- * PC_EINVAL for bad arguments, PC_EHIP. */
+ * 1 <= n_steps <= seg_steps.  Errors: PC_ENOTSUP without segment storage
+ * or when a species has a type switch (a discrete event), PC_EINVAL for bad
+ * arguments, PC_EHIP. */
 size_t pc_workspace_bytes_adjoint(const pc_config *cfg, const pc_species_t *species,
                                   int n_species, const pc_instance *inst, int n_inst,
                                   int seg_steps);

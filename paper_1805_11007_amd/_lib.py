@@ -11,12 +11,12 @@ from pathlib import Path
 LIB_PATH = Path(__file__).resolve().parent / "libpc.so"
 
 PC_OK, PC_EINVAL, PC_EUNSTABLE, PC_ENOSPACE, PC_EHIP, PC_ENONFINITE, PC_ENOTSUP = 0, -1, -2, -3, -4, -5, -6
-PC_WARN_DT_RULE, PC_WARN_POSITIVITY, PC_WARN_CLAMPED = 1, 2, 4
+PC_WARN_DT_RULE, PC_WARN_POSITIVITY, PC_WARN_CLAMPED, PC_WARN_REACTION = 1, 2, 4, 8
 MAX_SPECIES = 8
 
 EXPORTS = (
     "pc_workspace_bytes", "pc_workspace_bytes_adjoint", "pc_create", "pc_step", "pc_use_graph",
-    "pc_positions", "pc_field", "pc_species", "pc_get_state", "pc_set_state", "pc_sync",
+    "pc_positions", "pc_field", "pc_species", "pc_get_state", "pc_set_state", "pc_set_species", "pc_sync",
     "pc_warnings", "pc_info", "pc_destroy", "pc_strerror", "pc_last_error",
     "pc_debug_neighbours", "pc_debug_forces", "pc_adjoint_segment", "pc_profile_steps",
     "pc_density_loss_work_bytes", "pc_density_loss", "pc_density_hist",
@@ -34,7 +34,8 @@ class PcConfig(C.Structure):
 
 class PcSpecies(C.Structure):
     _fields_ = [("diameter", C.c_double), ("D", C.c_double), ("chi", C.c_double),
-                ("source", C.c_double), ("uptake", C.c_double)]
+                ("source", C.c_double), ("uptake", C.c_double), ("react_to", C.c_int32),
+                ("reserved", C.c_int32), ("react_rate", C.c_double), ("react_rate_c", C.c_double)]
 
 
 class PcInstance(C.Structure):
@@ -81,6 +82,7 @@ def load() -> C.CDLL:
         "pc_species": ([vp, vp], i32),
         "pc_get_state": ([vp, vp, vp, u32p], i32),
         "pc_set_state": ([vp, vp, vp, C.c_uint32], i32),
+        "pc_set_species": ([vp, vp], i32),
         "pc_sync": ([vp], i32),
         "pc_warnings": ([vp, u32p], i32),
         "pc_info": ([vp, C.POINTER(PcInfo)], i32),

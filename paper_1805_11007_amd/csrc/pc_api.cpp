@@ -3,6 +3,7 @@
 // checkpoint / debug entry points.  Device work is enqueued on the caller's
 // stream; the library allocates no device memory.
 #include <math.h>
+#include <cmath>
 #include <string.h>
 
 #include <new>
@@ -36,9 +37,14 @@ struct Derived {
     int nb, stencil;
     double bin_side, cutoff, h;
     int64_t bins_per_inst, bins_total, nodes_per_inst, nodes_total;
-    int n_sub, block, has_uptake;
+    int n_sub, block, has_uptake, has_react;
     uint32_t warn;
 };
+
+// A species switches when react_to >= 0 and one of its rates is > 0.
+static bool reacts(const pc_species_t &s) {
+    return s.react_to >= 0 && (s.react_rate > 0 || s.react_rate_c > 0);
+}
 
 struct Layout {
     size_t P[3], I[3], bin, rank, count, start, tile_sum, c[2], S_src, S_upt, inst, species_id,
@@ -73,11 +79,20 @@ int derive(const pc_config *cfg, const pc_species_t *sp, int ns, const pc_instan
     d.ni = ni;
     d.cutoff = 0;
     d.has_uptake = 0;
+    d.has_react = 0;
     for (int s = 0; s < ns; ++s) {
         if (!(sp[s].diameter > 0)) return fail(PC_EINVAL, "diameter must be > 0");
         if (!(sp[s].D >= 0)) return fail(PC_EINVAL, "D must be >= 0");
         if (!(sp[s].source >= 0) || !(sp[s].uptake >= 0))
             return fail(PC_EINVAL, "source and uptake must be >= 0");
+        if (!(sp[s].react_rate >= 0) || !(sp[s].react_rate_c >= 0) ||
+            !std::isfinite(sp[s].react_rate) || !std::isfinite(sp[s].react_rate_c))
+            return fail(PC_EINVAL, "switching rates must be finite and >= 0");
+        if (reacts(sp[s])) {
+            if (sp[s].react_to >= ns) return fail(PC_EINVAL, "react_to >= n_species");
+            if (sp[s].react_to == s) return fail(PC_EINVAL, "a species cannot switch to itself");
+            d.has_react = 1;
+        }
         if (sp[s].diameter > d.cutoff) d.cutoff = sp[s].diameter;
         if (sp[s].uptake > 0) d.has_uptake = 1;
     }
@@ -250,7 +265,17 @@ static void fill_params(pc_sim *s) {
         p.chi[a] = (float)s->species[a].chi;
         p.src_fx[a] = (float)(s->species[a].source * 4294967296.0);
         p.upt_fx[a] = (float)(s->species[a].uptake * 4294967296.0);
+        // probability threshold rate*dt rounded up to float: for a float
+        // uniform u, u < float threshold exactly when u < the double product
+        const pc_species_t &sa = s->species[a];
+        p.react_to[a] = reacts(sa) ? sa.react_to : -1;
+        const double pr = sa.react_rate * c.dt;
+        float f = (float)pr;
+        if ((double)f < pr) f = std::nextafter(f, INFINITY);
+        p.react_p[a] = reacts(sa) ? f : 0.0f;
+        p.react_cdt[a] = reacts(sa) ? (float)(sa.react_rate_c * c.dt) : 0.0f;
     }
+    p.has_react = d.has_react;
     PdeParams &q = s->pp;
     memset(&q, 0, sizeof(q));
     q.dim = d.dim;
@@ -640,6 +665,17 @@ int pc_set_state(pc_sim *s, const float *x_dev, const float *c_dev, uint32_t ste
     return PC_OK;
 }
 
+int pc_set_species(pc_sim *s, const uint8_t *species_dev) {
+    if (!s || !species_dev) return fail(PC_EINVAL, "null argument");
+    HIP_OK(hipMemcpyAsync(s->b.species_id, species_dev, (size_t)s->d.n_total,
+                          hipMemcpyDeviceToDevice, s->stream));
+    launch_apply_species(s->sp, s->b, 0, s->b.species_id, s->stream);
+    // a sorted copy made before this call holds the old species
+    s->sorted = 0;
+    HIP_OK(hipGetLastError());
+    return PC_OK;
+}
+
 static int read_flags(pc_sim *s) {
     HIP_OK(hipStreamSynchronize(s->stream));
     uint32_t fl = 0;
@@ -647,6 +683,7 @@ static int read_flags(pc_sim *s) {
     s->flags_host |= fl;
     if (fl & FLAG_WARN_POSITIVITY) s->warn_bits |= PC_WARN_POSITIVITY;
     if (fl & FLAG_WARN_CLAMPED) s->warn_bits |= PC_WARN_CLAMPED;
+    if (fl & FLAG_WARN_REACTION) s->warn_bits |= PC_WARN_REACTION;
     return PC_OK;
 }
 
@@ -659,6 +696,12 @@ int pc_sync(pc_sim *s) {
         uint32_t zero = 0;
         HIP_OK(hipMemcpy(s->b.flags, &zero, 4, hipMemcpyHostToDevice));
         return fail(PC_ENONFINITE, "a non-finite value reached the state");
+    }
+    if (s->flags_host & FLAG_BAD_SPECIES) {
+        s->flags_host &= ~FLAG_BAD_SPECIES;
+        uint32_t zero = 0;
+        HIP_OK(hipMemcpy(s->b.flags, &zero, 4, hipMemcpyHostToDevice));
+        return fail(PC_EINVAL, "a species index >= n_species was replaced by 0");
     }
     return PC_OK;
 }
@@ -743,6 +786,7 @@ int pc_adjoint_segment(pc_sim *s, const float *lamX_in_dev, const float *lamC_in
     if (s->seg_steps < 1) return fail(PC_ENOTSUP, "workspace holds no adjoint segment");
     if (n_steps < 1 || n_steps > s->seg_steps)
         return fail(PC_EINVAL, "n_steps must be in [1, segment capacity]");
+    if (s->d.has_react) return fail(PC_ENOTSUP, "reverse mode over type switches is not built");
     hipStream_t st = s->stream;
     const Buffers &b = s->b;
     const size_t XD = (size_t)s->d.n_total * s->d.dim;

@@ -425,6 +425,35 @@ __device__ __forceinline__ int idx_p2(const StepParams &p, int i0) {
     return p.periodic ? q - p.grid_n : p.grid_n - 2;
 }
 
+// Multilinear interpolation of the node values c at x.
+template <int DIM>
+__device__ __forceinline__ float value_interp(const StepParams &p, const float *__restrict__ c,
+                                              float4 x) {
+    const Cell cx = cell_of(p, x.x), cy = cell_of(p, x.y);
+    const int n = p.grid_n;
+    const float wx[2] = {1.0f - cx.t, cx.t}, wy[2] = {1.0f - cy.t, cy.t};
+    const int X2[2] = {cx.i0, cx.i1}, Y2[2] = {cy.i0 * n, cy.i1 * n};
+    float v = 0.f;
+    if (DIM == 2) {
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int a = 0; a < 2; ++a) v = fmaf(wx[a] * wy[b], c[Y2[b] + X2[a]], v);
+    } else {
+        const Cell cz = cell_of(p, x.z);
+        const float wz[2] = {1.0f - cz.t, cz.t};
+        const int Z2[2] = {cz.i0 * n * n, cz.i1 * n * n};
+#pragma unroll
+        for (int e = 0; e < 2; ++e)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int a = 0; a < 2; ++a)
+                    v = fmaf(wx[a] * wy[b] * wz[e], c[Z2[e] + Y2[b] + X2[a]], v);
+    }
+    return v;
+}
+
 // Multilinear interpolation at x of the centred-difference gradient of c,
 // computed on the fly from the 4^dim-minus-corners stencil of c around the
 // agent's cell (the node gradient field itself is never stored).

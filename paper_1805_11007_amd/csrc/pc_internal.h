@@ -44,6 +44,10 @@ struct StepParams {
     float chi[kMaxSpecies];
     float src_fx[kMaxSpecies];              // source_s * 2^32
     float upt_fx[kMaxSpecies];              // uptake_s * 2^32
+    int32_t has_react;
+    int32_t react_to[kMaxSpecies];          // -1: no switch
+    float react_p[kMaxSpecies];             // react_rate dt rounded up to float
+    float react_cdt[kMaxSpecies];           // react_rate_c dt
 };
 
 struct PdeParams {
@@ -61,6 +65,7 @@ enum : uint32_t {
     FLAG_BAD_SPECIES = 1u << 1,
     FLAG_WARN_POSITIVITY = 1u << 8,
     FLAG_WARN_CLAMPED = 1u << 9,
+    FLAG_WARN_REACTION = 1u << 10,
 };
 
 // Device buffers carved from the caller's workspace.
@@ -128,6 +133,8 @@ void launch_zero_u32(uint32_t *d, int64_t n, hipStream_t s);
 void launch_positions(const StepParams &p, const Buffers &b, int src, float *out,
                       hipStream_t s);
 void launch_species(const StepParams &p, const Buffers &b, int src, uint8_t *out, hipStream_t s);
+void launch_apply_species(const StepParams &p, const Buffers &b, int src, const uint8_t *sp,
+                          hipStream_t s);
 void launch_debug_pairs(const StepParams &p, const Buffers &b, int src, uint32_t *count,
                         unsigned long long *hash, float *F, int block, hipStream_t s);
 void launch_pde_ptr(const PdeParams &q, const float *cin, float *cout, unsigned long long *Ssrc,

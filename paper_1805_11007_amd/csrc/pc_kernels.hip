@@ -241,6 +241,21 @@ k_update(StepParams p, const InstInfo *__restrict__ inst, const float4 *__restri
     xn.y = boundary(p, pi.y + p.dt * (F[1] + drift[1]) + amp * xi[1], flag);
     xn.z = DIM == 3 ? boundary(p, pi.z + p.dt * (F[2] + drift[2]) + amp * xi[2], flag) : 0.0f;
     xn.w = pi.w;
+    if (p.has_react) {
+        // type switch (eq. Chemo_reactions, fixed-step rule): one more Philox
+        // block on counter word 3 = 1; the rate reads c^n at X^n
+        const int to = NS == 1 ? p.react_to[0] : (NS == 2 ? (si ? p.react_to[1] : p.react_to[0])
+                                                           : p.react_to[si]);
+        if (to >= 0) {
+            float prob = sel<NS>(p.react_p, p.react_p, si);
+            const float rc = sel<NS>(p.react_cdt, p.react_cdt, si);
+            if (rc != 0.0f) prob = fmaf(rc, value_interp<DIM>(p, c + ii.node_base, pi), prob);
+            const U4 wr = philox4x32_10(*stepc, id, ii.stream, 1u, ii.key0, ii.key1);
+            if (uniform24(wr.v[0]) < prob)
+                xn.w = __uint_as_float((__float_as_uint(pi.w) & ~0xffu) | (uint32_t)to);
+            if (prob >= 1.0f) flag |= FLAG_WARN_REACTION;
+        }
+    }
     if (!(isfinite(xn.x) && isfinite(xn.y) && isfinite(xn.z))) flag |= FLAG_NONFINITE;
     Pout[i] = xn;
     Iout[i] = id;
@@ -456,6 +471,22 @@ __global__ void k_species(StepParams p, const InstInfo *__restrict__ inst,
     out[inst[inst_of(x.w)].agent_base + I[j]] = (uint8_t)species_of(x.w);
 }
 
+// Species of every agent from an id-ordered array (pc_set_species).
+__global__ void k_apply_species(StepParams p, const InstInfo *__restrict__ inst,
+                                float4 *__restrict__ P, const uint32_t *__restrict__ I,
+                                const uint8_t *__restrict__ sp, uint32_t *__restrict__ flags) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= p.n_total) return;
+    const float4 x = P[j];
+    const uint32_t k = inst_of(x.w);
+    uint32_t s = sp[inst[k].agent_base + I[j]];
+    if (s >= (uint32_t)p.n_species) {
+        atomicOr(flags, FLAG_BAD_SPECIES);
+        s = 0;
+    }
+    P[j].w = __uint_as_float((k << 8) | s);
+}
+
 template <int DIM, int NS, int STENCIL>
 __global__ void __launch_bounds__(1024)
 k_debug_pairs(StepParams p, const InstInfo *__restrict__ inst, const float4 *__restrict__ Ps,
@@ -649,6 +680,12 @@ void launch_positions(const StepParams &p, const Buffers &b, int src, float *out
 void launch_species(const StepParams &p, const Buffers &b, int src, uint8_t *out, hipStream_t s) {
     hipLaunchKernelGGL(k_species, dim3(grid_for(p.n_total, 256)), dim3(256), 0, s, p, b.inst,
                        b.P[src], b.I[src], out);
+}
+
+void launch_apply_species(const StepParams &p, const Buffers &b, int src, const uint8_t *sp,
+                          hipStream_t s) {
+    hipLaunchKernelGGL(k_apply_species, dim3(grid_for(p.n_total, 256)), dim3(256), 0, s, p,
+                       b.inst, b.P[src], b.I[src], sp, b.flags);
 }
 
 void launch_set_u32(uint32_t *ptr, uint32_t v, hipStream_t s) {

@@ -24,6 +24,9 @@ class SpeciesSpec:
     chi: float = 0.0
     source: float = 0.0
     uptake: float = 0.0
+    react_to: int = -1        # species switched to (eq. Chemo_reactions); -1: none
+    react_rate: float = 0.0   # switching rate react_rate + react_rate_c * c(X)
+    react_rate_c: float = 0.0
 
 
 @dataclass
@@ -54,7 +57,9 @@ class ModelSpec:
     @classmethod
     def from_workload(cls, w, **over) -> "ModelSpec":
         """Build from any object with the attributes of a workload description."""
-        sp = [SpeciesSpec(s.diameter, s.D, s.chi, s.source, s.uptake) for s in w.species]
+        sp = [SpeciesSpec(s.diameter, s.D, s.chi, s.source, s.uptake,
+                          getattr(s, "react_to", -1), getattr(s, "react_rate", 0.0),
+                          getattr(s, "react_rate_c", 0.0)) for s in w.species]
         ins = [InstanceSpec(i.n_agents, i.seed, i.chi_scale, getattr(i, 'stream', -1))
                for i in w.instances]
         kw = dict(dim=w.dim, periodic=w.periodic, L=w.L, grid_n=w.grid_n, dt=w.dt, k=w.k,
@@ -83,6 +88,8 @@ class ModelSpec:
         for k, s in enumerate(self.species):
             sp[k].diameter, sp[k].D, sp[k].chi = s.diameter, s.D, s.chi
             sp[k].source, sp[k].uptake = s.source, s.uptake
+            sp[k].react_to = int(s.react_to)
+            sp[k].react_rate, sp[k].react_rate_c = float(s.react_rate), float(s.react_rate_c)
         ni = len(self.instances)
         ins = (LB.PcInstance * max(ni, 1))()
         for k, i in enumerate(self.instances):
@@ -194,6 +201,12 @@ class Sim:
         c = c.to(self.device, torch.float32).contiguous()
         LB.check(self.L.pc_set_state(self.h, _ptr(x), _ptr(c), int(step)))
         self._keep = (x, c)  # inputs must live until the stream has read them
+
+    def set_species(self, species: torch.Tensor) -> None:
+        """Species of every agent (id order); also what set_state restores."""
+        species = species.to(self.device, torch.uint8).contiguous().reshape(self.spec.n_total)
+        LB.check(self.L.pc_set_species(self.h, _ptr(species)))
+        self._keep_sp = species  # must live until the stream has read it
 
     def sync(self) -> None:
         LB.check(self.L.pc_sync(self.h))
