@@ -91,6 +91,8 @@ def lib():
             "orc_density_loss": ([C.c_int, C.c_double, i64, vp, C.c_int, C.c_double, vp, vp],
                                  C.c_double),
             "orc_density_hist": ([C.c_int, C.c_double, i64, vp, C.c_int, C.c_double, vp], None),
+            "orc_species_hist": ([C.c_int, C.c_double, i64, vp, vp, C.c_int, C.c_int, vp, vp],
+                                 None),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -352,3 +354,20 @@ def run_workload(w, inputs: dict, n_steps: int, mode: int = 1, step0: int = 0,
         off += n
     out = (np.concatenate(xs, 0), np.concatenate(cs, 0))
     return out + (np.concatenate(ss, 0),) if return_species else out
+
+
+def species_hist(dim: int, L: float, X: np.ndarray, sp: np.ndarray, n_species: int, hist_n: int):
+    """Per-species position histograms over all realisations (float32 positions)
+    and the species totals: (counts[n_species, hist_n^dim], totals[n_species])."""
+    X = _c(X, np.float32)
+    sp = _c(sp, np.uint8)
+    counts = np.empty(n_species * hist_n ** dim, np.uint32)
+    totals = np.empty(n_species, np.uint32)
+    lib().orc_species_hist(dim, L, len(sp), _ptr(X), _ptr(sp), n_species, hist_n, _ptr(counts),
+                           _ptr(totals))
+    return counts.reshape(n_species, -1), totals
+
+
+def field_mean(c: np.ndarray, n_inst: int) -> np.ndarray:
+    """Mean of the chemical over realisations, node by node (FP64)."""
+    return np.asarray(c, np.float64).reshape(n_inst, -1).mean(0)

@@ -822,3 +822,32 @@ void orc_density_hist(int dim, double L, int64_t n, const double *X, int m, doub
     free(taps);
     free(tmp);
 }
+
+/* Ensemble statistics in the style of the experiment of Sect. 4 (Fig. 1):
+ * per-species position histograms over all realisations, hist_n bins per
+ * axis on [0, L].  The bin of a coordinate is floor(x * s) clamped to
+ * [0, hist_n - 1] with s = float32(hist_n / L), formed in float32 arithmetic
+ * on float32 positions (an integer decided by floating point is decided in
+ * the precision of the positions).  counts: n_species x hist_n^dim (x
+ * fastest); totals: agents of each species. */
+void orc_species_hist(int dim, double L, int64_t n, const float *X, const uint8_t *sp,
+                      int n_species, int hist_n, uint32_t *counts, uint32_t *totals) {
+    int64_t H = 1;
+    for (int a = 0; a < dim; ++a) H *= hist_n;
+    memset(counts, 0, sizeof(uint32_t) * (size_t)(H * n_species));
+    memset(totals, 0, sizeof(uint32_t) * (size_t)n_species);
+    const float s = (float)((double)hist_n / L);
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t idx = 0, stride = 1;
+        for (int a = 0; a < dim; ++a) {
+            const float v = X[i * dim + a] * s;
+            int b = (int)floorf(v);
+            if (b < 0) b = 0;
+            if (b > hist_n - 1) b = hist_n - 1;
+            idx += b * stride;
+            stride *= hist_n;
+        }
+        counts[(int64_t)sp[i] * H + idx] += 1;
+        totals[sp[i]] += 1;
+    }
+}

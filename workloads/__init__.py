@@ -14,6 +14,9 @@ workloads below stand in for them:
 * ``config(3)``  3D periodic, 1,000,000 agents in 8 Gaussian blobs, 128^3 grid
 * ``config(4)``  256 independent 2D instances of uneven size, 128^2 grids
 * ``config(5)``  2D periodic, 50,000 agents (producers / consumers), 256^2 grid
+* ``config(6)``  2000 realisations of the experiment of Sect. 4 (Fig. 1):
+  100 producers that switch to consumers plus 100 consumers each, reflecting
+  walls, 52^2 grid
 
 Initial conditions follow one recipe: a numpy ``PCG64(1000 + cfg)``
 generator draws everything in float64, which is then rounded to float32
@@ -69,7 +72,7 @@ class Workload:
     species: Tuple[Species, ...]
     instances: Tuple[Instance, ...]
     pde_substeps: int = 0    # 0 = choose the smallest stable count
-    layout: str = "uniform"  # "uniform" | "blobs"
+    layout: str = "uniform"  # "uniform" | "blobs" | "centre_uniform"
     species_rule: str = "single"  # "single" | "halves" (id >= N/2 -> species 1)
     c0: str = "sin"          # "sin": prod sin(2 pi x) + 1 ; "cos": prod cos(pi x) + 1
     gen_seed: int = 1000
@@ -115,7 +118,28 @@ def config(n: int) -> Workload:
                         _one_species_cfg1(), inst, gen_seed=1004)
     if n == 5:
         return config5()
+    if n == 6:
+        return config6()
     raise ValueError(f"no workload {n}")
+
+
+def config6(n_real: int = 2000, chi: float = 10.0, seed: int = 1006) -> Workload:
+    """The experiment of Sect. 4 with the parameters of its Fig. 1 caption:
+    N_alpha(0) = N_beta(0) = 100, diameter 0.02, r_alpha = 10, r_beta = 0,
+    D_alpha = 0.1, D_beta = 1, D_c = 1, k_alpha = 0.1, k_beta = 0.03,
+    dt = (0.23 * 0.02)^2 / (4 D_beta), N_c = 52, T_f = 0.05.  The caption
+    leaves chi, gamma, the repulsion strength and the initial profiles open:
+    chi = 10, gamma = 0, k = 1e4 (k dt = 0.05), alpha agents from a Gaussian
+    of width 0.1 at the centre, beta agents uniform, c0 = 0."""
+    dt = (0.23 * 0.02) ** 2 / 4.0
+    sp = (Species(0.02, 0.1, 0.0, 0.1, 0.0, react_to=1, react_rate=10.0),
+          Species(0.02, 1.0, chi, 0.0, 0.03))
+    rng = np.random.Generator(np.random.PCG64(seed))
+    seeds = rng.integers(0, 2**63, n_real, dtype=np.int64)
+    inst = tuple(Instance(200, int(s)) for s in seeds)
+    return Workload("cfg6_2d_walls_fig1_2000x200", 2, False, 1.0, 52, dt, 1e4, 1.0, 0.0,
+                    int(round(0.05 / dt)), sp, inst, layout="centre_uniform",
+                    species_rule="halves", c0="zero", gen_seed=seed)
 
 
 def config5(chi: float = 1.0, k: float = 100.0, D: float = 1.0, seed: int = 1005) -> Workload:
@@ -126,7 +150,7 @@ def config5(chi: float = 1.0, k: float = 100.0, D: float = 1.0, seed: int = 1005
                     gen_seed=1005)
 
 
-CONFIGS = (1, 2, 3, 4, 5)
+CONFIGS = (1, 2, 3, 4, 5, 6)
 
 
 def scaled(w: Workload, n_agents: int | Sequence[int] | None = None,
@@ -178,6 +202,13 @@ def _positions(w: Workload, n: int, rng: np.random.Generator) -> np.ndarray:
         z = rng.standard_normal(size=(n, d))
         blob = np.arange(n) % 8
         x = np.mod(centres[blob] + 0.05 * w.L * z, w.L)
+    elif w.layout == "centre_uniform":
+        # first half (species 0 under the "halves" rule): Gaussian of width
+        # 0.1 L at the centre, clipped to the box; second half uniform
+        h = n // 2
+        x = np.empty((n, d))
+        x[:h] = np.clip(0.5 * w.L + 0.1 * w.L * rng.standard_normal(size=(h, d)), 0.0, w.L)
+        x[h:] = rng.uniform(0.0, w.L, size=(n - h, d))
     else:
         raise ValueError(w.layout)
     return _f32_in_box(x, w)
