@@ -144,6 +144,83 @@ def ensemble_leg(steps: int = 500, plain_steps: int = 50) -> dict:
             "tuned": {"bin_size": spec.bin_size, "block": spec.block}}
 
 
+def fig1_leg(hist_n: int = 52) -> dict:
+    """The experiment of Sect. 4 (Fig. 1): 2000 realisations of 100 producers
+    that switch to consumers at rate 10 plus 100 consumers, stepped to
+    T_f = 0.05 as one batch with HIP-graph replay, with the ensemble
+    statistics (per-species hist_n^2 histograms, mean field) taken at
+    t = 0, T/3, 2T/3 and T inside the timed region."""
+    import math
+    import torch
+    import workloads as W
+    from paper_1805_11007_amd import ModelSpec, Sim
+    w = W.config(6)
+    inp = W.make_inputs(w)
+    x0, s0, c0 = (torch.from_numpy(inp[k]).cuda() for k in ("x0", "species0", "c0"))
+    sim = Sim(ModelSpec.from_workload(w), x0, s0, c0)
+    sim.use_graph(True)
+    sim.step(4)
+    sim.set_state(x0, c0, 0)
+    marks = [0, round(w.steps / 3), round(2 * w.steps / 3), w.steps]
+    snaps = []
+
+    def run():
+        snaps.clear()
+        snaps.append(sim.ensemble_stats(hist_n))
+        for a, b in zip(marks, marks[1:]):
+            sim.step(b - a)
+            snaps.append(sim.ensemble_stats(hist_n))
+
+    ms = _timed(run)
+    sim.sync()
+    tot = [s[1].cpu().tolist() for s in snaps]
+    sim.set_state(x0, c0, 0)
+    prof = sim.profile_steps(300)
+    stats_ms = _timed(lambda: [sim.ensemble_stats(hist_n) for _ in range(20)]) / 20
+    sim.close()
+    r_dt = w.species[0].react_rate * w.dt
+    n_a0 = tot[0][0]
+    return {"workload": w.name, "realisations": w.n_inst, "agents_total": w.n_total,
+            "steps": w.steps, "T_f": w.steps * w.dt, "wall_s": ms / 1e3,
+            "ms_per_step": ms / w.steps,
+            "particle_steps_per_s": w.n_total * w.steps / (ms / 1e3),
+            "stats_call_ms": stats_ms, "stage_ms": prof,
+            "alpha_beta_totals_at_marks": tot,
+            "alpha_fraction_T": tot[-1][0] / n_a0,
+            "alpha_fraction_T_expected": (1 - r_dt) ** w.steps,
+            "alpha_fraction_T_sd": math.sqrt((1 - r_dt) ** w.steps *
+                                             (1 - (1 - r_dt) ** w.steps) / n_a0)}
+
+
+def reaction_overhead_leg(steps: int = 500) -> dict:
+    """Step time of the 100k-agent two-species walls workload without and with
+    type switching (0 -> 1 at rate 1e4, 1 -> 0 at 5e3 c), graph replay."""
+    import dataclasses
+    import torch
+    import workloads as W
+    from paper_1805_11007_amd import ModelSpec, Sim
+    w = W.config(2)
+    inp = W.make_inputs(w)
+    x0, s0, c0 = (torch.from_numpy(inp[k]).cuda() for k in ("x0", "species0", "c0"))
+    a, b = w.species
+    wr = dataclasses.replace(w, species=(dataclasses.replace(a, react_to=1, react_rate=1e4),
+                                         dataclasses.replace(b, react_to=0, react_rate_c=5e3)))
+    out = {}
+    for name, ww in (("plain", w), ("switching", wr)):
+        sim = Sim(ModelSpec.from_workload(ww), x0, s0, c0)
+        sim.use_graph(True)
+        sim.step(4)
+        sim.set_state(x0, c0, 0)
+        out[name + "_ms_per_step"] = _timed(lambda: sim.step(steps)) / steps
+        sim.sync()
+        sim.set_state(x0, c0, 0)
+        out[name + "_update_ms"] = sim.profile_steps(steps)["update"]
+        sim.close()
+    out["workload"] = w.name
+    out["overhead"] = out["switching_ms_per_step"] / out["plain_ms_per_step"] - 1
+    return out
+
+
 def adjoint_leg(steps: int = 200, K: int = 20) -> dict:
     """Forward with checkpoints every K steps plus the reverse sweep (which
     recomputes each segment) on the 50k-agent differentiation workload, vs
@@ -188,6 +265,10 @@ def adjoint_leg(steps: int = 200, K: int = 20) -> dict:
             "grad_theta": theta.grad.tolist()}
 
 
+LEGS = {"ensemble": lambda: ensemble_leg(), "fig1": lambda: fig1_leg(),
+        "switching": lambda: reaction_overhead_leg(), "fwd_bwd": lambda: adjoint_leg()}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -204,6 +285,8 @@ def main() -> int:
     ap.add_argument("--deterministic", action="store_true")
     ap.add_argument("--bin-size", type=float, default=0.0)
     ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--leg", choices=sorted(LEGS), default=None,
+                    help="run only this extra leg and print its JSON line")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -212,6 +295,10 @@ def main() -> int:
 
     import numpy as np
     import torch
+
+    if args.leg:
+        print(json.dumps({args.leg: LEGS[args.leg]()}), flush=True)
+        return 0
 
     if args.copy_calibration:
         a = torch.ones(64 * 1024 * 1024, device="cuda")
@@ -318,6 +405,12 @@ def main() -> int:
         print("[bench] ensemble leg", file=sys.stderr, flush=True)
         res["ensemble"] = ensemble_leg()
         print(f"[bench] ensemble: {json.dumps(res['ensemble'])}", file=sys.stderr, flush=True)
+        print("[bench] Fig. 1 ensemble leg", file=sys.stderr, flush=True)
+        res["fig1"] = fig1_leg()
+        print(f"[bench] fig1: {json.dumps(res['fig1'])}", file=sys.stderr, flush=True)
+        print("[bench] switching overhead leg", file=sys.stderr, flush=True)
+        res["switching"] = reaction_overhead_leg()
+        print(f"[bench] switching: {json.dumps(res['switching'])}", file=sys.stderr, flush=True)
         print("[bench] forward+backward leg", file=sys.stderr, flush=True)
         res["fwd_bwd"] = adjoint_leg()
         print(f"[bench] fwd_bwd: {json.dumps(res['fwd_bwd'])}", file=sys.stderr, flush=True)

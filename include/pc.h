@@ -92,7 +92,13 @@ typedef struct {
     int32_t block;          /* 0: automatic; else work-group size of the agent kernels
                                (64, 128, 256, 512 or 1024)                              */
     int32_t bin_order;      /* 0: row-major bins (x fastest); 1: 2x2(x2) brick order     */
-    int32_t reserved;
+    int32_t deposit_mode;   /* 0: automatic; 1: contributions summed per work-group in
+                               LDS before the device atomics; 2: device atomics only;
+                               3: deposit and PDE substeps of each instance in one
+                               work-group, with the deposit sums in LDS (needs them to
+                               fit: 8 bytes x grid_n^dim x (2 with uptake, else 1)).
+                               The deposit is an integer sum, so every mode gives the
+                               same bits                                                */
 } pc_config;
 
 /* One agent species (the paper's cell type).
@@ -185,6 +191,23 @@ int pc_set_state(pc_sim *sim, const float *x_dev, const float *c_dev, uint32_t s
  * caller's array may be reused once the stream has passed this point. */
 int pc_set_species(pc_sim *sim, const uint8_t *species_dev);
 
+/* Ensemble statistics of the current state, in the style of the experiment
+ * of Sect. 4 (Fig. 1: species densities and the chemical averaged over
+ * realisations), every instance of the handle being one realisation.
+ *   hist_n      bins per axis on [0, L]; an agent's bin on an axis is
+ *               floor(x * float32(hist_n / L)) clamped to [0, hist_n - 1],
+ *               formed in float32;
+ *   counts_dev  (uint32, n_species x hist_n^dim, x fastest; overwritten):
+ *               agents of each species in each bin, summed over instances;
+ *   totals_dev  (uint32, n_species; overwritten): agents of each species;
+ *   c_mean_dev  (float32, grid_n^dim; NULL to skip): the field averaged
+ *               over instances node by node (summed in FP64).
+ * Densities normalised as in Fig. 1 are counts / totals.  Stream-ordered;
+ * no synchronisation.  Errors: PC_EINVAL for null arrays or
+ * n_species * hist_n^dim >= 2^31. */
+int pc_ensemble_stats(pc_sim *sim, int hist_n, uint32_t *counts_dev, uint32_t *totals_dev,
+                      float *c_mean_dev);
+
 /* Wait for the stream; report PC_ENONFINITE if a non-finite value reached
  * the state since the last call, else PC_OK. */
 int pc_sync(pc_sim *sim);
@@ -204,6 +227,8 @@ typedef struct {
     int32_t block;
     double bin_side;
     size_t workspace_bytes;
+    int32_t deposit_path;   /* deposit_mode in effect (1, 2 or 3; never 0)  */
+    int32_t reserved;
 } pc_info_t;
 int pc_info(pc_sim *sim, pc_info_t *info);
 

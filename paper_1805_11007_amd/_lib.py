@@ -16,7 +16,7 @@ MAX_SPECIES = 8
 
 EXPORTS = (
     "pc_workspace_bytes", "pc_workspace_bytes_adjoint", "pc_create", "pc_step", "pc_use_graph",
-    "pc_positions", "pc_field", "pc_species", "pc_get_state", "pc_set_state", "pc_set_species", "pc_sync",
+    "pc_positions", "pc_field", "pc_species", "pc_get_state", "pc_set_state", "pc_set_species", "pc_ensemble_stats", "pc_sync",
     "pc_warnings", "pc_info", "pc_destroy", "pc_strerror", "pc_last_error",
     "pc_debug_neighbours", "pc_debug_forces", "pc_adjoint_segment", "pc_profile_steps",
     "pc_density_loss_work_bytes", "pc_density_loss", "pc_density_hist",
@@ -29,7 +29,7 @@ class PcConfig(C.Structure):
                 ("grid_n", C.c_int32), ("dt", C.c_double), ("k_rep", C.c_double),
                 ("D_c", C.c_double), ("gamma", C.c_double), ("pde_substeps", C.c_int32),
                 ("bin_size", C.c_double), ("deterministic", C.c_int32), ("block", C.c_int32),
-                ("bin_order", C.c_int32), ("reserved", C.c_int32)]
+                ("bin_order", C.c_int32), ("deposit_mode", C.c_int32)]
 
 
 class PcSpecies(C.Structure):
@@ -47,7 +47,8 @@ class PcInfo(C.Structure):
     _fields_ = [("n_total", C.c_int32), ("n_inst", C.c_int32), ("bins_per_axis", C.c_int32),
                 ("stencil", C.c_int32), ("n_bins_total", C.c_int64),
                 ("n_nodes_total", C.c_int64), ("pde_substeps", C.c_int32),
-                ("block", C.c_int32), ("bin_side", C.c_double), ("workspace_bytes", C.c_size_t)]
+                ("block", C.c_int32), ("bin_side", C.c_double), ("workspace_bytes", C.c_size_t),
+                ("deposit_path", C.c_int32), ("reserved", C.c_int32)]
 
 
 class PcError(RuntimeError):
@@ -83,6 +84,7 @@ def load() -> C.CDLL:
         "pc_get_state": ([vp, vp, vp, u32p], i32),
         "pc_set_state": ([vp, vp, vp, C.c_uint32], i32),
         "pc_set_species": ([vp, vp], i32),
+        "pc_ensemble_stats": ([vp, i32, vp, vp, vp], i32),
         "pc_sync": ([vp], i32),
         "pc_warnings": ([vp, u32p], i32),
         "pc_info": ([vp, C.POINTER(PcInfo)], i32),

@@ -42,6 +42,12 @@ struct Derived {
 };
 
 // A species switches when react_to >= 0 and one of its rates is > 0.
+// Agents per chemical node below which the deposit skips LDS aggregation.
+constexpr double kDepositSparse = 0.2;
+// Instances from which a batch whose per-instance deposit sums fit in LDS
+// runs deposit + PDE as one work-group per instance.
+constexpr int kFusedMinInstances = 64;
+
 static bool reacts(const pc_species_t &s) {
     return s.react_to >= 0 && (s.react_rate > 0 || s.react_rate_c > 0);
 }
@@ -70,6 +76,8 @@ int derive(const pc_config *cfg, const pc_species_t *sp, int ns, const pc_instan
     if (ns < 1 || ns > PC_MAX_SPECIES) return fail(PC_EINVAL, "1..8 species supported");
     if (ni < 1 || ni >= (1 << 24)) return fail(PC_EINVAL, "instance count out of range");
     if (cfg->bin_order != 0) return fail(PC_ENOTSUP, "only row-major bin order is built");
+    if (cfg->deposit_mode < 0 || cfg->deposit_mode > 3)
+        return fail(PC_EINVAL, "deposit_mode must be 0, 1, 2 or 3");
     if (cfg->block != 0 && cfg->block != 64 && cfg->block != 128 && cfg->block != 256 &&
         cfg->block != 512 && cfg->block != 1024)
         return fail(PC_EINVAL, "block must be 0, 64, 128, 256, 512 or 1024");
@@ -226,6 +234,7 @@ struct pc_sim {
     // binned:  count/bin/rank hold the cell-list counts of the positions in P[0]
     // sorted:  P[sorted_src] / start hold the cell-sorted current positions
     int binned, sorted, sorted_src;
+    int chem_fused;           // deposit + PDE in one per-instance kernel (k_chem_inst)
 };
 
 static void fill_params(pc_sim *s) {
@@ -276,6 +285,11 @@ static void fill_params(pc_sim *s) {
         p.react_cdt[a] = reacts(sa) ? (float)(sa.react_rate_c * c.dt) : 0.0f;
     }
     p.has_react = d.has_react;
+    // LDS aggregation pays where a work-group's agents share nodes; with
+    // fewer agents than kDepositSparse per node most corners are distinct
+    p.deposit_agg = c.deposit_mode == 1 ? 1
+                    : c.deposit_mode == 2 ? 0
+                    : ((double)d.n_total >= kDepositSparse * (double)d.nodes_total ? 1 : 0);
     PdeParams &q = s->pp;
     memset(&q, 0, sizeof(q));
     q.dim = d.dim;
@@ -357,11 +371,20 @@ static void enqueue_pde(pc_sim *s, hipStream_t st) {
 }
 
 // Kernel sequence of one step (kernels only, so it can be graph-captured).
+static void enqueue_chem(pc_sim *s, hipStream_t st) {
+    if (s->chem_fused) {
+        launch_chem_inst(s->sp, s->pp, s->b, 0, s->cur_c, s->d.n_sub, st);
+        s->cur_c = (s->cur_c + s->d.n_sub) & 1;
+    } else {
+        launch_deposit(s->sp, s->b, 0, st);
+        enqueue_pde(s, st);
+    }
+}
+
 static void enqueue_step(pc_sim *s, hipStream_t st) {
     ensure_sorted(s, st);
     launch_update(s->sp, s->b, s->sorted_src, 0, s->cur_c, s->d.block, st);
-    launch_deposit(s->sp, s->b, 0, st);
-    enqueue_pde(s, st);
+    enqueue_chem(s, st);
     launch_step_inc(s->b, st);
     s->binned = 1;
     s->sorted = 0;
@@ -406,6 +429,20 @@ static int common_create(const pc_config *cfg, const pc_species_t *species, int 
     s->sorted_src = 1;
     (void)hipGetDevice(&s->device);
     fill_params(s);
+    {
+        int max_lds = 65536;
+        if (hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock,
+                                  s->device) != hipSuccess)
+            max_lds = 65536;
+        // dynamic LDS of k_chem_inst plus room for its static species table
+        const bool fits = chem_inst_lds_bytes(s->pp) + 4096 <= (size_t)max_lds;
+        if (cfg->deposit_mode == 3 && !fits) {
+            delete s;
+            return fail(PC_EINVAL, "deposit_mode 3: an instance's deposit sums exceed the LDS");
+        }
+        s->chem_fused = cfg->deposit_mode == 3 ||
+                        (cfg->deposit_mode == 0 && fits && d.ni >= kFusedMinInstances);
+    }
     carve(s, (char *)workspace_dev);
     s->inst_host.resize(n_inst);
     uint32_t abase = 0;
@@ -591,9 +628,15 @@ int pc_profile_steps(pc_sim *s, int n_steps, double *stage_ms) {
         HIP_OK(hipEventRecord(ev[PC_STAGE_UPDATE], st));
         launch_update(s->sp, s->b, s->sorted_src, 0, s->cur_c, blk, st);
         HIP_OK(hipEventRecord(ev[PC_STAGE_DEPOSIT], st));
-        launch_deposit(s->sp, s->b, 0, st);
-        HIP_OK(hipEventRecord(ev[PC_STAGE_PDE], st));
-        enqueue_pde(s, st);
+        if (s->chem_fused) {
+            // one kernel for both: its time is reported under the deposit
+            enqueue_chem(s, st);
+            HIP_OK(hipEventRecord(ev[PC_STAGE_PDE], st));
+        } else {
+            launch_deposit(s->sp, s->b, 0, st);
+            HIP_OK(hipEventRecord(ev[PC_STAGE_PDE], st));
+            enqueue_pde(s, st);
+        }
         launch_step_inc(s->b, st);
         s->binned = 1;
         s->sorted = 0;
@@ -726,6 +769,8 @@ int pc_info(pc_sim *s, pc_info_t *info) {
     info->block = s->d.block;
     info->bin_side = s->d.bin_side;
     info->workspace_bytes = s->lay.total;
+    info->deposit_path = s->chem_fused ? 3 : (s->sp.deposit_agg ? 1 : 2);
+    info->reserved = 0;
     return PC_OK;
 }
 
@@ -849,6 +894,23 @@ int pc_adjoint_segment(pc_sim *s, const float *lamX_in_dev, const float *lamC_in
     int rc = pc_set_state(s, b.seg_x, b.seg_c, t0);
     if (rc) return rc;
     HIP_OK(hipStreamSynchronize(st));
+    HIP_OK(hipGetLastError());
+    return PC_OK;
+}
+
+int pc_ensemble_stats(pc_sim *s, int hist_n, uint32_t *counts_dev, uint32_t *totals_dev,
+                      float *c_mean_dev) {
+    if (!s || !counts_dev || !totals_dev) return fail(PC_EINVAL, "null argument");
+    if (hist_n < 1) return fail(PC_EINVAL, "hist_n must be >= 1");
+    int64_t H = 1;
+    for (int a = 0; a < s->d.dim; ++a) {
+        H *= hist_n;
+        if (H * s->d.ns >= ((int64_t)1 << 31)) return fail(PC_EINVAL, "hist_n too large");
+    }
+    const float scale = (float)((double)hist_n / s->cfg.L);
+    launch_species_hist(s->sp, s->b, 0, hist_n, scale, counts_dev, totals_dev, s->stream);
+    if (c_mean_dev)
+        launch_field_mean(s->b.c[s->cur_c], s->d.ni, s->d.nodes_per_inst, c_mean_dev, s->stream);
     HIP_OK(hipGetLastError());
     return PC_OK;
 }

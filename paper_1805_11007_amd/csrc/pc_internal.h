@@ -33,6 +33,7 @@ struct StepParams {
     int32_t nodes_per_inst;
     int32_t bins_per_inst;
     int32_t has_uptake;
+    int32_t deposit_agg;   // 1: LDS-aggregated deposit; 0: direct device atomics
     float L, halfL;
     float inv_bin;         // nb / L
     float h, inv_h, inv_2h, inv_h2;
@@ -130,6 +131,12 @@ void launch_pde(const PdeParams &q, const Buffers &b, int cin, int cout, int las
                 hipStream_t s);
 void launch_step_inc(const Buffers &b, hipStream_t s);
 void launch_zero_u32(uint32_t *d, int64_t n, hipStream_t s);
+size_t chem_inst_lds_bytes(const PdeParams &q);
+void launch_chem_inst(const StepParams &p, const PdeParams &q, const Buffers &b, int src, int cur,
+                      int n_sub, hipStream_t s);
+int launch_species_hist(const StepParams &p, const Buffers &b, int src, int m, float s,
+                        uint32_t *counts, uint32_t *totals, hipStream_t st);
+void launch_field_mean(const float *c, int n_inst, int64_t G, float *out, hipStream_t st);
 void launch_positions(const StepParams &p, const Buffers &b, int src, float *out,
                       hipStream_t s);
 void launch_species(const StepParams &p, const Buffers &b, int src, uint8_t *out, hipStream_t s);

@@ -332,18 +332,61 @@ __device__ __forceinline__ void lds_insert(uint32_t *keys, unsigned long long *v
     if (upt && b) atomicAdd(Supt + key, b);
 }
 
+// Corner nodes (instance-local index + base) and fixed-point contributions
+// of one agent's piecewise-linear deposit.  Returns false for an agent of a
+// species with neither source nor uptake (all contributions zero).
 template <int DIM, int NS, bool UPT>
+__device__ __forceinline__ bool deposit_corners(const StepParams &p, const SpTab &tab, float4 x,
+                                                uint32_t base, uint32_t key[1 << DIM],
+                                                unsigned long long cs[1 << DIM],
+                                                unsigned long long cu[1 << DIM]) {
+    const int s = species_of(x.w);
+    const float qs = sel<NS>(p.src_fx, tab.src, s);
+    const float qu = UPT ? sel<NS>(p.upt_fx, tab.upt, s) : 0.0f;
+    const bool valid = qs != 0.0f || qu != 0.0f;
+    Cell cc[3];
+    cc[0] = cell_of(p, x.x);
+    cc[1] = cell_of(p, x.y);
+    if (DIM == 3) cc[2] = cell_of(p, x.z);
+    const int n = p.grid_n;
+#pragma unroll
+    for (int m = 0; m < (1 << DIM); ++m) {
+        float ws = qs, wu = qu;
+        uint32_t idx = 0, stride = 1;
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            const int up = (m >> a) & 1;
+            const float f = up ? cc[a].t : 1.0f - cc[a].t;
+            ws *= f;
+            if (UPT) wu *= f;
+            idx += (uint32_t)(up ? cc[a].i1 : cc[a].i0) * stride;
+            stride *= (uint32_t)n;
+        }
+        key[m] = base + idx;
+        cs[m] = valid ? (unsigned long long)__float2ull_rn(ws) : 0ull;
+        cu[m] = valid && UPT ? (unsigned long long)__float2ull_rn(wu) : 0ull;
+    }
+    return valid;
+}
+
+// AGG = false skips the LDS table (each contribution goes straight to a
+// device atomic): cheaper when agents are sparse next to the nodes, so that
+// a work-group's agents rarely share a node.
+template <int DIM, int NS, bool UPT, bool AGG>
 __global__ void __launch_bounds__(256)
 k_deposit(StepParams p, const InstInfo *__restrict__ inst, const float4 *__restrict__ P,
           unsigned long long *__restrict__ Ssrc, unsigned long long *__restrict__ Supt) {
-    __shared__ uint32_t keys[kDepSlots];
-    __shared__ unsigned long long vs[kDepSlots];
-    __shared__ unsigned long long vu[UPT ? kDepSlots : 1];
+    constexpr int slots = AGG ? kDepSlots : 1;
+    __shared__ uint32_t keys[slots];
+    __shared__ unsigned long long vs[slots];
+    __shared__ unsigned long long vu[UPT && AGG ? kDepSlots : 1];
     __shared__ SpTab tab;
-    for (int q = threadIdx.x; q < kDepSlots; q += blockDim.x) {
-        keys[q] = kEmpty;
-        vs[q] = 0ull;
-        if (UPT) vu[q] = 0ull;
+    if (AGG) {
+        for (int q = threadIdx.x; q < kDepSlots; q += blockDim.x) {
+            keys[q] = kEmpty;
+            vs[q] = 0ull;
+            if (UPT) vu[q] = 0ull;
+        }
     }
     if (NS == 0) load_tab(p, tab);
     __syncthreads();
@@ -355,33 +398,8 @@ k_deposit(StepParams p, const InstInfo *__restrict__ inst, const float4 *__restr
     bool valid = false;
     if (i < p.n_total) {
         const float4 x = P[i];
-        const int s = species_of(x.w);
-        const uint32_t base = inst[inst_of(x.w)].node_base;
-        const float qs = sel<NS>(p.src_fx, tab.src, s);
-        const float qu = UPT ? sel<NS>(p.upt_fx, tab.upt, s) : 0.0f;
-        valid = qs != 0.0f || qu != 0.0f;
-        Cell cc[3];
-        cc[0] = cell_of(p, x.x);
-        cc[1] = cell_of(p, x.y);
-        if (DIM == 3) cc[2] = cell_of(p, x.z);
-        const int n = p.grid_n;
-#pragma unroll
-        for (int m = 0; m < (1 << DIM); ++m) {
-            float ws = qs, wu = qu;
-            uint32_t idx = 0, stride = 1;
-#pragma unroll
-            for (int a = 0; a < DIM; ++a) {
-                const int up = (m >> a) & 1;
-                const float f = up ? cc[a].t : 1.0f - cc[a].t;
-                ws *= f;
-                if (UPT) wu *= f;
-                idx += (uint32_t)(up ? cc[a].i1 : cc[a].i0) * stride;
-                stride *= (uint32_t)n;
-            }
-            key[m] = base + idx;
-            cs[m] = valid ? (unsigned long long)__float2ull_rn(ws) : 0ull;
-            cu[m] = valid && UPT ? (unsigned long long)__float2ull_rn(wu) : 0ull;
-        }
+        valid = deposit_corners<DIM, NS, UPT>(p, tab, x, inst[inst_of(x.w)].node_base, key, cs,
+                                              cu);
     } else {
 #pragma unroll
         for (int m = 0; m < (1 << DIM); ++m) {
@@ -389,6 +407,14 @@ k_deposit(StepParams p, const InstInfo *__restrict__ inst, const float4 *__restr
             cs[m] = cu[m] = 0ull;
         }
     }
+    auto emit = [&](uint32_t k, unsigned long long a, unsigned long long b) {
+        if (AGG) {
+            lds_insert(keys, vs, vu, UPT, k, a, b, Ssrc, Supt);
+        } else {
+            if (a) atomicAdd(Ssrc + k, a);
+            if (UPT && b) atomicAdd(Supt + k, b);
+        }
+    };
     // In dense clusters every lane of the wave often deposits into the same
     // 2^dim nodes: sum over the wave first and insert once per node.
     const uint32_t k0 = valid ? key[0] : kEmpty;
@@ -403,13 +429,14 @@ k_deposit(StepParams p, const InstInfo *__restrict__ inst, const float4 *__restr
                 a += __shfl_xor(a, d, 64);
                 if (UPT) b += __shfl_xor(b, d, 64);
             }
-            if ((threadIdx.x & 63) == 0) lds_insert(keys, vs, vu, UPT, key[m], a, b, Ssrc, Supt);
+            if ((threadIdx.x & 63) == 0) emit(key[m], a, b);
         }
     } else if (valid) {
 #pragma unroll
         for (int m = 0; m < (1 << DIM); ++m)
-            if (cs[m] || cu[m]) lds_insert(keys, vs, vu, UPT, key[m], cs[m], cu[m], Ssrc, Supt);
+            if (cs[m] || cu[m]) emit(key[m], cs[m], cu[m]);
     }
+    if (!AGG) return;
     __syncthreads();
     for (int q = threadIdx.x; q < kDepSlots; q += blockDim.x) {
         const uint32_t k = keys[q];
@@ -417,6 +444,52 @@ k_deposit(StepParams p, const InstInfo *__restrict__ inst, const float4 *__restr
         if (vs[q]) atomicAdd(Ssrc + k, vs[q]);
         if (UPT && vu[q]) atomicAdd(Supt + k, vu[q]);
     }
+}
+
+// Deposit and every PDE substep of one instance in one work-group, for
+// batches of many small instances: the instance's deposit sums stay in LDS
+// (never in HBM) and the field is read and written once per substep.  The
+// agents of instance k occupy rows [agent_base, agent_base + n_agents) of
+// the state in every order the step uses (instance-major bins).  The same
+// corner contributions and node update as k_deposit + k_pde, so the same
+// bits.  Substeps ping-pong between the two field buffers, starting from
+// buffer `cur`; the barrier between substeps orders them.
+template <int DIM, int NS, bool UPT>
+__global__ void __launch_bounds__(1024)
+k_chem_inst(StepParams p, PdeParams q, const InstInfo *__restrict__ inst,
+            const float4 *__restrict__ P, float *__restrict__ c0, float *__restrict__ c1, int cur,
+            int n_sub, uint32_t *__restrict__ flags) {
+    extern __shared__ unsigned long long S[];  // G source sums, then G uptake sums
+    __shared__ SpTab tab;
+    const int G = q.nodes_per_inst;
+    for (int l = threadIdx.x; l < G * (UPT ? 2 : 1); l += blockDim.x) S[l] = 0ull;
+    if (NS == 0) load_tab(p, tab);
+    __syncthreads();
+    const InstInfo ii = inst[blockIdx.x];
+    for (uint32_t i = threadIdx.x; i < ii.n_agents; i += blockDim.x) {
+        uint32_t key[1 << DIM];
+        unsigned long long cs[1 << DIM], cu[1 << DIM];
+        if (!deposit_corners<DIM, NS, UPT>(p, tab, P[ii.agent_base + i], 0u, key, cs, cu))
+            continue;
+#pragma unroll
+        for (int m = 0; m < (1 << DIM); ++m) {
+            if (cs[m]) atomicAdd(&S[key[m]], cs[m]);
+            if (UPT && cu[m]) atomicAdd(&S[G + key[m]], cu[m]);
+        }
+    }
+    __syncthreads();
+    const int n = q.grid_n;
+    uint32_t flag = 0;
+    for (int m = 0; m < n_sub; ++m) {
+        const float *src = (((cur + m) & 1) ? c1 : c0) + ii.node_base;
+        float *dst = (((cur + m + 1) & 1) ? c1 : c0) + ii.node_base;
+        for (int l = threadIdx.x; l < G; l += blockDim.x) {
+            const int ic[3] = {l % n, (l / n) % n, DIM == 3 ? l / (n * n) : 0};
+            dst[l] = pde_node<DIM>(q, src, ic, S[l], UPT ? S[G + l] : 0ull, flag);
+        }
+        if (m + 1 < n_sub) __syncthreads();
+    }
+    if (flag) atomicOr(flags, flag);
 }
 
 // PDE substep, one thread per node; the last substep of a step clears the
@@ -619,8 +692,12 @@ void launch_debug_pairs(const StepParams &p, const Buffers &b, int src, uint32_t
 
 template <int DIM, int NS, bool UPT>
 static void dep(const StepParams &p, const Buffers &b, int src, hipStream_t s) {
-    hipLaunchKernelGGL((k_deposit<DIM, NS, UPT>), dim3(grid_for(p.n_total, 256)), dim3(256), 0, s,
-                       p, b.inst, b.P[src], b.S_src, b.S_upt);
+    if (p.deposit_agg)
+        hipLaunchKernelGGL((k_deposit<DIM, NS, UPT, true>), dim3(grid_for(p.n_total, 256)),
+                           dim3(256), 0, s, p, b.inst, b.P[src], b.S_src, b.S_upt);
+    else
+        hipLaunchKernelGGL((k_deposit<DIM, NS, UPT, false>), dim3(grid_for(p.n_total, 256)),
+                           dim3(256), 0, s, p, b.inst, b.P[src], b.S_src, b.S_upt);
 }
 
 void launch_deposit(const StepParams &p, const Buffers &b, int src, hipStream_t s) {
@@ -640,6 +717,38 @@ void launch_deposit(const StepParams &p, const Buffers &b, int src, hipStream_t 
         else PC_DEP(3, 0);
     }
 #undef PC_DEP
+}
+
+template <int DIM, int NS, bool UPT>
+static void chem(const StepParams &p, const PdeParams &q, const Buffers &b, int src, int cur,
+                 int n_sub, hipStream_t s) {
+    const size_t lds = 8 * (size_t)q.nodes_per_inst * (UPT ? 2 : 1);
+    hipLaunchKernelGGL((k_chem_inst<DIM, NS, UPT>), dim3(p.n_inst), dim3(1024), lds, s, p, q,
+                       b.inst, b.P[src], b.c[0], b.c[1], cur, n_sub, b.flags);
+}
+
+size_t chem_inst_lds_bytes(const PdeParams &q) {
+    return 8 * (size_t)q.nodes_per_inst * (q.has_uptake ? 2 : 1);
+}
+
+void launch_chem_inst(const StepParams &p, const PdeParams &q, const Buffers &b, int src, int cur,
+                      int n_sub, hipStream_t s) {
+    const int ns = p.n_species == 1 ? 1 : (p.n_species == 2 ? 2 : 0);
+#define PC_CHEM(D, N)                                                   \
+    do {                                                                \
+        if (p.has_uptake) chem<D, N, true>(p, q, b, src, cur, n_sub, s); \
+        else chem<D, N, false>(p, q, b, src, cur, n_sub, s);            \
+    } while (0)
+    if (p.dim == 2) {
+        if (ns == 1) PC_CHEM(2, 1);
+        else if (ns == 2) PC_CHEM(2, 2);
+        else PC_CHEM(2, 0);
+    } else {
+        if (ns == 1) PC_CHEM(3, 1);
+        else if (ns == 2) PC_CHEM(3, 2);
+        else PC_CHEM(3, 0);
+    }
+#undef PC_CHEM
 }
 
 void launch_pde(const PdeParams &q, const Buffers &b, int cin, int cout, int last,

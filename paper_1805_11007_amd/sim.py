@@ -53,6 +53,7 @@ class ModelSpec:
     bin_size: float = 0.0
     deterministic: bool = False
     block: int = 0
+    deposit_mode: int = 0    # 0 auto, 1 LDS-aggregated, 2 direct atomics, 3 fused per instance
 
     @classmethod
     def from_workload(cls, w, **over) -> "ModelSpec":
@@ -83,6 +84,7 @@ class ModelSpec:
         cfg.deterministic = 1 if self.deterministic else 0
         cfg.block = self.block
         cfg.bin_order = 0
+        cfg.deposit_mode = self.deposit_mode
         ns = len(self.species)
         sp = (LB.PcSpecies * max(ns, 1))()
         for k, s in enumerate(self.species):
@@ -207,6 +209,19 @@ class Sim:
         species = species.to(self.device, torch.uint8).contiguous().reshape(self.spec.n_total)
         LB.check(self.L.pc_set_species(self.h, _ptr(species)))
         self._keep_sp = species  # must live until the stream has read it
+
+    def ensemble_stats(self, hist_n: int, field_mean: bool = True):
+        """Per-species histograms summed over instances (n_species x
+        hist_n^dim, int32 view of uint32 counts), species totals and the
+        instance-mean field (None if not asked for)."""
+        ns = len(self.spec.species)
+        counts = torch.empty(ns * hist_n ** self.spec.dim, dtype=torch.int32, device=self.device)
+        totals = torch.empty(ns, dtype=torch.int32, device=self.device)
+        cm = torch.empty(self.spec.grid_n ** self.spec.dim, dtype=torch.float32,
+                         device=self.device) if field_mean else None
+        LB.check(self.L.pc_ensemble_stats(self.h, int(hist_n), _ptr(counts), _ptr(totals),
+                                          _ptr(cm) if field_mean else C.c_void_p(0)))
+        return counts.view(ns, -1), totals, cm
 
     def sync(self) -> None:
         LB.check(self.L.pc_sync(self.h))

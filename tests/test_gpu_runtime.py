@@ -156,3 +156,43 @@ def test_error_paths():
     with pytest.raises(PcError):
         Sim(ModelSpec.from_workload(w, pde_substeps=1, dt=1e-2), torch.from_numpy(inp["x0"]),
             torch.from_numpy(inp["species0"]), torch.from_numpy(inp["c0"]))
+
+
+def _dep_case(cfg, n, g):
+    if cfg == 4:
+        return W.scaled(W.config(4), n_agents=list(np.random.default_rng(7).integers(1, 600, 70)),
+                        grid_n=g)
+    if cfg == 6:
+        return W.config6(n_real=n)
+    return W.scaled(W.config(cfg), n_agents=n, grid_n=g)
+
+
+@pytest.mark.parametrize("cfg,n,g,modes", [(3, 40000, 32, (2,)), (2, 20011, 129, (2,)),
+                                           (1, 3001, 37, (2, 3)), (4, None, 24, (2, 3)),
+                                           (5, 3000, 32, (2, 3)), (6, 70, None, (2, 3))])
+def test_deposit_modes_bitwise_equal(cfg, n, g, modes):
+    """The deposit is an integer sum: LDS-aggregated, direct-atomic and
+    per-instance fused (deposit + PDE substeps in one work-group) paths give
+    the same bits, step after step."""
+    w = _dep_case(cfg, n, g)
+    inp = W.make_inputs(w)
+    a = make_sim(w, inp, deterministic=True, deposit_mode=1)
+    assert a.info["deposit_path"] == 1
+    a.step(7)
+    xa, ca = _state(a)
+    for m in modes:
+        b = make_sim(w, inp, deterministic=True, deposit_mode=m)
+        assert b.info["deposit_path"] == m
+        b.step(7)
+        xb, cb = _state(b)
+        assert np.array_equal(xa, xb) and np.array_equal(ca, cb), m
+        b.close()
+
+
+def test_fused_path_chosen_for_many_small_instances_and_rejected_when_too_big():
+    from paper_1805_11007_amd import PcError
+    w = W.config6(n_real=64)
+    assert make_sim(w, W.make_inputs(w)).info["deposit_path"] == 3
+    w = W.scaled(W.config(3), n_agents=1000, grid_n=64)  # 64^3 sums do not fit in LDS
+    with pytest.raises(PcError):
+        make_sim(w, W.make_inputs(w), deposit_mode=3)
