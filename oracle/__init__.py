@@ -55,7 +55,8 @@ class Params(C.Structure):
                 ("uptake", C.c_double * MAX_SPECIES), ("react_to", C.c_int32 * MAX_SPECIES),
                 ("react_rate", C.c_double * MAX_SPECIES),
                 ("react_rate_c", C.c_double * MAX_SPECIES), ("seed", C.c_uint64),
-                ("inst", C.c_uint32), ("chi_scale", C.c_double)]
+                ("inst", C.c_uint32), ("chi_scale", C.c_double),
+                ("deposit_kernel", C.c_int32), ("kde_radius", C.c_double)]
 
 
 _lib = None
@@ -85,6 +86,8 @@ def lib():
             "orc_drift": ([P, vp, i64, vp, vp, vp], None),
             "orc_deposit": ([P, i64, vp, vp, vp, vp], None),
             "orc_pde": ([P, vp, vp, vp], None),
+            "orc_pde_density": ([P, vp, vp, vp], None),
+            "orc_deposit_kde": ([P, i64, vp, vp, vp, vp], None),
             "orc_react": ([P, i64, vp, vp, vp, vp, C.c_uint32, vp], None),
             "orc_step": ([P, i64, vp, vp, vp, vp, vp], None),
             "orc_run": ([P, i64, vp, vp, vp, vp, vp, C.c_int], None),
@@ -141,6 +144,8 @@ def params(w, inst: int = 0, mode: int = 1, **over) -> Params:
     p.inst = ins.stream if getattr(ins, "stream", -1) >= 0 else inst
     p.chi_scale = ins.chi_scale
     p.mode = mode
+    p.deposit_kernel = getattr(w, "deposit_kernel", 0)
+    p.kde_radius = getattr(w, "kde_radius", 3.0)
     for k, v in over.items():
         setattr(p, k, v)
     return p
@@ -247,6 +252,23 @@ def deposit(p: Params, X: np.ndarray, sp: np.ndarray):
     Su = np.empty(n_nodes(p), np.float64)
     lib().orc_deposit(C.byref(p), len(X), _ptr(X), _ptr(sp), _ptr(Ss), _ptr(Su))
     return Ss, Su
+
+
+def deposit_kde(p: Params, X: np.ndarray, sp: np.ndarray):
+    """Gaussian kernel density of source and uptake at every node: (sigma, upsilon)."""
+    X = _c(X, np.float64)
+    sp = _c(sp, np.uint8)
+    sig = np.empty(n_nodes(p), np.float64)
+    ups = np.empty(n_nodes(p), np.float64)
+    lib().orc_deposit_kde(C.byref(p), len(X), _ptr(X), _ptr(sp), _ptr(sig), _ptr(ups))
+    return sig, ups
+
+
+def pde_density(p: Params, c: np.ndarray, sigma: np.ndarray, ups: np.ndarray) -> np.ndarray:
+    c = _c(c, np.float64).copy()
+    lib().orc_pde_density(C.byref(p), _ptr(c), _ptr(_c(sigma, np.float64)),
+                          _ptr(_c(ups, np.float64)))
+    return c
 
 
 def pde(p: Params, c: np.ndarray, S_src: np.ndarray, S_upt: np.ndarray) -> np.ndarray:

@@ -44,6 +44,8 @@ typedef struct {
     uint64_t seed;        /* Philox key = (lo32(seed), hi32(seed) ^ inst) */
     uint32_t inst;
     double chi_scale;     /* per-instance multiplier of chi */
+    int32_t deposit_kernel;  /* 0: particle-in-cell ; 1: Gaussian kernel density */
+    double kde_radius;    /* kernel truncation radius in units of the bandwidth */
 } orc_params;
 
 int orc_num_threads(void) {
@@ -512,6 +514,46 @@ void orc_deposit(const orc_params *p, int64_t n, const double *X, const uint8_t 
     }
 }
 
+/* Gaussian kernel density estimate at every node (Sect. 2.3 and the
+ * density loop of Sect. 3.5): rho_s(p_l) = sum over agents i of species s
+ * within distance kde_radius * eps_s of p_l of
+ *   K_eps(p_l - X_i) = (2 pi eps^2)^(-dim/2) exp(-|p_l - X_i|^2 / (2 eps^2)),
+ * with the bandwidth eps_s = the species' diameter (the cell size).  Distances
+ * are minimum-image on the torus; with walls there is no image (kernel mass
+ * beyond a wall is lost, as in the paper's loop).  sigma = sum_s source_s
+ * rho_s and upsilon = sum_s uptake_s rho_s are densities (no control
+ * volume).  Readings: the 2D kernel of the paper taken to dim dimensions;
+ * a per-species bandwidth; the truncation radius is a parameter. */
+void orc_deposit_kde(const orc_params *p, int64_t n, const double *X, const uint8_t *sp,
+                     double *sigma, double *ups) {
+    const int64_t G = orc_nodes(p);
+    const double h = orc_h(p);
+    const double PI = 3.14159265358979323846;
+#pragma omp parallel for
+    for (int64_t l = 0; l < G; ++l) {
+        int ci[3];
+        orc_unflat(p, l, ci);
+        double s_acc = 0.0, u_acc = 0.0;
+        for (int64_t i = 0; i < n; ++i) {
+            const int s = sp[i];
+            const double eps = p->diam[s];
+            double r2 = 0.0;
+            for (int a = 0; a < p->dim; ++a) {
+                double dx = ci[a] * h - X[i * p->dim + a];
+                if (p->periodic) dx = orc_min_image(dx, p->L);
+                r2 += dx * dx;
+            }
+            const double R = p->kde_radius * eps;
+            if (!(r2 < R * R)) continue;
+            const double K = pow(2.0 * PI * eps * eps, -0.5 * p->dim) * exp(-r2 / (2.0 * eps * eps));
+            s_acc += p->source[s] * K;
+            u_acc += p->uptake[s] * K;
+        }
+        sigma[l] = s_acc;
+        ups[l] = u_acc;
+    }
+}
+
 /* Control volume of node l in units of h^dim: 1, or 1/2 per wall axis. */
 static double orc_volume(const orc_params *p, int64_t l) {
     if (p->periodic) return 1.0;
@@ -531,11 +573,30 @@ static double orc_volume(const orc_params *p, int64_t l) {
  * the substeps.  Reading: the printed update matrix I - dt D^2 has the sign
  * of an implicit step while the text states forward Euler; forward Euler
  * with +dt D_c Lap_h is taken. */
+void orc_pde_density(const orc_params *p, double *c, const double *sigma, const double *ups);
+
 void orc_pde(const orc_params *p, double *c, const double *S_src, const double *S_upt) {
     const int64_t G = orc_nodes(p);
     const double h = orc_h(p);
     double hd = 1.0;
     for (int a = 0; a < p->dim; ++a) hd *= h;
+    double *sigma = (double *)malloc(sizeof(double) * (size_t)G);
+    double *ups = (double *)malloc(sizeof(double) * (size_t)G);
+    for (int64_t l = 0; l < G; ++l) {
+        const double vol = hd * orc_volume(p, l);
+        sigma[l] = S_src[l] / vol;
+        ups[l] = S_upt[l] / vol;
+    }
+    orc_pde_density(p, c, sigma, ups);
+    free(sigma);
+    free(ups);
+}
+
+/* The update above with the source and uptake densities given per node. */
+void orc_pde_density(const orc_params *p, double *c, const double *sigma_in,
+                     const double *ups_in) {
+    const int64_t G = orc_nodes(p);
+    const double h = orc_h(p);
     const double dts = p->dt / p->n_sub;
     double *tmp = (double *)malloc(sizeof(double) * (size_t)G);
     for (int sub = 0; sub < p->n_sub; ++sub) {
@@ -550,8 +611,7 @@ void orc_pde(const orc_params *p, double *c, const double *S_src, const double *
                 cm[a] = orc_nbr(p, ci[a], -1);
                 lap += (c[orc_flat(p, cp)] - 2.0 * c[l] + c[orc_flat(p, cm)]) / (h * h);
             }
-            double vol = hd * orc_volume(p, l);
-            double sigma = S_src[l] / vol, ups = S_upt[l] / vol;
+            const double sigma = sigma_in[l], ups = ups_in[l];
             tmp[l] = c[l] + dts * (p->D_c * lap + sigma - ups * c[l] - p->gamma * c[l]);
         }
         memcpy(c, tmp, sizeof(double) * (size_t)G);
@@ -644,8 +704,13 @@ void orc_step(const orc_params *p, int64_t n, double *X, uint8_t *sp, const uint
     memcpy(sp, nsp, (size_t)n);  /* the deposit sees the switched types */
     double *Ss = (double *)malloc(sizeof(double) * (size_t)G);
     double *Su = (double *)malloc(sizeof(double) * (size_t)G);
-    orc_deposit(p, n, X, sp, Ss, Su);
-    orc_pde(p, c, Ss, Su);
+    if (p->deposit_kernel == 1) {
+        orc_deposit_kde(p, n, X, sp, Ss, Su);
+        orc_pde_density(p, c, Ss, Su);
+    } else {
+        orc_deposit(p, n, X, sp, Ss, Su);
+        orc_pde(p, c, Ss, Su);
+    }
     *step += 1;
     free(Ss);
     free(Su);

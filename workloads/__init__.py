@@ -76,6 +76,8 @@ class Workload:
     species_rule: str = "single"  # "single" | "halves" (id >= N/2 -> species 1)
     c0: str = "sin"          # "sin": prod sin(2 pi x) + 1 ; "cos": prod cos(pi x) + 1
     gen_seed: int = 1000
+    deposit_kernel: int = 0  # 0: particle-in-cell ; 1: Gaussian kernel density (Sect. 2.3)
+    kde_radius: float = 3.0  # kernel truncation radius in bandwidths
 
     @property
     def n_total(self) -> int:
