@@ -99,6 +99,17 @@ typedef struct {
                                fit: 8 bytes x grid_n^dim x (2 with uptake, else 1)).
                                The deposit is an integer sum, so every mode gives the
                                same bits                                                */
+    int32_t deposit_kernel; /* 0: particle-in-cell (piecewise-linear weights);
+                               1: Gaussian kernel density (Sect. 2.3): at node p,
+                               sigma = sum_i source_i K(p - X_i), upsilon likewise,
+                               K(x) = (2 pi e^2)^(-dim/2) exp(-|x|^2 / (2 e^2)), e =
+                               the agent's diameter, over |p - X_i| < kde_radius e
+                               (minimum image on the torus; no image across walls).
+                               Gathered per node over the cell list of X^{n+1};
+                               deposit_mode is then ignored (3 is rejected)           */
+    int32_t reserved;
+    double kde_radius;      /* truncation radius in bandwidths (0: 3); kde_radius times
+                               the largest diameter must be < L/2                       */
 } pc_config;
 
 /* One agent species (the paper's cell type).

@@ -29,7 +29,9 @@ class PcConfig(C.Structure):
                 ("grid_n", C.c_int32), ("dt", C.c_double), ("k_rep", C.c_double),
                 ("D_c", C.c_double), ("gamma", C.c_double), ("pde_substeps", C.c_int32),
                 ("bin_size", C.c_double), ("deterministic", C.c_int32), ("block", C.c_int32),
-                ("bin_order", C.c_int32), ("deposit_mode", C.c_int32)]
+                ("bin_order", C.c_int32), ("deposit_mode", C.c_int32),
+                ("deposit_kernel", C.c_int32), ("reserved", C.c_int32),
+                ("kde_radius", C.c_double)]
 
 
 class PcSpecies(C.Structure):

@@ -2,7 +2,9 @@
 
 It searches the cell-list bin side (as a multiple of the largest contact
 distance: 1.0 selects the 3^dim stencil, >= 2.0 the 2^dim half-bin stencil)
-and the work-group size of the agent kernels.  It times a few steps of each
+and the work-group size of the agent kernels, then, with the best of those,
+the deposit mode (LDS-aggregated, direct atomics, or deposit + PDE fused per
+instance where an instance's sums fit in LDS).  It times a few steps of each
 candidate on the caller's own initial state, with HIP-graph replay, and
 returns the fastest.  Results are cached in a JSON file keyed by device
 name, dimension, agent-count bucket, instance count, grid size and boundary
@@ -22,6 +24,7 @@ from .sim import ModelSpec, Sim
 
 CANDIDATE_BINS = (1.0, 1.25, 2.0)
 CANDIDATE_BLOCKS = (128, 256, 512)
+CANDIDATE_DEPOSIT = (1, 2, 3)
 
 
 def cache_path() -> Path:
@@ -75,15 +78,17 @@ def time_steps(spec: ModelSpec, x0, s0, c0, steps: int, warmup: int = 2) -> floa
 
 
 def tune(spec: ModelSpec, x0, s0, c0, steps: int = 10, use_cache: bool = True,
-         bins=CANDIDATE_BINS, blocks=CANDIDATE_BLOCKS) -> tuple[ModelSpec, dict]:
-    """Return (spec with the fastest bin_size and block, report)."""
+         bins=CANDIDATE_BINS, blocks=CANDIDATE_BLOCKS,
+         deposit_modes=CANDIDATE_DEPOSIT) -> tuple[ModelSpec, dict]:
+    """Return (spec with the fastest bin_size, block and deposit mode, report)."""
     key = shape_key(spec)
     cache = _load() if use_cache else {}
     cut = max(s.diameter for s in spec.species)
     if key in cache:
         c = cache[key]
         return dataclasses.replace(spec, bin_size=c["bin_mult"] * cut * (1 + 2e-4) if
-                                   c["bin_mult"] else 0.0, block=c["block"]), {"cached": c}
+                                   c["bin_mult"] else 0.0, block=c["block"],
+                                   deposit_mode=c.get("deposit_mode", 0)), {"cached": c}
     x0 = x0.cuda()
     s0 = s0.cuda()
     c0 = c0.cuda()
@@ -103,11 +108,26 @@ def tune(spec: ModelSpec, x0, s0, c0, steps: int = 10, use_cache: bool = True,
     ok = [t for t in trials if "ms_per_step" in t]
     if not ok:
         return spec, {"trials": trials}
-    best = min(ok, key=lambda t: t["ms_per_step"])
+    best = dict(min(ok, key=lambda t: t["ms_per_step"]), deposit_mode=spec.deposit_mode)
+    side = best["bin_mult"] * cut * (1 + 2e-4)
+    for dm in deposit_modes:
+        if dm == spec.deposit_mode:
+            continue
+        cand = dataclasses.replace(spec, bin_size=side, block=best["block"], deposit_mode=dm)
+        try:
+            ms = time_steps(cand, x0, s0, c0, steps)
+        except Exception as e:  # e.g. per-instance sums that do not fit in LDS
+            trials.append({"deposit_mode": dm, "error": str(e)})
+            continue
+        trials.append({"bin_mult": best["bin_mult"], "block": best["block"], "deposit_mode": dm,
+                       "ms_per_step": ms})
+        if ms < best["ms_per_step"]:
+            best = {"bin_mult": best["bin_mult"], "block": best["block"], "deposit_mode": dm,
+                    "ms_per_step": ms}
     if use_cache:
         cache[key] = {"bin_mult": best["bin_mult"], "block": best["block"],
-                      "ms_per_step": best["ms_per_step"]}
+                      "deposit_mode": best["deposit_mode"], "ms_per_step": best["ms_per_step"]}
         _store(cache)
-    tuned = dataclasses.replace(spec, bin_size=best["bin_mult"] * cut * (1 + 2e-4),
-                                block=best["block"])
+    tuned = dataclasses.replace(spec, bin_size=side, block=best["block"],
+                                deposit_mode=best["deposit_mode"])
     return tuned, {"trials": trials, "best": best}

@@ -37,7 +37,8 @@ struct Derived {
     int nb, stencil;
     double bin_side, cutoff, h;
     int64_t bins_per_inst, bins_total, nodes_per_inst, nodes_total;
-    int n_sub, block, has_uptake, has_react;
+    int n_sub, block, has_uptake, has_react, kde;
+    double kde_radius;
     uint32_t warn;
 };
 
@@ -111,6 +112,18 @@ int derive(const pc_config *cfg, const pc_species_t *sp, int ns, const pc_instan
     }
     if (d.n_total >= (int64_t)1 << 31) return fail(PC_EINVAL, "too many agents");
     if (d.cutoff >= cfg->L / 2) return fail(PC_EINVAL, "cutoff must be < L/2");
+    if (cfg->deposit_kernel != 0 && cfg->deposit_kernel != 1)
+        return fail(PC_EINVAL, "deposit_kernel must be 0 or 1");
+    d.kde = cfg->deposit_kernel;
+    d.kde_radius = cfg->kde_radius > 0 ? cfg->kde_radius : 3.0;
+    if (!(cfg->kde_radius >= 0) || !std::isfinite(cfg->kde_radius))
+        return fail(PC_EINVAL, "kde_radius must be finite and >= 0");
+    if (d.kde) {
+        if (cfg->deposit_mode == 3)
+            return fail(PC_EINVAL, "deposit_mode 3 is a particle-in-cell path");
+        if (d.kde_radius * d.cutoff >= cfg->L / 2)
+            return fail(PC_EINVAL, "kde_radius * diameter must be < L/2");
+    }
 
     // Bins: side >= cutoff (1 + 1e-4) so float32 rounding of the bin index
     // can never separate a pair closer than the cutoff by two bins.  A side
@@ -283,7 +296,17 @@ static void fill_params(pc_sim *s) {
         if ((double)f < pr) f = std::nextafter(f, INFINITY);
         p.react_p[a] = reacts(sa) ? f : 0.0f;
         p.react_cdt[a] = reacts(sa) ? (float)(sa.react_rate_c * c.dt) : 0.0f;
+        const double e = sa.diameter, R = d.kde_radius * e;
+        p.kde_R2[a] = (float)(R * R);
+        p.kde_norm[a] = (float)pow(2.0 * M_PI * e * e, -0.5 * d.dim);
+        p.kde_inv2e2[a] = (float)(1.0 / (2.0 * e * e));
+        p.src_f[a] = (float)sa.source;
+        p.upt_f[a] = (float)sa.uptake;
     }
+    p.kde = d.kde;
+    // bins scanned around a node: a hair wider than the largest radius, so
+    // that float32 rounding of the bin range never drops a candidate
+    p.kde_R = (float)(d.kde_radius * d.cutoff * (1.0 + 1e-4));
     p.has_react = d.has_react;
     // LDS aggregation pays where a work-group's agents share nodes; with
     // fewer agents than kDepositSparse per node most corners are distinct
@@ -306,6 +329,7 @@ static void fill_params(pc_sim *s) {
     q.fx_to_density = (float)(1.0 / (4294967296.0 * hd));
     q.inv_hd = (float)(1.0 / hd);
     q.has_uptake = d.has_uptake;
+    q.kde = d.kde;
 }
 
 static void carve(pc_sim *s, char *ws) {
@@ -384,13 +408,28 @@ static void enqueue_chem(pc_sim *s, hipStream_t st) {
 static void enqueue_step(pc_sim *s, hipStream_t st) {
     ensure_sorted(s, st);
     launch_update(s->sp, s->b, s->sorted_src, 0, s->cur_c, s->d.block, st);
+    if (s->d.kde) {
+        // the density gather needs the cell list of X^{n+1}: sort now, and
+        // the next step starts from the sorted state
+        s->binned = 1;
+        s->sorted = 0;
+        ensure_sorted(s, st);
+        launch_kde(s->sp, s->b, s->sorted_src, st);
+        enqueue_pde(s, st);
+        launch_step_inc(s->b, st);
+        return;
+    }
     enqueue_chem(s, st);
     launch_step_inc(s->b, st);
     s->binned = 1;
     s->sorted = 0;
 }
 
-static int is_steady(const pc_sim *s) { return s->binned && !s->sorted; }
+// The state a step leaves: binned (counts of X^{n+1} kept for the next
+// step's scan), or sorted already when the deposit gathers per node.
+static int is_steady(const pc_sim *s) {
+    return s->d.kde ? (s->sorted && !s->binned) : (s->binned && !s->sorted);
+}
 
 static int common_create(const pc_config *cfg, const pc_species_t *species, int n_species,
                          const pc_instance *inst, int n_inst, void *workspace_dev,
@@ -440,8 +479,8 @@ static int common_create(const pc_config *cfg, const pc_species_t *species, int 
             delete s;
             return fail(PC_EINVAL, "deposit_mode 3: an instance's deposit sums exceed the LDS");
         }
-        s->chem_fused = cfg->deposit_mode == 3 ||
-                        (cfg->deposit_mode == 0 && fits && d.ni >= kFusedMinInstances);
+        s->chem_fused = !d.kde && (cfg->deposit_mode == 3 ||
+                                   (cfg->deposit_mode == 0 && fits && d.ni >= kFusedMinInstances));
     }
     carve(s, (char *)workspace_dev);
     s->inst_host.resize(n_inst);
@@ -599,57 +638,73 @@ int pc_profile_steps(pc_sim *s, int n_steps, double *stage_ms) {
     if (!s || !stage_ms || n_steps < 1) return fail(PC_EINVAL, "bad argument");
     hipStream_t st = s->stream;
     const int blk = s->d.block;
-    hipEvent_t ev[PC_N_STAGES + 1];
-    for (int k = 0; k <= PC_N_STAGES; ++k) HIP_OK(hipEventCreate(&ev[k]));
+    hipEvent_t e0[PC_N_STAGES], e1[PC_N_STAGES];
+    for (int k = 0; k < PC_N_STAGES; ++k) {
+        HIP_OK(hipEventCreate(&e0[k]));
+        HIP_OK(hipEventCreate(&e1[k]));
+    }
     double acc[PC_N_STAGES] = {0};
+    // with the per-node density gather a step starts sorted; the sort of
+    // the initial state belongs to no step
+    if (s->d.kde) ensure_sorted(s, st);
     for (int t = 0; t < n_steps; ++t) {
-        HIP_OK(hipEventRecord(ev[PC_STAGE_BIN], st));
-        const int was_sorted = s->sorted;
-        if (!was_sorted && !s->binned) {
-            launch_bin(s->sp, s->b, 0, blk, st);
-            s->binned = 1;
-        }
-        HIP_OK(hipEventRecord(ev[PC_STAGE_SCAN], st));
-        if (!was_sorted) {
-            launch_scan(s->b, s->d.bins_total, (int32_t)s->d.n_total, st);
+        bool ran[PC_N_STAGES] = {false};
+#define PC_STAGE(K, BODY)                              \
+    do {                                               \
+        HIP_OK(hipEventRecord(e0[K], st));             \
+        BODY;                                          \
+        HIP_OK(hipEventRecord(e1[K], st));             \
+        ran[K] = true;                                 \
+    } while (0)
+        auto sort_stages = [&]() -> int {
+            if (s->sorted) return PC_OK;
+            if (!s->binned) {
+                PC_STAGE(PC_STAGE_BIN, launch_bin(s->sp, s->b, 0, blk, st));
+                s->binned = 1;
+            }
+            PC_STAGE(PC_STAGE_SCAN, launch_scan(s->b, s->d.bins_total, (int32_t)s->d.n_total, st));
             s->binned = 0;
-        }
-        HIP_OK(hipEventRecord(ev[PC_STAGE_SCATTER], st));
-        if (!was_sorted) {
-            launch_scatter(s->sp, s->b, 0, 1, blk, st);
+            PC_STAGE(PC_STAGE_SCATTER, launch_scatter(s->sp, s->b, 0, 1, blk, st));
             s->sorted_src = 1;
-        }
-        HIP_OK(hipEventRecord(ev[PC_STAGE_STABLE], st));
-        if (!was_sorted && s->cfg.deterministic) {
-            launch_stable(s->sp, s->b, 1, 2, blk, st);
-            s->sorted_src = 2;
-        }
-        s->sorted = 1;
-        HIP_OK(hipEventRecord(ev[PC_STAGE_UPDATE], st));
-        launch_update(s->sp, s->b, s->sorted_src, 0, s->cur_c, blk, st);
-        HIP_OK(hipEventRecord(ev[PC_STAGE_DEPOSIT], st));
-        if (s->chem_fused) {
-            // one kernel for both: its time is reported under the deposit
-            enqueue_chem(s, st);
-            HIP_OK(hipEventRecord(ev[PC_STAGE_PDE], st));
-        } else {
-            launch_deposit(s->sp, s->b, 0, st);
-            HIP_OK(hipEventRecord(ev[PC_STAGE_PDE], st));
-            enqueue_pde(s, st);
-        }
-        launch_step_inc(s->b, st);
+            if (s->cfg.deterministic) {
+                PC_STAGE(PC_STAGE_STABLE, launch_stable(s->sp, s->b, 1, 2, blk, st));
+                s->sorted_src = 2;
+            }
+            s->sorted = 1;
+            return PC_OK;
+        };
+        int rc = sort_stages();
+        if (rc) return rc;
+        PC_STAGE(PC_STAGE_UPDATE, launch_update(s->sp, s->b, s->sorted_src, 0, s->cur_c, blk, st));
         s->binned = 1;
         s->sorted = 0;
-        HIP_OK(hipEventRecord(ev[PC_N_STAGES], st));
+        if (s->d.kde) {
+            rc = sort_stages();
+            if (rc) return rc;
+            PC_STAGE(PC_STAGE_DEPOSIT, launch_kde(s->sp, s->b, s->sorted_src, st));
+            PC_STAGE(PC_STAGE_PDE, enqueue_pde(s, st));
+        } else if (s->chem_fused) {
+            // one kernel for both: its time is reported under the deposit
+            PC_STAGE(PC_STAGE_DEPOSIT, enqueue_chem(s, st));
+        } else {
+            PC_STAGE(PC_STAGE_DEPOSIT, launch_deposit(s->sp, s->b, 0, st));
+            PC_STAGE(PC_STAGE_PDE, enqueue_pde(s, st));
+        }
+#undef PC_STAGE
+        launch_step_inc(s->b, st);
         s->host_step += 1;
-        HIP_OK(hipEventSynchronize(ev[PC_N_STAGES]));
+        HIP_OK(hipStreamSynchronize(st));
         for (int k = 0; k < PC_N_STAGES; ++k) {
+            if (!ran[k]) continue;
             float ms = 0.f;
-            HIP_OK(hipEventElapsedTime(&ms, ev[k], ev[k + 1]));
+            HIP_OK(hipEventElapsedTime(&ms, e0[k], e1[k]));
             acc[k] += ms;
         }
     }
-    for (int k = 0; k <= PC_N_STAGES; ++k) (void)hipEventDestroy(ev[k]);
+    for (int k = 0; k < PC_N_STAGES; ++k) {
+        (void)hipEventDestroy(e0[k]);
+        (void)hipEventDestroy(e1[k]);
+    }
     for (int k = 0; k < PC_N_STAGES; ++k) stage_ms[k] = acc[k] / n_steps;
     HIP_OK(hipGetLastError());
     return PC_OK;
@@ -769,7 +824,7 @@ int pc_info(pc_sim *s, pc_info_t *info) {
     info->block = s->d.block;
     info->bin_side = s->d.bin_side;
     info->workspace_bytes = s->lay.total;
-    info->deposit_path = s->chem_fused ? 3 : (s->sp.deposit_agg ? 1 : 2);
+    info->deposit_path = s->d.kde ? 4 : s->chem_fused ? 3 : (s->sp.deposit_agg ? 1 : 2);
     info->reserved = 0;
     return PC_OK;
 }
@@ -832,6 +887,7 @@ int pc_adjoint_segment(pc_sim *s, const float *lamX_in_dev, const float *lamC_in
     if (n_steps < 1 || n_steps > s->seg_steps)
         return fail(PC_EINVAL, "n_steps must be in [1, segment capacity]");
     if (s->d.has_react) return fail(PC_ENOTSUP, "reverse mode over type switches is not built");
+    if (s->d.kde) return fail(PC_ENOTSUP, "reverse mode of the kernel density deposit is not built");
     hipStream_t st = s->stream;
     const Buffers &b = s->b;
     const size_t XD = (size_t)s->d.n_total * s->d.dim;

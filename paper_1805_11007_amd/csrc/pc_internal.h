@@ -49,6 +49,13 @@ struct StepParams {
     int32_t react_to[kMaxSpecies];          // -1: no switch
     float react_p[kMaxSpecies];             // react_rate dt rounded up to float
     float react_cdt[kMaxSpecies];           // react_rate_c dt
+    // Gaussian kernel density deposit (bandwidth eps_s = diameter_s)
+    int32_t kde;
+    float kde_R;                            // largest truncation radius
+    float kde_R2[kMaxSpecies];              // (kde_radius eps_s)^2
+    float kde_norm[kMaxSpecies];            // (2 pi eps_s^2)^(-dim/2)
+    float kde_inv2e2[kMaxSpecies];          // 1 / (2 eps_s^2)
+    float src_f[kMaxSpecies], upt_f[kMaxSpecies];
 };
 
 struct PdeParams {
@@ -58,6 +65,7 @@ struct PdeParams {
     float fx_to_density;   // 2^-32 / h^dim
     float inv_hd;          // 1 / h^dim
     int32_t has_uptake;
+    int32_t kde;           // 1: sources are kernel-density pairs (sigma, upsilon)
 };
 
 // Flag bits latched by kernels in the device flag word.
@@ -131,6 +139,7 @@ void launch_pde(const PdeParams &q, const Buffers &b, int cin, int cout, int las
                 hipStream_t s);
 void launch_step_inc(const Buffers &b, hipStream_t s);
 void launch_zero_u32(uint32_t *d, int64_t n, hipStream_t s);
+void launch_kde(const StepParams &p, const Buffers &b, int src, hipStream_t s);
 size_t chem_inst_lds_bytes(const PdeParams &q);
 void launch_chem_inst(const StepParams &p, const PdeParams &q, const Buffers &b, int src, int cur,
                       int n_sub, hipStream_t s);

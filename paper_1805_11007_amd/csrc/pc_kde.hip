@@ -1,0 +1,102 @@
+// Gaussian kernel density deposit (Sect. 2.3; the density loop of Sect. 3.5
+// gathers, for every grid node, the agents within a cutoff of it): for node
+// p_l, sigma_l = sum_i source_{s_i} K_{eps_i}(p_l - X_i) and upsilon_l the
+// same with uptake, K_eps(x) = (2 pi eps^2)^(-dim/2) exp(-|x|^2 / (2 eps^2)),
+// eps = the agent's species diameter, over |p_l - X_i| < kde_radius * eps.
+// One thread per node walks the cell-list bins that overlap the ball of the
+// largest radius around it, row by row (x-adjacent bins are contiguous in
+// the sorted agent array), so the gather needs no atomics and sums in a
+// fixed order.
+#include <hip/hip_runtime.h>
+
+#include "pc_device.h"
+
+namespace pc {
+
+template <int DIM>
+__global__ void __launch_bounds__(256)
+k_kde(StepParams p, const InstInfo *__restrict__ inst, const float4 *__restrict__ Ps,
+      const uint32_t *__restrict__ start, float2 *__restrict__ dens) {
+    __shared__ float tR2[kMaxSpecies], tnorm[kMaxSpecies], tinv[kMaxSpecies];
+    __shared__ float tsrc[kMaxSpecies], tupt[kMaxSpecies];
+    if (threadIdx.x < (unsigned)p.n_species) {
+        const int s = threadIdx.x;
+        tR2[s] = p.kde_R2[s];
+        tnorm[s] = p.kde_norm[s];
+        tinv[s] = p.kde_inv2e2[s];
+        tsrc[s] = p.src_f[s];
+        tupt[s] = p.upt_f[s];
+    }
+    __syncthreads();
+    const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int G = p.nodes_per_inst;
+    if (l >= (int64_t)G * p.n_inst) return;
+    const int n = p.grid_n, nb = p.nb;
+    const int k = (int)(l / G);
+    const int loc = (int)(l - (int64_t)k * G);
+    const int ic[3] = {loc % n, (loc / n) % n, DIM == 3 ? loc / (n * n) : 0};
+    const float pc[3] = {ic[0] * p.h, ic[1] * p.h, DIM == 3 ? ic[2] * p.h : 0.0f};
+    const uint32_t bb = inst[k].bin_base;
+    // bins overlapping [p - R, p + R] on each axis
+    int lo[3] = {0, 0, 0}, cnt[3] = {1, 1, 1};
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        int b0 = (int)floorf((pc[a] - p.kde_R) * p.inv_bin);
+        int b1 = (int)floorf((pc[a] + p.kde_R) * p.inv_bin);
+        if (p.periodic) {
+            cnt[a] = min(b1 - b0 + 1, nb);
+            lo[a] = ((b0 % nb) + nb) % nb;
+        } else {
+            b0 = max(b0, 0);
+            b1 = min(b1, nb - 1);
+            lo[a] = b0;
+            cnt[a] = b1 - b0 + 1;
+        }
+    }
+    float sig = 0.0f, ups = 0.0f;
+    for (int cz = 0; cz < cnt[2]; ++cz) {
+        const int bz = DIM == 3 ? (lo[2] + cz) % nb : 0;
+        for (int cy = 0; cy < cnt[1]; ++cy) {
+            const int by = (lo[1] + cy) % nb;
+            const uint32_t row = bb + (uint32_t)(nb * (by + nb * bz));
+            // the x range as at most two contiguous runs of bins
+            const int x0 = lo[0], x1 = lo[0] + cnt[0];
+            const int runs = x1 > nb ? 2 : 1;
+            for (int r = 0; r < runs; ++r) {
+                const int a0 = r == 0 ? x0 : 0;
+                const int a1 = r == 0 ? min(x1, nb) : x1 - nb;
+                const uint32_t j0 = start[row + a0], j1 = start[row + a1];
+                for (uint32_t j = j0; j < j1; ++j) {
+                    const float4 q = Ps[j];
+                    float dx = pc[0] - q.x, dy = pc[1] - q.y, dz = DIM == 3 ? pc[2] - q.z : 0.0f;
+                    if (p.periodic) {
+                        dx = dx > p.halfL ? dx - p.L : (dx < -p.halfL ? dx + p.L : dx);
+                        dy = dy > p.halfL ? dy - p.L : (dy < -p.halfL ? dy + p.L : dy);
+                        if (DIM == 3) dz = dz > p.halfL ? dz - p.L : (dz < -p.halfL ? dz + p.L : dz);
+                    }
+                    float r2 = dx * dx + dy * dy;
+                    if (DIM == 3) r2 += dz * dz;
+                    const int s = species_of(q.w);
+                    if (r2 < tR2[s]) {
+                        const float w = tnorm[s] * expf(-r2 * tinv[s]);
+                        sig = fmaf(tsrc[s], w, sig);
+                        ups = fmaf(tupt[s], w, ups);
+                    }
+                }
+            }
+        }
+    }
+    dens[l] = make_float2(sig, ups);
+}
+
+void launch_kde(const StepParams &p, const Buffers &b, int src, hipStream_t s) {
+    const int64_t total = (int64_t)p.nodes_per_inst * p.n_inst;
+    const dim3 g((unsigned)((total + 255) / 256)), t(256);
+    float2 *dens = reinterpret_cast<float2 *>(b.S_src);
+    if (p.dim == 2)
+        hipLaunchKernelGGL(k_kde<2>, g, t, 0, s, p, b.inst, b.P[src], b.start, dens);
+    else
+        hipLaunchKernelGGL(k_kde<3>, g, t, 0, s, p, b.inst, b.P[src], b.start, dens);
+}
+
+}  // namespace pc

@@ -266,12 +266,14 @@ k_update(StepParams p, const InstInfo *__restrict__ inst, const float4 *__restri
 }
 
 // Forward-Euler update of node l with the centred Laplacian (periodic wrap
-// or mirror ghost nodes); sigma and upsilon are the number densities of the
-// fixed-point deposits (divided by the node control volume).
+// or mirror ghost nodes) and the source / uptake densities sigma, upsilon
+// at the node.  The particle-in-cell densities are the fixed-point deposits
+// divided by the node control volume (the wrapper below); the kernel
+// density estimate gives densities directly.
 template <int DIM>
-__device__ __forceinline__ float pde_node(const PdeParams &q, const float *__restrict__ cb,
-                                          const int ic[3], unsigned long long sS,
-                                          unsigned long long sU, uint32_t &flag) {
+__device__ __forceinline__ float pde_node_dens(const PdeParams &q, const float *__restrict__ cb,
+                                               const int ic[3], float sigma, float ups,
+                                               uint32_t &flag) {
     const int n = q.grid_n, nn = n * n;
     auto nbr = [&](int i, int off) {
         const int r = i + off;
@@ -289,19 +291,27 @@ __device__ __forceinline__ float pde_node(const PdeParams &q, const float *__res
         diag = 6.0f;
     }
     lap = (lap - diag * c0) * q.inv_h2;
-    float inv_v = 1.0f;
-    if (!q.periodic) {
-        if (ix == 0 || ix == n - 1) inv_v *= 2.0f;
-        if (iy == 0 || iy == n - 1) inv_v *= 2.0f;
-        if (DIM == 3 && (iz == 0 || iz == n - 1)) inv_v *= 2.0f;
-    }
-    const float dens = q.fx_to_density * inv_v;
-    const float sigma = (float)sS * dens;
-    const float ups = q.has_uptake ? (float)sU * dens : 0.0f;
     const float cn = c0 + q.dts * (q.D_c * lap + sigma - ups * c0 - q.gamma * c0);
     if (!isfinite(cn)) flag |= FLAG_NONFINITE;
     if (q.dts * (q.gamma + ups) >= 1.0f) flag |= FLAG_WARN_POSITIVITY;
     return cn;
+}
+
+template <int DIM>
+__device__ __forceinline__ float pde_node(const PdeParams &q, const float *__restrict__ cb,
+                                          const int ic[3], unsigned long long sS,
+                                          unsigned long long sU, uint32_t &flag) {
+    const int n = q.grid_n;
+    float inv_v = 1.0f;
+    if (!q.periodic) {
+        if (ic[0] == 0 || ic[0] == n - 1) inv_v *= 2.0f;
+        if (ic[1] == 0 || ic[1] == n - 1) inv_v *= 2.0f;
+        if (DIM == 3 && (ic[2] == 0 || ic[2] == n - 1)) inv_v *= 2.0f;
+    }
+    const float dens = q.fx_to_density * inv_v;
+    const float sigma = (float)sS * dens;
+    const float ups = q.has_uptake ? (float)sU * dens : 0.0f;
+    return pde_node_dens<DIM>(q, cb, ic, sigma, ups, flag);
 }
 
 // Piecewise-linear deposit (fixed point, 2^-32 units) of every agent at its
@@ -494,7 +504,9 @@ k_chem_inst(StepParams p, PdeParams q, const InstInfo *__restrict__ inst,
 
 // PDE substep, one thread per node; the last substep of a step clears the
 // deposits for the next step.
-template <int DIM>
+// KDE: the source array holds (sigma, upsilon) float pairs, rewritten by
+// every step's density gather, so nothing is cleared.
+template <int DIM, bool KDE>
 __global__ void __launch_bounds__(256)
 k_pde(PdeParams q, const float *__restrict__ cin, float *__restrict__ cout,
       unsigned long long *__restrict__ Ssrc, unsigned long long *__restrict__ Supt, int last,
@@ -507,6 +519,12 @@ k_pde(PdeParams q, const float *__restrict__ cin, float *__restrict__ cout,
     const int loc = (int)(l - k * G);
     const int ic[3] = {loc % n, (loc / n) % n, DIM == 3 ? loc / (n * n) : 0};
     uint32_t flag = 0;
+    if (KDE) {
+        const float2 su = reinterpret_cast<const float2 *>(Ssrc)[l];
+        cout[l] = pde_node_dens<DIM>(q, cin + k * G, ic, su.x, su.y, flag);
+        if (flag) atomicOr(flags, flag);
+        return;
+    }
     const unsigned long long sS = Ssrc[l], sU = q.has_uptake ? Supt[l] : 0ull;
     cout[l] = pde_node<DIM>(q, cin + k * G, ic, sS, sU, flag);
     if (last) {
@@ -754,21 +772,30 @@ void launch_chem_inst(const StepParams &p, const PdeParams &q, const Buffers &b,
 void launch_pde(const PdeParams &q, const Buffers &b, int cin, int cout, int last,
                 hipStream_t s) {
     const dim3 g(grid_for(q.n_nodes_total, 256)), t(256);
+    if (q.kde) {
+        if (q.dim == 2)
+            hipLaunchKernelGGL((k_pde<2, true>), g, t, 0, s, q, b.c[cin], b.c[cout], b.S_src,
+                               b.S_upt, last, b.flags);
+        else
+            hipLaunchKernelGGL((k_pde<3, true>), g, t, 0, s, q, b.c[cin], b.c[cout], b.S_src,
+                               b.S_upt, last, b.flags);
+        return;
+    }
     if (q.dim == 2)
-        hipLaunchKernelGGL(k_pde<2>, g, t, 0, s, q, b.c[cin], b.c[cout], b.S_src, b.S_upt, last,
-                           b.flags);
+        hipLaunchKernelGGL((k_pde<2, false>), g, t, 0, s, q, b.c[cin], b.c[cout], b.S_src,
+                           b.S_upt, last, b.flags);
     else
-        hipLaunchKernelGGL(k_pde<3>, g, t, 0, s, q, b.c[cin], b.c[cout], b.S_src, b.S_upt, last,
-                           b.flags);
+        hipLaunchKernelGGL((k_pde<3, false>), g, t, 0, s, q, b.c[cin], b.c[cout], b.S_src,
+                           b.S_upt, last, b.flags);
 }
 
 void launch_pde_ptr(const PdeParams &q, const float *cin, float *cout, unsigned long long *Ssrc,
                     unsigned long long *Supt, int last, uint32_t *flags, hipStream_t s) {
     const dim3 g(grid_for(q.n_nodes_total, 256)), t(256);
     if (q.dim == 2)
-        hipLaunchKernelGGL(k_pde<2>, g, t, 0, s, q, cin, cout, Ssrc, Supt, last, flags);
+        hipLaunchKernelGGL((k_pde<2, false>), g, t, 0, s, q, cin, cout, Ssrc, Supt, last, flags);
     else
-        hipLaunchKernelGGL(k_pde<3>, g, t, 0, s, q, cin, cout, Ssrc, Supt, last, flags);
+        hipLaunchKernelGGL((k_pde<3, false>), g, t, 0, s, q, cin, cout, Ssrc, Supt, last, flags);
 }
 
 void launch_step_inc(const Buffers &b, hipStream_t s) {

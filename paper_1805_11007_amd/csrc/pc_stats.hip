@@ -52,15 +52,40 @@ k_species_hist(int n_total, int n_species, const float4 *__restrict__ P, int m, 
     }
 }
 
-// Mean over instances of the field, node by node, summed in instance order
-// in FP64 (one thread per node; every instance step is a coalesced row).
-__global__ void k_field_mean(const float *__restrict__ c, int n_inst, int64_t G,
-                             float *__restrict__ out) {
-    const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (l >= G) return;
+// Mean over instances of the field, node by node, in FP64.  A work-group
+// owns 64 consecutive nodes (one per lane, so every load is a coalesced row
+// segment); its W waves split the instances (wave w takes k = w, w + W, ...
+// in ascending order) and their partial sums are added in wave order, so
+// the result does not depend on scheduling.
+constexpr int kMeanWaves = 16;
+
+__global__ void __launch_bounds__(64 * kMeanWaves)
+k_field_mean(const float *__restrict__ c, int n_inst, int64_t G, float *__restrict__ out) {
+    __shared__ double part[kMeanWaves][64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t l = (int64_t)blockIdx.x * 64 + lane;
     double acc = 0.0;
-    for (int k = 0; k < n_inst; ++k) acc += (double)c[(int64_t)k * G + l];
-    out[l] = (float)(acc / n_inst);
+    if (l < G) {
+        int k = wv;
+        for (; k + 3 * kMeanWaves < n_inst; k += 4 * kMeanWaves) {
+            const float a0 = c[(int64_t)k * G + l];
+            const float a1 = c[(int64_t)(k + kMeanWaves) * G + l];
+            const float a2 = c[(int64_t)(k + 2 * kMeanWaves) * G + l];
+            const float a3 = c[(int64_t)(k + 3 * kMeanWaves) * G + l];
+            acc += (double)a0;
+            acc += (double)a1;
+            acc += (double)a2;
+            acc += (double)a3;
+        }
+        for (; k < n_inst; k += kMeanWaves) acc += (double)c[(int64_t)k * G + l];
+    }
+    part[wv][lane] = acc;
+    __syncthreads();
+    if (wv == 0 && l < G) {
+        double s = 0.0;
+        for (int w = 0; w < kMeanWaves; ++w) s += part[w][lane];
+        out[l] = (float)(s / n_inst);
+    }
 }
 
 constexpr int kHistLdsBytes = 64 * 1024;
@@ -100,8 +125,8 @@ int launch_species_hist(const StepParams &p, const Buffers &b, int src, int m, f
 }
 
 void launch_field_mean(const float *c, int n_inst, int64_t G, float *out, hipStream_t st) {
-    hipLaunchKernelGGL(k_field_mean, dim3((unsigned)((G + 255) / 256)), dim3(256), 0, st, c,
-                       n_inst, G, out);
+    hipLaunchKernelGGL(k_field_mean, dim3((unsigned)((G + 63) / 64)), dim3(64 * kMeanWaves), 0,
+                       st, c, n_inst, G, out);
 }
 
 }  // namespace pc

@@ -54,6 +54,8 @@ class ModelSpec:
     deterministic: bool = False
     block: int = 0
     deposit_mode: int = 0    # 0 auto, 1 LDS-aggregated, 2 direct atomics, 3 fused per instance
+    deposit_kernel: int = 0  # 0 particle-in-cell, 1 Gaussian kernel density (Sect. 2.3)
+    kde_radius: float = 0.0  # kernel truncation in bandwidths (0: 3)
 
     @classmethod
     def from_workload(cls, w, **over) -> "ModelSpec":
@@ -65,7 +67,8 @@ class ModelSpec:
                for i in w.instances]
         kw = dict(dim=w.dim, periodic=w.periodic, L=w.L, grid_n=w.grid_n, dt=w.dt, k=w.k,
                   D_c=w.D_c, gamma=w.gamma, species=sp, instances=ins,
-                  pde_substeps=w.pde_substeps)
+                  pde_substeps=w.pde_substeps, deposit_kernel=getattr(w, "deposit_kernel", 0),
+                  kde_radius=getattr(w, "kde_radius", 0.0))
         kw.update(over)
         return cls(**kw)
 
@@ -85,6 +88,8 @@ class ModelSpec:
         cfg.block = self.block
         cfg.bin_order = 0
         cfg.deposit_mode = self.deposit_mode
+        cfg.deposit_kernel = self.deposit_kernel
+        cfg.kde_radius = self.kde_radius
         ns = len(self.species)
         sp = (LB.PcSpecies * max(ns, 1))()
         for k, s in enumerate(self.species):

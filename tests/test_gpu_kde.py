@@ -1,0 +1,123 @@
+"""Gaussian kernel density deposit on the GPU (per-node gather over the cell
+list of X^{n+1}) against the FP64 oracle, through the C ABI.
+
+Bars: positions as the plain step (1e-5 L per step).  The field after a
+step lies within 1e-5 max|c| of the oracle's field bracketed by truncation
+radii kde_radius (1 -/+ 1e-5): a node-agent pair at the truncation radius
+may be decided either way in float32.  Graph replay equals eager replay
+bit for bit; deterministic mode repeats bit for bit.
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from gpu_helpers import make_sim, pos_err
+
+pytestmark = pytest.mark.gpu
+
+
+def _kde(w, kappa=3.0):
+    return dataclasses.replace(w, deposit_kernel=1, kde_radius=kappa)
+
+
+def _case(cfg, n, g, kappa=3.0):
+    if cfg == 4:
+        w = W.scaled(W.config(4), n_agents=list(np.random.default_rng(9).integers(1, 900, 6)),
+                     grid_n=g)
+    else:
+        w = W.scaled(W.config(cfg), n_agents=n, grid_n=g)
+    return _kde(w, kappa)
+
+
+def _bracket(w, inp, steps):
+    lo = oracle.run_workload(dataclasses.replace(w, kde_radius=w.kde_radius * (1 - 1e-5)), inp,
+                             steps)
+    hi = oracle.run_workload(dataclasses.replace(w, kde_radius=w.kde_radius * (1 + 1e-5)), inp,
+                             steps)
+    return lo, hi
+
+
+def _within(c, lo, hi, tol):
+    a, b = np.minimum(lo, hi), np.maximum(lo, hi)
+    return np.all(c >= a - tol) and np.all(c <= b + tol)
+
+
+CASES = [(1, 3001, 37, 3.0), (2, 20011, 129, 3.0), (3, 8000, 32, 3.0), (5, 6000, 48, 3.0),
+         (4, None, 24, 3.0), (1, 3001, 37, 1.5), (2, 5000, 65, 6.0)]
+
+
+@pytest.mark.parametrize("cfg,n,g,kappa", CASES)
+def test_one_step_matches_oracle(cfg, n, g, kappa):
+    w = _case(cfg, n, g, kappa)
+    inp = W.make_inputs(w)
+    sim = make_sim(w, inp)
+    assert sim.info["deposit_path"] == 4
+    sim.step(1)
+    x, c, _ = sim.get_state()
+    (Xlo, clo), (Xhi, chi_) = _bracket(w, inp, 1)
+    assert pos_err(x.cpu().numpy(), Xlo, w.L, w.periodic) <= 1e-5
+    scale = max(np.abs(clo).max(), 1e-30)
+    assert _within(c.cpu().numpy().astype(np.float64), clo, chi_, 1e-5 * scale)
+
+
+@pytest.mark.parametrize("cfg,n,g,steps", [(1, 2000, 37, 10), (2, 8000, 65, 6)])
+def test_trajectory_matches_oracle(cfg, n, g, steps):
+    w = _case(cfg, n, g)
+    inp = W.make_inputs(w)
+    sim = make_sim(w, inp)
+    sim.use_graph(True)
+    sim.step(steps)
+    x, c, _ = sim.get_state()
+    (Xlo, clo), (Xhi, chi_) = _bracket(w, inp, steps)
+    assert pos_err(x.cpu().numpy(), Xlo, w.L, w.periodic) <= 1e-5 * steps
+    scale = max(np.abs(clo).max(), 1e-30)
+    assert _within(c.cpu().numpy().astype(np.float64), clo, chi_, 1e-5 * steps * scale)
+
+
+def test_graph_equals_eager_and_deterministic_repeats():
+    w = _case(2, 6000, 65)
+    inp = W.make_inputs(w)
+    runs = []
+    for graph in (False, True, True):
+        sim = make_sim(w, inp, deterministic=True)
+        sim.use_graph(graph)
+        sim.step(9)
+        sim.sync()
+        x, c, st = sim.get_state()
+        assert st == 9
+        runs.append((x.cpu().numpy(), c.cpu().numpy()))
+        sim.close()
+    for x, c in runs[1:]:
+        assert np.array_equal(x, runs[0][0]) and np.array_equal(c, runs[0][1])
+
+
+def test_profile_and_set_state_round_trip():
+    import torch
+    w = _case(1, 3000, 37)
+    inp = W.make_inputs(w)
+    sim = make_sim(w, inp)
+    prof = sim.profile_steps(3)
+    assert prof["deposit"] > 0 and prof["pde"] > 0 and prof["update"] > 0
+    sim.set_state(torch.from_numpy(inp["x0"]), torch.from_numpy(inp["c0"]), 0)
+    sim.step(1)
+    x, c, _ = sim.get_state()
+    (Xlo, clo), (_, chi_) = _bracket(w, inp, 1)
+    assert pos_err(x.cpu().numpy(), Xlo, w.L, w.periodic) <= 1e-5
+    assert _within(c.cpu().numpy().astype(np.float64), clo, chi_, 1e-5 * np.abs(clo).max())
+
+
+def test_rejections():
+    import torch
+    from paper_1805_11007_amd import PcError
+    w = _case(5, 2000, 32)
+    inp = W.make_inputs(w)
+    with pytest.raises(PcError):
+        make_sim(w, inp, deposit_mode=3)
+    with pytest.raises(PcError):
+        make_sim(w, inp, kde_radius=60.0)   # 60 * 0.01 >= L / 2
+    sim = make_sim(w, inp, adjoint_steps=2)
+    with pytest.raises(PcError):
+        sim.adjoint_segment(torch.zeros(w.n_total, 2), torch.zeros(w.n_nodes), 1)
