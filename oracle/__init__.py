@@ -56,7 +56,8 @@ class Params(C.Structure):
                 ("react_rate", C.c_double * MAX_SPECIES),
                 ("react_rate_c", C.c_double * MAX_SPECIES), ("seed", C.c_uint64),
                 ("inst", C.c_uint32), ("chi_scale", C.c_double),
-                ("deposit_kernel", C.c_int32), ("kde_radius", C.c_double)]
+                ("deposit_kernel", C.c_int32), ("kde_radius", C.c_double),
+                ("potential", C.c_int32), ("tamed", C.c_int32), ("pot_range", C.c_double)]
 
 
 _lib = None
@@ -88,6 +89,7 @@ def lib():
             "orc_pde": ([P, vp, vp, vp], None),
             "orc_pde_density": ([P, vp, vp, vp], None),
             "orc_deposit_kde": ([P, i64, vp, vp, vp, vp], None),
+            "orc_hs_correct": ([P, i64, vp, vp], None),
             "orc_react": ([P, i64, vp, vp, vp, vp, C.c_uint32, vp], None),
             "orc_step": ([P, i64, vp, vp, vp, vp, vp], None),
             "orc_run": ([P, i64, vp, vp, vp, vp, vp, C.c_int], None),
@@ -146,6 +148,9 @@ def params(w, inst: int = 0, mode: int = 1, **over) -> Params:
     p.mode = mode
     p.deposit_kernel = getattr(w, "deposit_kernel", 0)
     p.kde_radius = getattr(w, "kde_radius", 3.0)
+    p.potential = getattr(w, "potential", 0)
+    p.tamed = 1 if getattr(w, "tamed", False) else 0
+    p.pot_range = getattr(w, "pot_range", 3.0)
     for k, v in over.items():
         setattr(p, k, v)
     return p
@@ -262,6 +267,13 @@ def deposit_kde(p: Params, X: np.ndarray, sp: np.ndarray):
     ups = np.empty(n_nodes(p), np.float64)
     lib().orc_deposit_kde(C.byref(p), len(X), _ptr(X), _ptr(sp), _ptr(sig), _ptr(ups))
     return sig, ups
+
+
+def hs_correct(p: Params, X: np.ndarray, sp: np.ndarray) -> np.ndarray:
+    """Hard-sphere overlap correction of positions X (returns a new array)."""
+    X = _c(X, np.float64).copy()
+    lib().orc_hs_correct(C.byref(p), len(X), _ptr(X), _ptr(_c(sp, np.uint8)))
+    return X
 
 
 def pde_density(p: Params, c: np.ndarray, sigma: np.ndarray, ups: np.ndarray) -> np.ndarray:

@@ -46,6 +46,9 @@ typedef struct {
     double chi_scale;     /* per-instance multiplier of chi */
     int32_t deposit_kernel;  /* 0: particle-in-cell ; 1: Gaussian kernel density */
     double kde_radius;    /* kernel truncation radius in units of the bandwidth */
+    int32_t potential;    /* 0: harmonic ; 1: exponential ; 2: hard spheres */
+    int32_t tamed;        /* 1: tamed Euler drift for the pair forces (eq. sde_ETamed) */
+    double pot_range;     /* exponential potential cut at pot_range * d_ij */
 } orc_params;
 
 int orc_num_threads(void) {
@@ -142,10 +145,30 @@ static double orc_contact(const orc_params *p, int si, int sj) {
     return 0.5 * (p->diam[si] + p->diam[sj]);
 }
 
+/* Interaction range of a pair: the contact distance, or pot_range times it
+ * for the exponential potential (which has no natural end). */
+static double orc_pair_cut(const orc_params *p, int si, int sj) {
+    const double d = orc_contact(p, si, sj);
+    return p->potential == 1 ? p->pot_range * d : d;
+}
+
 static double orc_max_cutoff(const orc_params *p) {
     double m = 0.0;
     for (int s = 0; s < p->n_species; ++s) if (p->diam[s] > m) m = p->diam[s];
-    return m;
+    return p->potential == 1 ? p->pot_range * m : m;
+}
+
+/* Pair force on i from j at distance r > 0 inside the range, as the factor g
+ * of F_i -= g (X_j - X_i):
+ *   harmonic    u = (k/2)(d - r)^2 :  g = k (d - r) / r;
+ *   exponential u = k exp(-r/d)    :  g = (k/d) exp(-r/d) / r (the soft
+ *               potential of Sect. 4 with length scale d = the contact
+ *               distance and strength k);
+ *   hard spheres have no force (overlaps are corrected after the step). */
+static double orc_pair_g(const orc_params *p, double dij, double r) {
+    if (p->potential == 0) return p->k * (dij - r) / r;
+    if (p->potential == 1) return (p->k / dij) * exp(-r / dij) / r;
+    return 0.0;
 }
 
 /* A plain uniform-bin index of the agents, used only to enumerate
@@ -247,10 +270,10 @@ static void orc_candidates(int dim, int periodic, int64_t n, const double *X, co
     qsort(out->v, (size_t)out->n, sizeof(int64_t), cmp_i64);
 }
 
-/* Pair repulsion for every agent: F_i = -sum_j k (d_ij - r) dx / r over
- * neighbours with r > 0 (the r > 0 guard of the interaction loop in
- * Sect. 3.2).  Harmonic soft-sphere force, unit mobility: F = -grad_i u with
- * u = (k/2)(d - r)^2 for r < d (eqs. sde_alpha, sde_beta). */
+/* Pair repulsion for every agent: F_i = -sum_j g(r) dx over neighbours
+ * (r inside the pair's range) with r > 0 (the r > 0 guard of the
+ * interaction loop in Sect. 3.2), dx = X_j - X_i; unit mobility, F = -grad_i
+ * u (eqs. sde_alpha, sde_beta) with the potential of orc_pair_g. */
 void orc_forces(const orc_params *p, int64_t n, const double *X, const uint8_t *sp, double *F) {
     const int dim = p->dim;
     orc_bins B;
@@ -271,11 +294,13 @@ void orc_forces(const orc_params *p, int64_t n, const double *X, const uint8_t *
                     if (p->periodic) dx[a] = orc_min_image(dx[a], p->L);
                     r2 += dx[a] * dx[a];
                 }
-                double dij = orc_contact(p, sp[i], sp[j]);
-                if (!(r2 < dij * dij)) continue;
+                const double cut = orc_pair_cut(p, sp[i], sp[j]);
+                if (!(r2 < cut * cut)) continue;
                 double r = sqrt(r2);
-                if (r > 0.0)
-                    for (int a = 0; a < dim; ++a) f[a] -= p->k * (dij - r) * dx[a] / r;
+                if (r > 0.0) {
+                    const double g = orc_pair_g(p, orc_contact(p, sp[i], sp[j]), r);
+                    for (int a = 0; a < dim; ++a) f[a] -= g * dx[a];
+                }
             }
             for (int a = 0; a < dim; ++a) F[i * dim + a] = f[a];
         }
@@ -307,11 +332,13 @@ void orc_forces_subset(const orc_params *p, int64_t n, const double *X, const ui
                     if (p->periodic) dx[a] = orc_min_image(dx[a], p->L);
                     r2 += dx[a] * dx[a];
                 }
-                double dij = orc_contact(p, sp[i], sp[j]);
-                if (!(r2 < dij * dij)) continue;
+                const double cut = orc_pair_cut(p, sp[i], sp[j]);
+                if (!(r2 < cut * cut)) continue;
                 double r = sqrt(r2);
-                if (r > 0.0)
-                    for (int a = 0; a < dim; ++a) f[a] -= p->k * (dij - r) * dx[a] / r;
+                if (r > 0.0) {
+                    const double g = orc_pair_g(p, orc_contact(p, sp[i], sp[j]), r);
+                    for (int a = 0; a < dim; ++a) f[a] -= g * dx[a];
+                }
             }
             for (int a = 0; a < dim; ++a) F[q * dim + a] = f[a];
         }
@@ -659,6 +686,55 @@ void orc_drift(const orc_params *p, const double *c, int64_t n, const double *X,
  * of the step; type switching; boundary closure; deposit of the new
  * positions with the new types; PDE update of c (eq. pde_c); step + 1.
  * X, sp, c are updated in place; `ids` are the stable agent ids. */
+/* Hard-sphere overlap correction (Sect. 2.2): at the updated positions,
+ * every pair closer than its contact distance d_ij = (eps_i + eps_j)/2 is
+ * pushed apart along the line of centres by twice the penetration
+ * d_p = d_ij - r, agent i taking the share D_i / (D_i + D_j) (a pair of
+ * immobile agents does not move).  All corrections are computed from the
+ * same positions and summed per agent, then the boundary closure is
+ * applied again.  Reading: the text's share D_i / (D_i + D_j) is taken; the
+ * printed loop divides by the sum of the two species' coefficients, which
+ * equals it only for unlike pairs. */
+static double orc_boundary(const orc_params *p, double x);
+
+void orc_hs_correct(const orc_params *p, int64_t n, double *X, const uint8_t *sp) {
+    const int dim = p->dim;
+    double *Y = (double *)malloc(sizeof(double) * (size_t)(n * dim > 0 ? n * dim : 1));
+    memcpy(Y, X, sizeof(double) * (size_t)(n * dim));
+    orc_bins B;
+    int use_bins = p->mode == 1 && n > 0 &&
+                   orc_bins_build(&B, dim, p->periodic, p->L, orc_max_cutoff(p), n, Y);
+#pragma omp parallel
+    {
+        orc_list cand = {0, 0, 0};
+#pragma omp for schedule(dynamic, 256)
+        for (int64_t i = 0; i < n; ++i) {
+            double corr[3] = {0, 0, 0};
+            orc_candidates(dim, p->periodic, n, Y, use_bins ? &B : NULL, i, &cand);
+            for (int64_t t = 0; t < cand.n; ++t) {
+                int64_t j = cand.v[t];
+                double dx[3], r2 = 0.0;
+                for (int a = 0; a < dim; ++a) {
+                    dx[a] = Y[j * dim + a] - Y[i * dim + a];
+                    if (p->periodic) dx[a] = orc_min_image(dx[a], p->L);
+                    r2 += dx[a] * dx[a];
+                }
+                const double dij = orc_contact(p, sp[i], sp[j]);
+                if (!(r2 < dij * dij)) continue;
+                const double r = sqrt(r2), Ds = p->D[sp[i]] + p->D[sp[j]];
+                if (!(r > 0.0) || !(Ds > 0.0)) continue;
+                const double share = 2.0 * (dij - r) * p->D[sp[i]] / Ds;
+                for (int a = 0; a < dim; ++a) corr[a] -= share * dx[a] / r;
+            }
+            for (int a = 0; a < dim; ++a)
+                X[i * dim + a] = orc_boundary(p, Y[i * dim + a] + corr[a]);
+        }
+        free(cand.v);
+    }
+    if (use_bins) orc_bins_free(&B);
+    free(Y);
+}
+
 /* Fixed-step type switching (Sect. 2.1 and the reaction listing of
  * Sect. 3.4): during [t, t + dt) agent i of species s switches to
  * react_to[s] iff zeta < (react_rate[s] + react_rate_c[s] c(X_i)) dt, with
@@ -689,6 +765,16 @@ void orc_step(const orc_params *p, int64_t n, double *X, uint8_t *sp, const uint
     double *drift = (double *)malloc(sizeof(double) * (size_t)(n * dim > 0 ? n * dim : 1));
     uint8_t *nsp = (uint8_t *)malloc((size_t)(n > 0 ? n : 1));
     orc_forces(p, n, X, sp, F);
+    if (p->tamed) {
+        /* tamed Euler (eq. sde_ETamed): the pair drift f becomes
+         * f / (1 + |f| dt), so its step is below one in length */
+        for (int64_t i = 0; i < n; ++i) {
+            double nf = 0.0;
+            for (int a = 0; a < dim; ++a) nf += F[i * dim + a] * F[i * dim + a];
+            nf = sqrt(nf);
+            for (int a = 0; a < dim; ++a) F[i * dim + a] /= 1.0 + nf * p->dt;
+        }
+    }
     orc_drift(p, c, n, X, sp, drift);
     orc_react(p, n, X, sp, ids, c, *step, nsp);
 #pragma omp parallel for
@@ -701,6 +787,7 @@ void orc_step(const orc_params *p, int64_t n, double *X, uint8_t *sp, const uint
             X[i * dim + a] = orc_boundary(p, x);
         }
     }
+    if (p->potential == 2) orc_hs_correct(p, n, X, sp);  /* overlaps at X^{n+1}, old types */
     memcpy(sp, nsp, (size_t)n);  /* the deposit sees the switched types */
     double *Ss = (double *)malloc(sizeof(double) * (size_t)G);
     double *Su = (double *)malloc(sizeof(double) * (size_t)G);

@@ -78,6 +78,9 @@ class Workload:
     gen_seed: int = 1000
     deposit_kernel: int = 0  # 0: particle-in-cell ; 1: Gaussian kernel density (Sect. 2.3)
     kde_radius: float = 3.0  # kernel truncation radius in bandwidths
+    potential: int = 0       # 0 harmonic ; 1 exponential k exp(-r/d) ; 2 hard spheres
+    tamed: bool = False      # tamed Euler pair drift (eq. sde_ETamed)
+    pot_range: float = 3.0   # exponential potential cut at pot_range * d
 
     @property
     def n_total(self) -> int:
