@@ -221,6 +221,55 @@ def reaction_overhead_leg(steps: int = 500) -> dict:
     return out
 
 
+def kde_leg(steps: int = 100, sample_nodes: int = 4000) -> dict:
+    """The Gaussian kernel density deposit (bandwidth = diameter, truncated at
+    3 bandwidths) against the particle-in-cell deposit on the 100k-agent walls
+    workload and the 1M-agent 3D workload, graph replay.  The gather's work
+    is counted as kernel evaluations (node-agent pairs inside the radius),
+    estimated on the initial state from a random sample of nodes."""
+    import dataclasses
+    import numpy as np
+    import torch
+    from scipy.spatial import cKDTree
+    import workloads as W
+    from paper_1805_11007_amd import ModelSpec, Sim
+    out = {}
+    for cfg in (2, 3):
+        w = W.config(cfg)
+        inp = W.make_inputs(w)
+        x0, s0, c0 = (torch.from_numpy(inp[k]).cuda() for k in ("x0", "species0", "c0"))
+        r = {}
+        for name, dk in (("pic", 0), ("kde", 1)):
+            sim = Sim(ModelSpec.from_workload(w, deposit_kernel=dk, kde_radius=3.0), x0, s0, c0)
+            sim.use_graph(True)
+            sim.step(4)
+            sim.set_state(x0, c0, 0)
+            r[name + "_ms_per_step"] = _timed(lambda: sim.step(steps)) / steps
+            sim.sync()
+            sim.set_state(x0, c0, 0)
+            prof = sim.profile_steps(min(steps, 50))
+            r[name + "_deposit_ms"] = prof["deposit"]
+            r[name + "_pde_ms"] = prof["pde"]
+            sim.close()
+        # kernel evaluations per step: node-agent pairs within 3 diameters
+        rng = np.random.default_rng(0)
+        xs = W.node_coords(w)
+        G = w.grid_n ** w.dim
+        idx = rng.integers(0, G, sample_nodes)
+        coords = np.stack([xs[(idx // w.grid_n ** a) % w.grid_n] for a in range(w.dim)], 1)
+        X = inp["x0"].astype(np.float64)
+        tree = cKDTree(X, boxsize=w.L if w.periodic else None)
+        R = 3.0 * max(s.diameter for s in w.species)
+        cnt = np.array([len(v) for v in tree.query_ball_point(coords, R)])
+        evals = float(cnt.mean()) * G
+        r["kernel_evals_per_step"] = evals
+        r["kde_evals_per_s"] = evals / (r["kde_deposit_ms"] * 1e-3)
+        r["agents"] = w.n_total
+        r["nodes"] = G
+        out[w.name] = r
+    return out
+
+
 def adjoint_leg(steps: int = 200, K: int = 20) -> dict:
     """Forward with checkpoints every K steps plus the reverse sweep (which
     recomputes each segment) on the 50k-agent differentiation workload, vs
@@ -265,7 +314,7 @@ def adjoint_leg(steps: int = 200, K: int = 20) -> dict:
             "grad_theta": theta.grad.tolist()}
 
 
-LEGS = {"ensemble": lambda: ensemble_leg(), "fig1": lambda: fig1_leg(),
+LEGS = {"ensemble": lambda: ensemble_leg(), "fig1": lambda: fig1_leg(), "kde": lambda: kde_leg(),
         "switching": lambda: reaction_overhead_leg(), "fwd_bwd": lambda: adjoint_leg()}
 
 
@@ -411,6 +460,9 @@ def main() -> int:
         print("[bench] switching overhead leg", file=sys.stderr, flush=True)
         res["switching"] = reaction_overhead_leg()
         print(f"[bench] switching: {json.dumps(res['switching'])}", file=sys.stderr, flush=True)
+        print("[bench] kernel density leg", file=sys.stderr, flush=True)
+        res["kde"] = kde_leg()
+        print(f"[bench] kde: {json.dumps(res['kde'])}", file=sys.stderr, flush=True)
         print("[bench] forward+backward leg", file=sys.stderr, flush=True)
         res["fwd_bwd"] = adjoint_leg()
         print(f"[bench] fwd_bwd: {json.dumps(res['fwd_bwd'])}", file=sys.stderr, flush=True)

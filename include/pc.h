@@ -110,6 +110,17 @@ typedef struct {
     int32_t reserved;
     double kde_radius;      /* truncation radius in bandwidths (0: 3); kde_radius times
                                the largest diameter must be < L/2                       */
+    int32_t potential;      /* pair interaction with contact distance d = mean diameter:
+                               0: harmonic soft sphere u = (k_rep/2)(d - r)^2, r < d;
+                               1: exponential u = k_rep exp(-r/d) (the soft potential
+                                  of Sect. 4), cut at r < pot_range d;
+                               2: hard spheres (Sect. 2.2): no force; after the update
+                                  every pair closer than d is pushed apart by 2 (d - r),
+                                  agent i taking D_i / (D_i + D_j) of it, from the same
+                                  positions, then the boundary closure again         */
+    int32_t tamed;          /* 1: tamed Euler (eq. sde_ETamed): the pair drift F becomes
+                               F / (1 + |F| dt); potentials 0 and 1                     */
+    double pot_range;       /* range of potential 1 in contact distances (0: 3)          */
 } pc_config;
 
 /* One agent species (the paper's cell type).
@@ -246,10 +257,13 @@ int pc_info(pc_sim *sim, pc_info_t *info);
 /* Measurement: run n_steps steps eagerly with HIP events between the
  * stages of each step and return the mean milliseconds per step of every
  * stage in stage_ms[PC_N_STAGES] (host): bin, scan, scatter, stable order,
- * update, deposit, PDE.  Synchronises the stream; advances the state like
- * pc_step. */
+ * update, deposit, PDE, hard-sphere overlap correction (a stage that does
+ * not run reports 0; a sort run twice in a step, as with the kernel density
+ * deposit or hard spheres, adds up).  The fused per-instance deposit + PDE
+ * path reports both under the deposit.  Synchronises the stream; advances
+ * the state like pc_step. */
 enum { PC_STAGE_BIN, PC_STAGE_SCAN, PC_STAGE_SCATTER, PC_STAGE_STABLE, PC_STAGE_UPDATE,
-       PC_STAGE_DEPOSIT, PC_STAGE_PDE, PC_N_STAGES };
+       PC_STAGE_DEPOSIT, PC_STAGE_PDE, PC_STAGE_OVERLAP, PC_N_STAGES };
 int pc_profile_steps(pc_sim *sim, int n_steps, double *stage_ms);
 
 /* Release the handle (does not touch caller memory). */
@@ -283,9 +297,10 @@ int pc_debug_forces(pc_sim *sim, float *F_dev);
  * The segment is recomputed forward inside the call (checkpointing); the
  * state is restored to what it was, and the call synchronises the stream.
  * Needs a workspace of pc_workspace_bytes_adjoint(..., seg_steps) bytes with
- * 1 <= n_steps <= seg_steps.  Errors: PC_ENOTSUP without segment storage
- * or when a species has a type switch (a discrete event), PC_EINVAL for bad
- * arguments, PC_EHIP. */
+ * 1 <= n_steps <= seg_steps.  Errors: PC_ENOTSUP without segment storage,
+ * when a species has a type switch (a discrete event), or for a setup other
+ * than the harmonic potential with the particle-in-cell deposit and no
+ * taming; PC_EINVAL for bad arguments, PC_EHIP. */
 size_t pc_workspace_bytes_adjoint(const pc_config *cfg, const pc_species_t *species,
                                   int n_species, const pc_instance *inst, int n_inst,
                                   int seg_steps);

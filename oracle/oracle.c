@@ -787,8 +787,8 @@ void orc_step(const orc_params *p, int64_t n, double *X, uint8_t *sp, const uint
             X[i * dim + a] = orc_boundary(p, x);
         }
     }
-    if (p->potential == 2) orc_hs_correct(p, n, X, sp);  /* overlaps at X^{n+1}, old types */
-    memcpy(sp, nsp, (size_t)n);  /* the deposit sees the switched types */
+    memcpy(sp, nsp, (size_t)n);  /* overlap correction and deposit see the switched types */
+    if (p->potential == 2) orc_hs_correct(p, n, X, sp);
     double *Ss = (double *)malloc(sizeof(double) * (size_t)G);
     double *Su = (double *)malloc(sizeof(double) * (size_t)G);
     if (p->deposit_kernel == 1) {

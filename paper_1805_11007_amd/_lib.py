@@ -21,7 +21,7 @@ EXPORTS = (
     "pc_debug_neighbours", "pc_debug_forces", "pc_adjoint_segment", "pc_profile_steps",
     "pc_density_loss_work_bytes", "pc_density_loss", "pc_density_hist",
 )
-STAGES = ("bin", "scan", "scatter", "stable", "update", "deposit", "pde")
+STAGES = ("bin", "scan", "scatter", "stable", "update", "deposit", "pde", "overlap")
 
 
 class PcConfig(C.Structure):
@@ -31,7 +31,8 @@ class PcConfig(C.Structure):
                 ("bin_size", C.c_double), ("deterministic", C.c_int32), ("block", C.c_int32),
                 ("bin_order", C.c_int32), ("deposit_mode", C.c_int32),
                 ("deposit_kernel", C.c_int32), ("reserved", C.c_int32),
-                ("kde_radius", C.c_double)]
+                ("kde_radius", C.c_double), ("potential", C.c_int32), ("tamed", C.c_int32),
+                ("pot_range", C.c_double)]
 
 
 class PcSpecies(C.Structure):

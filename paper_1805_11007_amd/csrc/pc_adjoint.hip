@@ -305,7 +305,7 @@ struct AdjPairVisitor {
     size_t base;
     int dim;
     __device__ __forceinline__ void operator()(uint32_t j, float dx, float dy, float dz, float r2,
-                                               float c2, float dd) {
+                                               float c2, float dd, int) {
         if (r2 < c2 && r2 > 0.0f) {
             const size_t rj = (base + Is[j]) * dim;
             const float v0 = li[0] - lamY[rj + 0];

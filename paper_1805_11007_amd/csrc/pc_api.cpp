@@ -37,8 +37,8 @@ struct Derived {
     int nb, stencil;
     double bin_side, cutoff, h;
     int64_t bins_per_inst, bins_total, nodes_per_inst, nodes_total;
-    int n_sub, block, has_uptake, has_react, kde;
-    double kde_radius;
+    int n_sub, block, has_uptake, has_react, kde, potential, tamed;
+    double kde_radius, pot_range, contact_max;
     uint32_t warn;
 };
 
@@ -89,6 +89,15 @@ int derive(const pc_config *cfg, const pc_species_t *sp, int ns, const pc_instan
     d.cutoff = 0;
     d.has_uptake = 0;
     d.has_react = 0;
+    if (cfg->potential < 0 || cfg->potential > 2) return fail(PC_EINVAL, "potential must be 0..2");
+    if (cfg->tamed != 0 && cfg->tamed != 1) return fail(PC_EINVAL, "tamed must be 0 or 1");
+    if (!(cfg->pot_range >= 0) || !std::isfinite(cfg->pot_range))
+        return fail(PC_EINVAL, "pot_range must be finite and >= 0");
+    d.potential = cfg->potential;
+    d.tamed = cfg->tamed;
+    d.pot_range = cfg->pot_range > 0 ? cfg->pot_range : 3.0;
+    if (d.potential == 1 && d.pot_range < 1.0)
+        return fail(PC_EINVAL, "pot_range must be >= 1 (the neighbour cut is >= the diameter)");
     for (int s = 0; s < ns; ++s) {
         if (!(sp[s].diameter > 0)) return fail(PC_EINVAL, "diameter must be > 0");
         if (!(sp[s].D >= 0)) return fail(PC_EINVAL, "D must be >= 0");
@@ -111,7 +120,9 @@ int derive(const pc_config *cfg, const pc_species_t *sp, int ns, const pc_instan
         d.n_total += in[k].n_agents;
     }
     if (d.n_total >= (int64_t)1 << 31) return fail(PC_EINVAL, "too many agents");
-    if (d.cutoff >= cfg->L / 2) return fail(PC_EINVAL, "cutoff must be < L/2");
+    d.contact_max = d.cutoff;
+    if (d.potential == 1) d.cutoff *= d.pot_range;  // neighbour range of the exponential
+    if (d.cutoff >= cfg->L / 2) return fail(PC_EINVAL, "interaction range must be < L/2");
     if (cfg->deposit_kernel != 0 && cfg->deposit_kernel != 1)
         return fail(PC_EINVAL, "deposit_kernel must be 0 or 1");
     d.kde = cfg->deposit_kernel;
@@ -121,8 +132,10 @@ int derive(const pc_config *cfg, const pc_species_t *sp, int ns, const pc_instan
     if (d.kde) {
         if (cfg->deposit_mode == 3)
             return fail(PC_EINVAL, "deposit_mode 3 is a particle-in-cell path");
-        if (d.kde_radius * d.cutoff >= cfg->L / 2)
+        if (d.kde_radius * d.contact_max >= cfg->L / 2)
             return fail(PC_EINVAL, "kde_radius * diameter must be < L/2");
+        if (d.potential == 2)
+            return fail(PC_ENOTSUP, "hard spheres with the kernel density deposit are not built");
     }
 
     // Bins: side >= cutoff (1 + 1e-4) so float32 rounding of the bin index
@@ -280,8 +293,11 @@ static void fill_params(pc_sim *s) {
     for (int a = 0; a < d.ns; ++a) {
         for (int b = 0; b < d.ns; ++b) {
             const double m = 0.5 * (s->species[a].diameter + s->species[b].diameter);
-            p.cut2[a * d.ns + b] = (float)(m * m);
+            const double range = d.potential == 1 ? d.pot_range * m : m;
+            p.cut2[a * d.ns + b] = (float)(range * range);
             p.dij[a * d.ns + b] = (float)m;
+            const double Ds = s->species[a].D + s->species[b].D;
+            p.hs_share[a * d.ns + b] = Ds > 0 ? (float)(2.0 * s->species[a].D / Ds) : 0.0f;
         }
         p.amp[a] = (float)sqrt(2.0 * s->species[a].D * c.dt);
         p.chi[a] = (float)s->species[a].chi;
@@ -306,7 +322,9 @@ static void fill_params(pc_sim *s) {
     p.kde = d.kde;
     // bins scanned around a node: a hair wider than the largest radius, so
     // that float32 rounding of the bin range never drops a candidate
-    p.kde_R = (float)(d.kde_radius * d.cutoff * (1.0 + 1e-4));
+    p.kde_R = (float)(d.kde_radius * d.contact_max * (1.0 + 1e-4));
+    p.potential = d.potential;
+    p.tamed = d.tamed;
     p.has_react = d.has_react;
     // LDS aggregation pays where a work-group's agents share nodes; with
     // fewer agents than kDepositSparse per node most corners are distinct
@@ -408,6 +426,16 @@ static void enqueue_chem(pc_sim *s, hipStream_t st) {
 static void enqueue_step(pc_sim *s, hipStream_t st) {
     ensure_sorted(s, st);
     launch_update(s->sp, s->b, s->sorted_src, 0, s->cur_c, s->d.block, st);
+    if (s->d.potential == 2) {
+        // overlaps are found on the cell list of the updated positions; the
+        // corrected positions go back to P[0] with their bins counted
+        s->binned = 1;
+        s->sorted = 0;
+        ensure_sorted(s, st);
+        launch_overlap(s->sp, s->b, s->sorted_src, 0, s->d.block, st);
+        s->binned = 1;
+        s->sorted = 0;
+    }
     if (s->d.kde) {
         // the density gather needs the cell list of X^{n+1}: sort now, and
         // the next step starts from the sorted state
@@ -678,6 +706,13 @@ int pc_profile_steps(pc_sim *s, int n_steps, double *stage_ms) {
         PC_STAGE(PC_STAGE_UPDATE, launch_update(s->sp, s->b, s->sorted_src, 0, s->cur_c, blk, st));
         s->binned = 1;
         s->sorted = 0;
+        if (s->d.potential == 2) {
+            rc = sort_stages();
+            if (rc) return rc;
+            PC_STAGE(PC_STAGE_OVERLAP, launch_overlap(s->sp, s->b, s->sorted_src, 0, blk, st));
+            s->binned = 1;
+            s->sorted = 0;
+        }
         if (s->d.kde) {
             rc = sort_stages();
             if (rc) return rc;
@@ -888,6 +923,8 @@ int pc_adjoint_segment(pc_sim *s, const float *lamX_in_dev, const float *lamC_in
         return fail(PC_EINVAL, "n_steps must be in [1, segment capacity]");
     if (s->d.has_react) return fail(PC_ENOTSUP, "reverse mode over type switches is not built");
     if (s->d.kde) return fail(PC_ENOTSUP, "reverse mode of the kernel density deposit is not built");
+    if (s->d.potential != 0 || s->d.tamed)
+        return fail(PC_ENOTSUP, "reverse mode is built for the untamed harmonic potential only");
     hipStream_t st = s->stream;
     const Buffers &b = s->b;
     const size_t XD = (size_t)s->d.n_total * s->d.dim;

@@ -82,6 +82,7 @@ __device__ __forceinline__ unsigned long long splitmix64(unsigned long long x) {
 struct SpTab {
     float cut2[kMaxSpecies * kMaxSpecies];
     float dij[kMaxSpecies * kMaxSpecies];
+    float share[kMaxSpecies * kMaxSpecies];
     float amp[kMaxSpecies], chi[kMaxSpecies], src[kMaxSpecies], upt[kMaxSpecies];
 };
 
@@ -90,6 +91,7 @@ __device__ __forceinline__ void load_tab(const StepParams &p, SpTab &t) {
     for (int q = threadIdx.x; q < n2; q += blockDim.x) {
         t.cut2[q] = p.cut2[q];
         t.dij[q] = p.dij[q];
+        t.share[q] = p.hs_share[q];
     }
     for (int q = threadIdx.x; q < p.n_species; q += blockDim.x) {
         t.amp[q] = p.amp[q];
@@ -141,19 +143,22 @@ __device__ __forceinline__ void pair_one(const StepParams &p, const SpTab &tab, 
         r2 = r2 + dz * dz;
     }
     float c2, dd;
+    int sj;
     if (NS == 1) {
         c2 = c2row[0];
         dd = drow[0];
+        sj = 0;
     } else if (NS == 2) {
         const bool s1 = species_of(q.w) != 0;
         c2 = s1 ? c2row[1] : c2row[0];
         dd = s1 ? drow[1] : drow[0];
+        sj = s1 ? 1 : 0;
     } else {
-        const int sj = species_of(q.w);
+        sj = species_of(q.w);
         c2 = tab.cut2[si * p.n_species + sj];
         dd = tab.dij[si * p.n_species + sj];
     }
-    v(j, dx, dy, dz, r2, c2, dd);
+    v(j, dx, dy, dz, r2, c2, dd, sj);
 }
 
 // Candidates j in [a, e) of one contiguous bin range.  dx = (x_j - x_i)
@@ -188,7 +193,7 @@ struct ForceVisitor {
     float k;
     float F[3];
     __device__ __forceinline__ void operator()(uint32_t, float dx, float dy, float dz, float r2,
-                                               float c2, float dd) {
+                                               float c2, float dd, int) {
         if (r2 < c2 && r2 > 0.0f) {
             const float f = fmaf(k * dd, rsqrtf(r2), -k);
             F[0] = fmaf(-f, dx, F[0]);
@@ -198,20 +203,56 @@ struct ForceVisitor {
     }
 };
 
+// Exponential potential u = k exp(-r/d) cut at the pair's range (c2):
+// F_i = -sum (k/d) exp(-r/d) dx / r over neighbours with r > 0.
+struct ExpVisitor {
+    float k;
+    float F[3];
+    __device__ __forceinline__ void operator()(uint32_t, float dx, float dy, float dz, float r2,
+                                               float c2, float dd, int) {
+        if (r2 < c2 && r2 > 0.0f) {
+            const float rinv = rsqrtf(r2);
+            const float f = (k / dd) * expf(-(r2 * rinv) / dd) * rinv;
+            F[0] = fmaf(-f, dx, F[0]);
+            F[1] = fmaf(-f, dy, F[1]);
+            F[2] = fmaf(-f, dz, F[2]);
+        }
+    }
+};
+
+// Hard-sphere overlap correction: every pair closer than its contact
+// distance d pushes i away from j by 2 (d - r) D_i / (D_i + D_j) (share row
+// of species i: share[sj] = 2 D_i / (D_i + D_j), 0 for two immobile agents).
+struct OverlapVisitor {
+    const float *share;
+    float C[3];
+    __device__ __forceinline__ void operator()(uint32_t, float dx, float dy, float dz, float r2,
+                                               float c2, float dd, int sj) {
+        if (r2 < c2 && r2 > 0.0f) {
+            const float rinv = rsqrtf(r2);
+            const float g = share[sj] * (dd * rinv - 1.0f);
+            C[0] = fmaf(-g, dx, C[0]);
+            C[1] = fmaf(-g, dy, C[1]);
+            C[2] = fmaf(-g, dz, C[2]);
+        }
+    }
+};
+
 // Forces plus the neighbour count and id hash (self excluded).
+template <class FV>
 struct DebugVisitor {
-    ForceVisitor fv;
+    FV fv;
     uint32_t self;
     const uint32_t *Is;
     uint32_t cnt;
     unsigned long long hs;
     __device__ __forceinline__ void operator()(uint32_t j, float dx, float dy, float dz, float r2,
-                                               float c2, float dd) {
+                                               float c2, float dd, int sj) {
         if (r2 < c2 && j != self) {
             cnt += 1;
             hs += splitmix64((unsigned long long)Is[j]);
         }
-        fv(j, dx, dy, dz, r2, c2, dd);
+        fv(j, dx, dy, dz, r2, c2, dd, sj);
     }
 };
 

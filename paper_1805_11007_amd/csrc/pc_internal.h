@@ -56,6 +56,10 @@ struct StepParams {
     float kde_norm[kMaxSpecies];            // (2 pi eps_s^2)^(-dim/2)
     float kde_inv2e2[kMaxSpecies];          // 1 / (2 eps_s^2)
     float src_f[kMaxSpecies], upt_f[kMaxSpecies];
+    // pair interaction: 0 harmonic, 1 exponential, 2 hard spheres (no force;
+    // overlaps corrected after the update); tamed Euler pair drift
+    int32_t potential, tamed;
+    float hs_share[kMaxSpecies * kMaxSpecies];  // 2 D_i / (D_i + D_j)
 };
 
 struct PdeParams {
@@ -140,6 +144,8 @@ void launch_pde(const PdeParams &q, const Buffers &b, int cin, int cout, int las
 void launch_step_inc(const Buffers &b, hipStream_t s);
 void launch_zero_u32(uint32_t *d, int64_t n, hipStream_t s);
 void launch_kde(const StepParams &p, const Buffers &b, int src, hipStream_t s);
+void launch_overlap(const StepParams &p, const Buffers &b, int src, int dst, int block,
+                    hipStream_t s);
 size_t chem_inst_lds_bytes(const PdeParams &q);
 void launch_chem_inst(const StepParams &p, const PdeParams &q, const Buffers &b, int src, int cur,
                       int n_sub, hipStream_t s);

@@ -197,7 +197,8 @@ __global__ void k_stable(StepParams p, const InstInfo *__restrict__ inst,
 // pair repulsion at X^n, chemotactic drift from c^n at X^n, Euler-Maruyama
 // with Philox normals, boundary closure; then the cell-list bin of X^{n+1}
 // and the agent's rank in it (the counting sort of the next step).
-template <int DIM, int NS, int STENCIL>
+// POT: 0 harmonic, 1 exponential, 2 hard spheres (no pair force here).
+template <int DIM, int NS, int STENCIL, int POT>
 __global__ void __launch_bounds__(1024)
 k_update(StepParams p, const InstInfo *__restrict__ inst, const float4 *__restrict__ Ps,
          const uint32_t *__restrict__ Is, const uint32_t *__restrict__ start,
@@ -217,9 +218,27 @@ k_update(StepParams p, const InstInfo *__restrict__ inst, const float4 *__restri
     const int si = species_of(pi.w);
     const InstInfo ii = inst[inst_of(pi.w)];
 
-    ForceVisitor fv{p.k, {0.f, 0.f, 0.f}};
-    pair_loop<DIM, NS, STENCIL>(p, tab, Ps, start, ii.bin_base, pi, si, fv);
-    const float *F = fv.F;
+    float F[3] = {0.f, 0.f, 0.f};
+    if (POT == 0) {
+        ForceVisitor fv{p.k, {0.f, 0.f, 0.f}};
+        pair_loop<DIM, NS, STENCIL>(p, tab, Ps, start, ii.bin_base, pi, si, fv);
+        F[0] = fv.F[0];
+        F[1] = fv.F[1];
+        F[2] = fv.F[2];
+    } else if (POT == 1) {
+        ExpVisitor ev{p.k, {0.f, 0.f, 0.f}};
+        pair_loop<DIM, NS, STENCIL>(p, tab, Ps, start, ii.bin_base, pi, si, ev);
+        F[0] = ev.F[0];
+        F[1] = ev.F[1];
+        F[2] = ev.F[2];
+    }
+    if (POT != 2 && p.tamed) {
+        // tamed Euler (eq. sde_ETamed): the pair drift becomes F / (1 + |F| dt)
+        const float s = 1.0f / (1.0f + sqrtf(F[0] * F[0] + F[1] * F[1] + F[2] * F[2]) * p.dt);
+        F[0] *= s;
+        F[1] *= s;
+        F[2] *= s;
+    }
 
     float drift[3] = {0.f, 0.f, 0.f};
     const float chi = sel<NS>(p.chi, tab.chi, si) * ii.chi_scale;
@@ -578,7 +597,7 @@ __global__ void k_apply_species(StepParams p, const InstInfo *__restrict__ inst,
     P[j].w = __uint_as_float((k << 8) | s);
 }
 
-template <int DIM, int NS, int STENCIL>
+template <int DIM, int NS, int STENCIL, int POT>
 __global__ void __launch_bounds__(1024)
 k_debug_pairs(StepParams p, const InstInfo *__restrict__ inst, const float4 *__restrict__ Ps,
               const uint32_t *__restrict__ Is, const uint32_t *__restrict__ start,
@@ -594,13 +613,67 @@ k_debug_pairs(StepParams p, const InstInfo *__restrict__ inst, const float4 *__r
     const float4 pi = Ps[i];
     const int si = species_of(pi.w);
     const InstInfo ii = inst[inst_of(pi.w)];
-    DebugVisitor dv{ForceVisitor{p.k, {0.f, 0.f, 0.f}}, (uint32_t)i, Is, 0u, 0ull};
-    pair_loop<DIM, NS, STENCIL>(p, tab, Ps, start, ii.bin_base, pi, si, dv);
     const size_t row = ii.agent_base + Is[i];
-    if (count) count[row] = dv.cnt;
-    if (hash) hash[row] = dv.hs;
+    uint32_t cnt;
+    unsigned long long hs;
+    float F[3];
+    if (POT == 1) {
+        DebugVisitor<ExpVisitor> dv{ExpVisitor{p.k, {0.f, 0.f, 0.f}}, (uint32_t)i, Is, 0u, 0ull};
+        pair_loop<DIM, NS, STENCIL>(p, tab, Ps, start, ii.bin_base, pi, si, dv);
+        cnt = dv.cnt;
+        hs = dv.hs;
+        F[0] = dv.fv.F[0], F[1] = dv.fv.F[1], F[2] = dv.fv.F[2];
+    } else {
+        // hard spheres exert no force
+        const float k = POT == 0 ? p.k : 0.0f;
+        DebugVisitor<ForceVisitor> dv{ForceVisitor{k, {0.f, 0.f, 0.f}}, (uint32_t)i, Is, 0u, 0ull};
+        pair_loop<DIM, NS, STENCIL>(p, tab, Ps, start, ii.bin_base, pi, si, dv);
+        cnt = dv.cnt;
+        hs = dv.hs;
+        F[0] = dv.fv.F[0], F[1] = dv.fv.F[1], F[2] = dv.fv.F[2];
+    }
+    if (count) count[row] = cnt;
+    if (hash) hash[row] = hs;
     if (Fo)
-        for (int a = 0; a < DIM; ++a) Fo[row * DIM + a] = dv.fv.F[a];
+        for (int a = 0; a < DIM; ++a) Fo[row * DIM + a] = F[a];
+}
+
+// Hard-sphere overlap correction (Sect. 2.2) at the updated, cell-sorted
+// positions: every pair closer than its contact distance pushes i away by
+// 2 (d - r) D_i / (D_i + D_j); all pushes come from the same positions.
+// Then the boundary closure, and the bin / rank of the corrected position
+// (the counting sort of the next step), as the update kernel does.
+template <int DIM, int STENCIL>
+__global__ void __launch_bounds__(1024)
+k_overlap(StepParams p, const InstInfo *__restrict__ inst, const float4 *__restrict__ Ps,
+          const uint32_t *__restrict__ Is, const uint32_t *__restrict__ start,
+          float4 *__restrict__ Pout, uint32_t *__restrict__ Iout, uint32_t *__restrict__ bin,
+          uint32_t *__restrict__ rank, uint32_t *__restrict__ count,
+          uint32_t *__restrict__ flags) {
+    __shared__ SpTab tab;
+    load_tab(p, tab);
+    __syncthreads();
+    const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
+    const int i = blk * blockDim.x + threadIdx.x;
+    if (i >= p.n_total) return;
+    const float4 pi = Ps[i];
+    const int si = species_of(pi.w);
+    const InstInfo ii = inst[inst_of(pi.w)];
+    OverlapVisitor ov{tab.share + si * p.n_species, {0.f, 0.f, 0.f}};
+    pair_loop<DIM, 0, STENCIL>(p, tab, Ps, start, ii.bin_base, pi, si, ov);
+    uint32_t flag = 0;
+    float4 xn;
+    xn.x = boundary(p, pi.x + ov.C[0], flag);
+    xn.y = boundary(p, pi.y + ov.C[1], flag);
+    xn.z = DIM == 3 ? boundary(p, pi.z + ov.C[2], flag) : 0.0f;
+    xn.w = pi.w;
+    if (!(isfinite(xn.x) && isfinite(xn.y) && isfinite(xn.z))) flag |= FLAG_NONFINITE;
+    Pout[i] = xn;
+    Iout[i] = Is[i];
+    const uint32_t b = ii.bin_base + agent_bin<DIM>(p, xn);
+    bin[i] = b;
+    rank[i] = atomicAdd(count + b, 1u);
+    if (flag) atomicOr(flags, flag);
 }
 
 __global__ void k_set_u32(uint32_t *ptr, uint32_t v) { *ptr = v; }
@@ -660,16 +733,35 @@ void launch_stable(const StepParams &p, const Buffers &b, int src, int dst, int 
 template <int DIM, int NS, int ST>
 static void upd(const StepParams &p, const Buffers &b, int src, int dst, int cbuf, int block,
                 hipStream_t s) {
-    hipLaunchKernelGGL((k_update<DIM, NS, ST>), dim3(grid_for(p.n_total, block)), dim3(block), 0,
-                       s, p, b.inst, b.P[src], b.I[src], b.start, b.c[cbuf], b.P[dst], b.I[dst],
-                       b.bin, b.rank, b.count, b.step, b.flags);
+    hipLaunchKernelGGL((k_update<DIM, NS, ST, 0>), dim3(grid_for(p.n_total, block)), dim3(block),
+                       0, s, p, b.inst, b.P[src], b.I[src], b.start, b.c[cbuf], b.P[dst],
+                       b.I[dst], b.bin, b.rank, b.count, b.step, b.flags);
+}
+
+// the other potentials use the generic (LDS) species table
+template <int DIM, int ST, int POT>
+static void upd_pot(const StepParams &p, const Buffers &b, int src, int dst, int cbuf, int block,
+                    hipStream_t s) {
+    hipLaunchKernelGGL((k_update<DIM, 0, ST, POT>), dim3(grid_for(p.n_total, block)),
+                       dim3(block), 0, s, p, b.inst, b.P[src], b.I[src], b.start, b.c[cbuf],
+                       b.P[dst], b.I[dst], b.bin, b.rank, b.count, b.step, b.flags);
 }
 
 template <int DIM, int NS, int ST>
 static void dbg(const StepParams &p, const Buffers &b, int src, uint32_t *count,
                 unsigned long long *hash, float *F, int block, hipStream_t s) {
-    hipLaunchKernelGGL((k_debug_pairs<DIM, NS, ST>), dim3(grid_for(p.n_total, block)),
-                       dim3(block), 0, s, p, b.inst, b.P[src], b.I[src], b.start, count, hash, F);
+    if (p.potential == 0)
+        hipLaunchKernelGGL((k_debug_pairs<DIM, NS, ST, 0>), dim3(grid_for(p.n_total, block)),
+                           dim3(block), 0, s, p, b.inst, b.P[src], b.I[src], b.start, count, hash,
+                           F);
+    else if (p.potential == 1)
+        hipLaunchKernelGGL((k_debug_pairs<DIM, 0, ST, 1>), dim3(grid_for(p.n_total, block)),
+                           dim3(block), 0, s, p, b.inst, b.P[src], b.I[src], b.start, count, hash,
+                           F);
+    else
+        hipLaunchKernelGGL((k_debug_pairs<DIM, 0, ST, 2>), dim3(grid_for(p.n_total, block)),
+                           dim3(block), 0, s, p, b.inst, b.P[src], b.I[src], b.start, count, hash,
+                           F);
 }
 
 #define PC_DISPATCH(FN, ...)                                                        \
@@ -700,7 +792,39 @@ static void dbg(const StepParams &p, const Buffers &b, int src, uint32_t *count,
 
 void launch_update(const StepParams &p, const Buffers &b, int src, int dst, int cbuf, int block,
                    hipStream_t s) {
-    PC_DISPATCH(upd, p, b, src, dst, cbuf, block, s);
+    if (p.potential == 0) {
+        PC_DISPATCH(upd, p, b, src, dst, cbuf, block, s);
+        return;
+    }
+#define PC_POT(D, S)                                                        \
+    do {                                                                    \
+        if (p.potential == 1) upd_pot<D, S, 1>(p, b, src, dst, cbuf, block, s); \
+        else upd_pot<D, S, 2>(p, b, src, dst, cbuf, block, s);              \
+    } while (0)
+    if (p.dim == 2) {
+        if (p.stencil == 3) PC_POT(2, 3);
+        else PC_POT(2, 2);
+    } else {
+        if (p.stencil == 3) PC_POT(3, 3);
+        else PC_POT(3, 2);
+    }
+#undef PC_POT
+}
+
+void launch_overlap(const StepParams &p, const Buffers &b, int src, int dst, int block,
+                    hipStream_t s) {
+    const dim3 g(grid_for(p.n_total, block)), t(block);
+#define PC_OV(D, S)                                                                          \
+    hipLaunchKernelGGL((k_overlap<D, S>), g, t, 0, s, p, b.inst, b.P[src], b.I[src], b.start, \
+                       b.P[dst], b.I[dst], b.bin, b.rank, b.count, b.flags)
+    if (p.dim == 2) {
+        if (p.stencil == 3) PC_OV(2, 3);
+        else PC_OV(2, 2);
+    } else {
+        if (p.stencil == 3) PC_OV(3, 3);
+        else PC_OV(3, 2);
+    }
+#undef PC_OV
 }
 
 void launch_debug_pairs(const StepParams &p, const Buffers &b, int src, uint32_t *count,

@@ -56,6 +56,9 @@ class ModelSpec:
     deposit_mode: int = 0    # 0 auto, 1 LDS-aggregated, 2 direct atomics, 3 fused per instance
     deposit_kernel: int = 0  # 0 particle-in-cell, 1 Gaussian kernel density (Sect. 2.3)
     kde_radius: float = 0.0  # kernel truncation in bandwidths (0: 3)
+    potential: int = 0       # 0 harmonic, 1 exponential k exp(-r/d), 2 hard spheres
+    tamed: bool = False      # tamed Euler pair drift (eq. sde_ETamed)
+    pot_range: float = 0.0   # exponential range in contact distances (0: 3)
 
     @classmethod
     def from_workload(cls, w, **over) -> "ModelSpec":
@@ -68,7 +71,9 @@ class ModelSpec:
         kw = dict(dim=w.dim, periodic=w.periodic, L=w.L, grid_n=w.grid_n, dt=w.dt, k=w.k,
                   D_c=w.D_c, gamma=w.gamma, species=sp, instances=ins,
                   pde_substeps=w.pde_substeps, deposit_kernel=getattr(w, "deposit_kernel", 0),
-                  kde_radius=getattr(w, "kde_radius", 0.0))
+                  kde_radius=getattr(w, "kde_radius", 0.0),
+                  potential=getattr(w, "potential", 0), tamed=bool(getattr(w, "tamed", False)),
+                  pot_range=getattr(w, "pot_range", 0.0))
         kw.update(over)
         return cls(**kw)
 
@@ -90,6 +95,9 @@ class ModelSpec:
         cfg.deposit_mode = self.deposit_mode
         cfg.deposit_kernel = self.deposit_kernel
         cfg.kde_radius = self.kde_radius
+        cfg.potential = self.potential
+        cfg.tamed = 1 if self.tamed else 0
+        cfg.pot_range = self.pot_range
         ns = len(self.species)
         sp = (LB.PcSpecies * max(ns, 1))()
         for k, s in enumerate(self.species):
