@@ -270,6 +270,38 @@ def kde_leg(steps: int = 100, sample_nodes: int = 4000) -> dict:
     return out
 
 
+def variants_leg(steps: int = 100) -> dict:
+    """Step time and per-stage profile of the pair/update variants against
+    the harmonic soft-sphere step on the 100k-agent walls workload and the
+    1M-agent 3D workload: exponential potential (range 3 d, k = 1), tamed
+    Euler (harmonic), hard spheres (overlap correction pass); graph replay."""
+    import torch
+    import workloads as W
+    from paper_1805_11007_amd import ModelSpec, Sim
+    variants = {"harmonic": {}, "exponential": {"potential": 1, "pot_range": 3.0, "k": 1.0},
+                "tamed": {"tamed": True}, "hard_spheres": {"potential": 2}}
+    out = {}
+    for cfg in (2, 3):
+        w = W.config(cfg)
+        inp = W.make_inputs(w)
+        x0, s0, c0 = (torch.from_numpy(inp[k]).cuda() for k in ("x0", "species0", "c0"))
+        r = {}
+        for name, kw in variants.items():
+            sim = Sim(ModelSpec.from_workload(w, **kw), x0, s0, c0)
+            sim.use_graph(True)
+            sim.step(4)
+            sim.set_state(x0, c0, 0)
+            ms = _timed(lambda: sim.step(steps)) / steps
+            sim.sync()
+            sim.set_state(x0, c0, 0)
+            prof = sim.profile_steps(min(steps, 50))
+            r[name] = {"ms_per_step": ms, "particle_steps_per_s": w.n_total / (ms * 1e-3),
+                       "stage_ms": {k: round(v, 5) for k, v in prof.items() if v > 0}}
+            sim.close()
+        out[w.name] = r
+    return out
+
+
 def adjoint_leg(steps: int = 200, K: int = 20) -> dict:
     """Forward with checkpoints every K steps plus the reverse sweep (which
     recomputes each segment) on the 50k-agent differentiation workload, vs
@@ -315,6 +347,7 @@ def adjoint_leg(steps: int = 200, K: int = 20) -> dict:
 
 
 LEGS = {"ensemble": lambda: ensemble_leg(), "fig1": lambda: fig1_leg(), "kde": lambda: kde_leg(),
+        "variants": lambda: variants_leg(),
         "switching": lambda: reaction_overhead_leg(), "fwd_bwd": lambda: adjoint_leg()}
 
 
@@ -463,6 +496,9 @@ def main() -> int:
         print("[bench] kernel density leg", file=sys.stderr, flush=True)
         res["kde"] = kde_leg()
         print(f"[bench] kde: {json.dumps(res['kde'])}", file=sys.stderr, flush=True)
+        print("[bench] pair/update variants leg", file=sys.stderr, flush=True)
+        res["variants"] = variants_leg()
+        print(f"[bench] variants: {json.dumps(res['variants'])}", file=sys.stderr, flush=True)
         print("[bench] forward+backward leg", file=sys.stderr, flush=True)
         res["fwd_bwd"] = adjoint_leg()
         print(f"[bench] fwd_bwd: {json.dumps(res['fwd_bwd'])}", file=sys.stderr, flush=True)
