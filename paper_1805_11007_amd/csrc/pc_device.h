@@ -174,8 +174,10 @@ __device__ __forceinline__ void pair_range(const StepParams &p, const SpTab &tab
                                            float sy, float sz, const float c2row[2],
                                            const float drow[2], V &v) {
     uint32_t j = a;
-    for (; j + 4 <= e; j += 4) {
-        const float4 q0 = Ps[j], q1 = Ps[j + 1], q2 = Ps[j + 2], q3 = Ps[j + 3];
+    // one 64-bit address per group of four; the rest are immediate offsets
+    const float4 *__restrict__ qp = Ps + a;
+    for (; j + 4 <= e; j += 4, qp += 4) {
+        const float4 q0 = qp[0], q1 = qp[1], q2 = qp[2], q3 = qp[3];
         pair_one<DIM, NS, SHIFT>(p, tab, j, q0, pi, si, sx, sy, sz, c2row, drow, v);
         pair_one<DIM, NS, SHIFT>(p, tab, j + 1, q1, pi, si, sx, sy, sz, c2row, drow, v);
         pair_one<DIM, NS, SHIFT>(p, tab, j + 2, q2, pi, si, sx, sy, sz, c2row, drow, v);
@@ -188,18 +190,22 @@ __device__ __forceinline__ void pair_range(const StepParams &p, const SpTab &tab
 }
 
 // Repulsion F_i = -sum k (d_ij - r) dx / r over neighbours with r > 0,
-// evaluated as k d / r - k.
+// evaluated as k d / r - k with the hardware reciprocal square root, for
+// every candidate, and selected by the neighbour test (no branch: in dense
+// regions nearly every wave has a neighbour among its candidates).  The
+// self pair and coincident agents (r2 = 0, dx = 0) contribute exactly zero
+// through the product with dx; the 1e-20 added to r2 keeps f finite there
+// and leaves r2 of any two distinct float32 positions in the box unchanged.
 struct ForceVisitor {
     float k;
     float F[3];
     __device__ __forceinline__ void operator()(uint32_t, float dx, float dy, float dz, float r2,
                                                float c2, float dd, int) {
-        if (r2 < c2 && r2 > 0.0f) {
-            const float f = fmaf(k * dd, rsqrtf(r2), -k);
-            F[0] = fmaf(-f, dx, F[0]);
-            F[1] = fmaf(-f, dy, F[1]);
-            F[2] = fmaf(-f, dz, F[2]);
-        }
+        const float fr = fmaf(k * dd, __builtin_amdgcn_rsqf(r2 + 1e-20f), -k);
+        const float f = r2 < c2 ? fr : 0.0f;
+        F[0] = fmaf(-f, dx, F[0]);
+        F[1] = fmaf(-f, dy, F[1]);
+        F[2] = fmaf(-f, dz, F[2]);
     }
 };
 
