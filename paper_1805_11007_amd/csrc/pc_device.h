@@ -165,8 +165,8 @@ __device__ __forceinline__ void pair_one(const StepParams &p, const SpTab &tab, 
 // (+ seam shift), r2 = dx.dx in plain float32 operations left to right; the
 // visitor receives every candidate with its squared contact distance c2 and
 // contact distance dd and decides what a neighbour is (r2 < c2).  Loads are
-// issued four candidates ahead of the arithmetic so that one wave keeps
-// several memory requests in flight.
+// issued eight (then four) candidates ahead of the arithmetic so that one
+// wave keeps several memory requests in flight.
 template <int DIM, int NS, bool SHIFT, class V>
 __device__ __forceinline__ void pair_range(const StepParams &p, const SpTab &tab,
                                            const float4 *__restrict__ Ps, uint32_t a,
@@ -176,6 +176,18 @@ __device__ __forceinline__ void pair_range(const StepParams &p, const SpTab &tab
     uint32_t j = a;
     // one 64-bit address per group of four; the rest are immediate offsets
     const float4 *__restrict__ qp = Ps + a;
+    for (; j + 8 <= e; j += 8, qp += 8) {
+        const float4 q0 = qp[0], q1 = qp[1], q2 = qp[2], q3 = qp[3];
+        const float4 q4 = qp[4], q5 = qp[5], q6 = qp[6], q7 = qp[7];
+        pair_one<DIM, NS, SHIFT>(p, tab, j, q0, pi, si, sx, sy, sz, c2row, drow, v);
+        pair_one<DIM, NS, SHIFT>(p, tab, j + 1, q1, pi, si, sx, sy, sz, c2row, drow, v);
+        pair_one<DIM, NS, SHIFT>(p, tab, j + 2, q2, pi, si, sx, sy, sz, c2row, drow, v);
+        pair_one<DIM, NS, SHIFT>(p, tab, j + 3, q3, pi, si, sx, sy, sz, c2row, drow, v);
+        pair_one<DIM, NS, SHIFT>(p, tab, j + 4, q4, pi, si, sx, sy, sz, c2row, drow, v);
+        pair_one<DIM, NS, SHIFT>(p, tab, j + 5, q5, pi, si, sx, sy, sz, c2row, drow, v);
+        pair_one<DIM, NS, SHIFT>(p, tab, j + 6, q6, pi, si, sx, sy, sz, c2row, drow, v);
+        pair_one<DIM, NS, SHIFT>(p, tab, j + 7, q7, pi, si, sx, sy, sz, c2row, drow, v);
+    }
     for (; j + 4 <= e; j += 4, qp += 4) {
         const float4 q0 = qp[0], q1 = qp[1], q2 = qp[2], q3 = qp[3];
         pair_one<DIM, NS, SHIFT>(p, tab, j, q0, pi, si, sx, sy, sz, c2row, drow, v);

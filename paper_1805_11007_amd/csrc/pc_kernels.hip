@@ -150,9 +150,11 @@ __global__ void __launch_bounds__(256) k_scan_apply(uint32_t *__restrict__ count
         uint4 *st4 = reinterpret_cast<uint4 *>(start + base);
         st4[0] = make_uint4(o[0], o[1], o[2], o[3]);
         st4[1] = make_uint4(o[4], o[5], o[6], o[7]);
+        // clear the counts for the next histogram, skipping groups already
+        // zero (most bins are empty, so most lines stay clean)
         uint4 *c4 = reinterpret_cast<uint4 *>(count + base);
-        c4[0] = make_uint4(0u, 0u, 0u, 0u);
-        c4[1] = make_uint4(0u, 0u, 0u, 0u);
+        if (v[0] | v[1] | v[2] | v[3]) c4[0] = make_uint4(0u, 0u, 0u, 0u);
+        if (v[4] | v[5] | v[6] | v[7]) c4[1] = make_uint4(0u, 0u, 0u, 0u);
     } else {
         for (int k = 0; k < 8; ++k)
             if (base + k < n) {
