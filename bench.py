@@ -39,6 +39,30 @@ FP32_PEAK_TFLOPS = 157.3      # MI355X FP32 vector (counts packed dual-issue)
 # (~10) -> 140.  Integer Philox work is not counted.
 FLOP_PER_PAIR, FLOP_PER_AGENT = 18.0, 140.0
 
+# HBM bytes per launch of the update kernel on the 1M-agent 3D workload, from
+# rocprofv3 FETCH_SIZE and WRITE_SIZE runs (each scaled by the same counter's
+# reading for a plain device copy); valid only for the kernel sources they
+# were taken with, identified by a hash of those files.
+UPDATE_TRAFFIC_BYTES = 101.4e6
+UPDATE_TRAFFIC_SOURCES = ("pc_internal.h", "pc_device.h", "pc_kernels.hip")
+UPDATE_TRAFFIC_SHA = "6d04533f0ee13dcf"
+
+
+def update_traffic(workload: str):
+    """Counter traffic of the update kernel, or None if the kernel sources
+    changed since the counters were taken or the workload differs."""
+    import hashlib
+    if workload != "cfg3_3d_periodic_1M_blobs":
+        return None
+    h = hashlib.sha256()
+    csrc = Path(__file__).resolve().parent / "paper_1805_11007_amd" / "csrc"
+    try:
+        for f in UPDATE_TRAFFIC_SOURCES:
+            h.update((csrc / f).read_bytes())
+    except OSError:
+        return None
+    return UPDATE_TRAFFIC_BYTES if h.hexdigest()[:16] == UPDATE_TRAFFIC_SHA else None
+
 
 def algorithmic_bytes(stage: str, w, n_sub: int) -> float:
     """Bytes a stage must move per launch (per step), by definition of what it
@@ -445,7 +469,8 @@ def main() -> int:
         flops = w.n_total * (FLOP_PER_PAIR * nbr_mean + FLOP_PER_AGENT)
         achieved = flops / (prof[dom] * 1e-3) / 1e12
         roof = {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": FP32_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
+                "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS,
+                "traffic": update_traffic(w.name),
                 "algorithmic_flop_per_launch": flops, "mean_neighbours": nbr_mean,
                 "launch_ms": prof[dom]}
     else:
