@@ -359,9 +359,9 @@ uint64_t orc_hash_id(uint32_t id) { return orc_splitmix64((uint64_t)id); }
 
 /* Neighbour sets decided in float32, as the float32 GPU state decides them:
  * dx = x_j - x_i (float32), minimum image by +-L when |dx| > L/2,
- * r2 = dx0*dx0 + dx1*dx1 (+ dx2*dx2) evaluated left to right without fused
- * multiply-add, neighbour iff r2 < cut2[s_i][s_j] (a float32 table of the
- * squared contact distances).  Output per agent: the neighbour count and the
+ * r2 = fma(dx2, dx2, fma(dx1, dx1, dx0*dx0)), every product and fused
+ * multiply-add rounded to float32 once (C99 fmaf); neighbour iff
+ * r2 < cut2[s_i][s_j] (a float32 table of the squared contact distances).  Output per agent: the neighbour count and the
  * wrap-around sum of splitmix64(id_j) over its neighbours. */
 void orc_neighbours_f32(int dim, int periodic, float L, int64_t n, const float *X,
                         const uint8_t *sp, const uint32_t *ids, const float *cut2, int n_species,
@@ -395,9 +395,9 @@ void orc_neighbours_f32(int dim, int periodic, float L, int64_t n, const float *
                     }
                     dx[a] = d;
                 }
-                volatile float r2 = dx[0] * dx[0];
-                r2 = r2 + dx[1] * dx[1];
-                if (dim == 3) r2 = r2 + dx[2] * dx[2];
+                volatile float x2 = dx[0] * dx[0];
+                volatile float r2 = fmaf(dx[1], dx[1], x2);
+                if (dim == 3) r2 = fmaf(dx[2], dx[2], r2);
                 if (r2 < cut2[sp[i] * n_species + sp[j]]) {
                     cnt++;
                     h += orc_splitmix64((uint64_t)ids[j]);

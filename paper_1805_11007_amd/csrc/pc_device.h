@@ -122,10 +122,10 @@ __device__ __forceinline__ uint32_t agent_bin(const StepParams &p, float4 x) {
     return (uint32_t)(bx + p.nb * (by + p.nb * bz));
 }
 
-// Candidates j in [a, e) of one contiguous bin range.  dx = (x_j - x_i)
-// (+ seam shift), r2 = dx.dx in plain float32 operations left to right; the
-// visitor receives every candidate with its squared contact distance c2 and
-// contact distance dd and decides what a neighbour is (r2 < c2).
+// One candidate j.  dx = (x_j - x_i) (+ seam shift) and r2 = fma(dz, dz,
+// fma(dy, dy, dx * dx)) in float32 (each fused multiply-add rounded once);
+// the visitor receives every candidate with its squared contact distance c2
+// and contact distance dd and decides what a neighbour is (r2 < c2).
 template <int DIM, int NS, bool SHIFT, class V>
 __device__ __forceinline__ void pair_one(const StepParams &p, const SpTab &tab, uint32_t j,
                                          const float4 &q, const float4 &pi, int si, float sx,
@@ -136,11 +136,11 @@ __device__ __forceinline__ void pair_one(const StepParams &p, const SpTab &tab, 
         dx = dx + sx;
         dy = dy + sy;
     }
-    float r2 = dx * dx + dy * dy;
+    float r2 = fmaf(dy, dy, dx * dx);
     if (DIM == 3) {
         dz = q.z - pi.z;
         if (SHIFT) dz = dz + sz;
-        r2 = r2 + dz * dz;
+        r2 = fmaf(dz, dz, r2);
     }
     float c2, dd;
     int sj;
@@ -161,12 +161,9 @@ __device__ __forceinline__ void pair_one(const StepParams &p, const SpTab &tab, 
     v(j, dx, dy, dz, r2, c2, dd, sj);
 }
 
-// Candidates j in [a, e) of one contiguous bin range.  dx = (x_j - x_i)
-// (+ seam shift), r2 = dx.dx in plain float32 operations left to right; the
-// visitor receives every candidate with its squared contact distance c2 and
-// contact distance dd and decides what a neighbour is (r2 < c2).  Loads are
-// issued eight (then four) candidates ahead of the arithmetic so that one
-// wave keeps several memory requests in flight.
+// Candidates j in [a, e) of one contiguous bin range, each as pair_one.
+// Loads are issued eight (then four) candidates ahead of the arithmetic so
+// that one wave keeps several memory requests in flight.
 template <int DIM, int NS, bool SHIFT, class V>
 __device__ __forceinline__ void pair_range(const StepParams &p, const SpTab &tab,
                                            const float4 *__restrict__ Ps, uint32_t a,
