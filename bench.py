@@ -45,7 +45,7 @@ FLOP_PER_PAIR, FLOP_PER_AGENT = 18.0, 140.0
 # were taken with, identified by a hash of those files.
 UPDATE_TRAFFIC_BYTES = 101.4e6
 UPDATE_TRAFFIC_SOURCES = ("pc_internal.h", "pc_device.h", "pc_kernels.hip")
-UPDATE_TRAFFIC_SHA = "6d04533f0ee13dcf"
+UPDATE_TRAFFIC_SHA = "941fc42bdb6710ea"
 
 
 def update_traffic(workload: str):
