@@ -165,7 +165,8 @@ def ensemble_leg(steps: int = 500, plain_steps: int = 50) -> dict:
             "batched_particle_steps_per_s": batched, "batched_steps": steps,
             "plain_particle_steps_per_s": plain, "plain_steps_per_instance": plain_steps,
             "speedup_vs_plain": batched / plain,
-            "tuned": {"bin_size": spec.bin_size, "block": spec.block}}
+            "tuned": {"bin_size": spec.bin_size, "block": spec.block,
+                      "deposit_mode": spec.deposit_mode}}
 
 
 def fig1_leg(hist_n: int = 52) -> dict:
@@ -178,10 +179,12 @@ def fig1_leg(hist_n: int = 52) -> dict:
     import torch
     import workloads as W
     from paper_1805_11007_amd import ModelSpec, Sim
+    from paper_1805_11007_amd.autotune import tune
     w = W.config(6)
     inp = W.make_inputs(w)
     x0, s0, c0 = (torch.from_numpy(inp[k]).cuda() for k in ("x0", "species0", "c0"))
-    sim = Sim(ModelSpec.from_workload(w), x0, s0, c0)
+    spec, _ = tune(ModelSpec.from_workload(w), x0, s0, c0)
+    sim = Sim(spec, x0, s0, c0)
     sim.use_graph(True)
     sim.step(4)
     sim.set_state(x0, c0, 0)
@@ -205,6 +208,8 @@ def fig1_leg(hist_n: int = 52) -> dict:
     r_dt = w.species[0].react_rate * w.dt
     n_a0 = tot[0][0]
     return {"workload": w.name, "realisations": w.n_inst, "agents_total": w.n_total,
+            "tuned": {"bin_size": spec.bin_size, "block": spec.block,
+                      "deposit_mode": spec.deposit_mode},
             "steps": w.steps, "T_f": w.steps * w.dt, "wall_s": ms / 1e3,
             "ms_per_step": ms / w.steps,
             "particle_steps_per_s": w.n_total * w.steps / (ms / 1e3),

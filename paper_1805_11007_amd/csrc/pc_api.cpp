@@ -404,7 +404,8 @@ static void ensure_sorted(pc_sim *s, hipStream_t st) {
     s->sorted = 1;
 }
 
-// PDE substeps of a step after the deposit; the last one clears the deposits.
+// PDE substeps of a step after the deposit; the last one clears the deposits
+// and advances the step counter.
 static void enqueue_pde(pc_sim *s, hipStream_t st) {
     for (int k = 0; k < s->d.n_sub; ++k) {
         launch_pde(s->pp, s->b, s->cur_c, 1 - s->cur_c, k == s->d.n_sub - 1 ? 1 : 0, st);
@@ -444,11 +445,9 @@ static void enqueue_step(pc_sim *s, hipStream_t st) {
         ensure_sorted(s, st);
         launch_kde(s->sp, s->b, s->sorted_src, st);
         enqueue_pde(s, st);
-        launch_step_inc(s->b, st);
         return;
     }
     enqueue_chem(s, st);
-    launch_step_inc(s->b, st);
     s->binned = 1;
     s->sorted = 0;
 }
@@ -726,7 +725,6 @@ int pc_profile_steps(pc_sim *s, int n_steps, double *stage_ms) {
             PC_STAGE(PC_STAGE_PDE, enqueue_pde(s, st));
         }
 #undef PC_STAGE
-        launch_step_inc(s->b, st);
         s->host_step += 1;
         HIP_OK(hipStreamSynchronize(st));
         for (int k = 0; k < PC_N_STAGES; ++k) {

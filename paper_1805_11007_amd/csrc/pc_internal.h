@@ -141,7 +141,6 @@ void launch_update(const StepParams &p, const Buffers &b, int src, int dst, int 
 void launch_deposit(const StepParams &p, const Buffers &b, int src, hipStream_t s);
 void launch_pde(const PdeParams &q, const Buffers &b, int cin, int cout, int last,
                 hipStream_t s);
-void launch_step_inc(const Buffers &b, hipStream_t s);
 void launch_zero_u32(uint32_t *d, int64_t n, hipStream_t s);
 void launch_kde(const StepParams &p, const Buffers &b, int src, hipStream_t s);
 void launch_overlap(const StepParams &p, const Buffers &b, int src, int dst, int block,

@@ -489,7 +489,10 @@ template <int DIM, int NS, bool UPT>
 __global__ void __launch_bounds__(1024)
 k_chem_inst(StepParams p, PdeParams q, const InstInfo *__restrict__ inst,
             const float4 *__restrict__ P, float *__restrict__ c0, float *__restrict__ c1, int cur,
-            int n_sub, uint32_t *__restrict__ flags) {
+            int n_sub, uint32_t *__restrict__ flags, uint32_t *__restrict__ stepc) {
+    // the last kernel of a step advances the step counter (the update,
+    // which reads it, has finished)
+    if (blockIdx.x == 0 && threadIdx.x == 0) *stepc += 1u;
     extern __shared__ unsigned long long S[];  // G source sums, then G uptake sums
     __shared__ SpTab tab;
     const int G = q.nodes_per_inst;
@@ -526,13 +529,15 @@ k_chem_inst(StepParams p, PdeParams q, const InstInfo *__restrict__ inst,
 // PDE substep, one thread per node; the last substep of a step clears the
 // deposits for the next step.
 // KDE: the source array holds (sigma, upsilon) float pairs, rewritten by
-// every step's density gather, so nothing is cleared.
+// every step's density gather, so nothing is cleared.  stepc (non-null on
+// the last substep of a step): the step counter, advanced by node 0.
 template <int DIM, bool KDE>
 __global__ void __launch_bounds__(256)
 k_pde(PdeParams q, const float *__restrict__ cin, float *__restrict__ cout,
       unsigned long long *__restrict__ Ssrc, unsigned long long *__restrict__ Supt, int last,
-      uint32_t *__restrict__ flags) {
+      uint32_t *__restrict__ flags, uint32_t *__restrict__ stepc) {
     const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (stepc && l == 0) *stepc += 1u;
     if (l >= q.n_nodes_total) return;
     const int n = q.grid_n;
     const int64_t G = q.nodes_per_inst;
@@ -554,8 +559,6 @@ k_pde(PdeParams q, const float *__restrict__ cin, float *__restrict__ cout,
     }
     if (flag) atomicOr(flags, flag);
 }
-
-__global__ void k_step_inc(uint32_t *stepc) { *stepc += 1u; }
 
 __global__ void k_zero_u32(uint32_t *__restrict__ d, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -868,7 +871,7 @@ static void chem(const StepParams &p, const PdeParams &q, const Buffers &b, int 
                  int n_sub, hipStream_t s) {
     const size_t lds = 8 * (size_t)q.nodes_per_inst * (UPT ? 2 : 1);
     hipLaunchKernelGGL((k_chem_inst<DIM, NS, UPT>), dim3(p.n_inst), dim3(1024), lds, s, p, q,
-                       b.inst, b.P[src], b.c[0], b.c[1], cur, n_sub, b.flags);
+                       b.inst, b.P[src], b.c[0], b.c[1], cur, n_sub, b.flags, b.step);
 }
 
 size_t chem_inst_lds_bytes(const PdeParams &q) {
@@ -901,32 +904,33 @@ void launch_pde(const PdeParams &q, const Buffers &b, int cin, int cout, int las
     if (q.kde) {
         if (q.dim == 2)
             hipLaunchKernelGGL((k_pde<2, true>), g, t, 0, s, q, b.c[cin], b.c[cout], b.S_src,
-                               b.S_upt, last, b.flags);
+                               b.S_upt, last, b.flags,
+                               last ? b.step : nullptr);
         else
             hipLaunchKernelGGL((k_pde<3, true>), g, t, 0, s, q, b.c[cin], b.c[cout], b.S_src,
-                               b.S_upt, last, b.flags);
+                               b.S_upt, last, b.flags,
+                               last ? b.step : nullptr);
         return;
     }
     if (q.dim == 2)
         hipLaunchKernelGGL((k_pde<2, false>), g, t, 0, s, q, b.c[cin], b.c[cout], b.S_src,
-                           b.S_upt, last, b.flags);
+                           b.S_upt, last, b.flags, last ? b.step : nullptr);
     else
         hipLaunchKernelGGL((k_pde<3, false>), g, t, 0, s, q, b.c[cin], b.c[cout], b.S_src,
-                           b.S_upt, last, b.flags);
+                           b.S_upt, last, b.flags, last ? b.step : nullptr);
 }
 
 void launch_pde_ptr(const PdeParams &q, const float *cin, float *cout, unsigned long long *Ssrc,
                     unsigned long long *Supt, int last, uint32_t *flags, hipStream_t s) {
     const dim3 g(grid_for(q.n_nodes_total, 256)), t(256);
     if (q.dim == 2)
-        hipLaunchKernelGGL((k_pde<2, false>), g, t, 0, s, q, cin, cout, Ssrc, Supt, last, flags);
+        hipLaunchKernelGGL((k_pde<2, false>), g, t, 0, s, q, cin, cout, Ssrc, Supt, last, flags,
+                           nullptr);
     else
-        hipLaunchKernelGGL((k_pde<3, false>), g, t, 0, s, q, cin, cout, Ssrc, Supt, last, flags);
+        hipLaunchKernelGGL((k_pde<3, false>), g, t, 0, s, q, cin, cout, Ssrc, Supt, last, flags,
+                           nullptr);
 }
 
-void launch_step_inc(const Buffers &b, hipStream_t s) {
-    hipLaunchKernelGGL(k_step_inc, dim3(1), dim3(1), 0, s, b.step);
-}
 
 void launch_zero_u32(uint32_t *d, int64_t n, hipStream_t s) {
     if (n <= 0) return;
