@@ -53,14 +53,44 @@ k_kde(StepParams p, const InstInfo *__restrict__ inst, const float4 *__restrict_
             cnt[a] = b1 - b0 + 1;
         }
     }
+    // distance from the node to a row of bins along y (z): zero for the
+    // node's own bin row, else to the nearer face of the row's slab
+    const float side = p.L / (float)nb;
+    auto slab_d = [&](int a, int c) -> float {
+        const float b = floorf(pc[a] * p.inv_bin);      // node's own bin (unwrapped)
+        const float q = floorf((pc[a] - p.kde_R) * p.inv_bin) + (float)c;  // row's bin
+        if (q < b) return pc[a] - (q + 1.0f) * side;
+        if (q > b) return q * side - pc[a];
+        return 0.0f;
+    };
+    const float R2 = p.kde_R * p.kde_R;
     float sig = 0.0f, ups = 0.0f;
     for (int cz = 0; cz < cnt[2]; ++cz) {
         const int bz = DIM == 3 ? (lo[2] + cz) % nb : 0;
+        const float dz = DIM == 3 && p.periodic ? fmaxf(slab_d(2, cz), 0.0f) : 0.0f;
         for (int cy = 0; cy < cnt[1]; ++cy) {
             const int by = (lo[1] + cy) % nb;
             const uint32_t row = bb + (uint32_t)(nb * (by + nb * bz));
-            // the x range as at most two contiguous runs of bins
-            const int x0 = lo[0], x1 = lo[0] + cnt[0];
+            // rows beyond the ball, and x bins beyond its chord, are skipped
+            // (torus only: with walls lo[] is clamped and the walk is plain)
+            int x0 = lo[0], x1 = lo[0] + cnt[0];
+            if (p.periodic) {
+                const float dy = fmaxf(slab_d(1, cy), 0.0f);
+                const float d2 = dy * dy + dz * dz;
+                if (d2 >= R2) continue;
+                const float ext = sqrtf(R2 - d2);
+                const int c0 = (int)floorf((pc[0] - ext) * p.inv_bin);
+                const int c1 = (int)floorf((pc[0] + ext) * p.inv_bin);
+                const int u0 = (int)floorf((pc[0] - p.kde_R) * p.inv_bin);
+                const int skip = max(c0 - u0, 0);
+                x0 = lo[0] + skip;
+                x1 = lo[0] + min(c1 - u0 + 1, cnt[0]);
+                if (x1 <= x0) continue;
+                if (x0 >= nb) {  // keep the first run's start inside the row
+                    x0 -= nb;
+                    x1 -= nb;
+                }
+            }
             const int runs = x1 > nb ? 2 : 1;
             for (int r = 0; r < runs; ++r) {
                 const int a0 = r == 0 ? x0 : 0;
