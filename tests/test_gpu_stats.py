@@ -83,3 +83,29 @@ def test_stats_along_a_trajectory_match_oracle_run(n_real):
     x, c, _ = sim.get_state()
     assert pos_err(x.cpu().numpy(), Xo64, w.L, w.periodic) <= 1e-5 * steps
     assert field_err(c.cpu().numpy(), co) <= 1e-5 * steps
+
+
+def test_fig1_full_size_sampled_realisations_match_oracle():
+    """The 2000-realisation batch (per-instance fused deposit + PDE, graph
+    replay) against the oracle run of three realisations on their own:
+    species bit-exact (constant switching rate), positions within 1e-5 L per
+    step, field within 1e-5 max|c| per step."""
+    w = W.config(6)
+    inp = W.make_inputs(w)
+    sim = make_sim(w, inp)
+    assert sim.info["deposit_path"] == 3
+    sim.use_graph(True)
+    steps = 12
+    sim.step(steps)
+    x, c, _ = sim.get_state()
+    x, c = x.cpu().numpy(), c.cpu().numpy()
+    sp = sim.species().cpu().numpy()
+    G = w.grid_n ** 2
+    for k in (0, 777, 1999):
+        a, n = 200 * k, 200
+        p = oracle.params(w, k)
+        Xo, co, _, so = oracle.run(p, inp["x0"][a:a + n], inp["species0"][a:a + n],
+                                   inp["c0"][k * G:(k + 1) * G], 0, steps, return_species=True)
+        assert np.array_equal(sp[a:a + n], so), k
+        assert pos_err(x[a:a + n], Xo, w.L, w.periodic) <= 1e-5 * steps, k
+        assert field_err(c[k * G:(k + 1) * G], co) <= 1e-5 * steps, k
