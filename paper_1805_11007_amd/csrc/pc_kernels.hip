@@ -341,7 +341,7 @@ __device__ __forceinline__ float pde_node(const PdeParams &q, const float *__res
 // close) are first summed in an LDS hash table keyed by node, then flushed
 // with one device atomic per distinct node.  Integer sums make the result
 // independent of the summation order.
-constexpr int kDepSlots = 2048;
+constexpr int kDepSlots = 4096;
 constexpr uint32_t kEmpty = 0xFFFFFFFFu;
 
 __device__ __forceinline__ void lds_insert(uint32_t *keys, unsigned long long *vs,
@@ -349,7 +349,7 @@ __device__ __forceinline__ void lds_insert(uint32_t *keys, unsigned long long *v
                                            unsigned long long a, unsigned long long b,
                                            unsigned long long *Ssrc,
                                            unsigned long long *Supt) {
-    uint32_t h = (key * 2654435761u) >> 21;  // 11 bits: kDepSlots = 2048
+    uint32_t h = (key * 2654435761u) >> 20;  // 12 bits: kDepSlots = 4096
     for (int probe = 0; probe < 16; ++probe) {
         const uint32_t old = atomicCAS(&keys[h], kEmpty, key);
         if (old == kEmpty || old == key) {
@@ -404,7 +404,7 @@ __device__ __forceinline__ bool deposit_corners(const StepParams &p, const SpTab
 // device atomic): cheaper when agents are sparse next to the nodes, so that
 // a work-group's agents rarely share a node.
 template <int DIM, int NS, bool UPT, bool AGG>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(1024)
 k_deposit(StepParams p, const InstInfo *__restrict__ inst, const float4 *__restrict__ P,
           unsigned long long *__restrict__ Ssrc, unsigned long long *__restrict__ Supt) {
     constexpr int slots = AGG ? kDepSlots : 1;
@@ -840,8 +840,8 @@ void launch_debug_pairs(const StepParams &p, const Buffers &b, int src, uint32_t
 template <int DIM, int NS, bool UPT>
 static void dep(const StepParams &p, const Buffers &b, int src, hipStream_t s) {
     if (p.deposit_agg)
-        hipLaunchKernelGGL((k_deposit<DIM, NS, UPT, true>), dim3(grid_for(p.n_total, 256)),
-                           dim3(256), 0, s, p, b.inst, b.P[src], b.S_src, b.S_upt);
+        hipLaunchKernelGGL((k_deposit<DIM, NS, UPT, true>), dim3(grid_for(p.n_total, 1024)),
+                           dim3(1024), 0, s, p, b.inst, b.P[src], b.S_src, b.S_upt);
     else
         hipLaunchKernelGGL((k_deposit<DIM, NS, UPT, false>), dim3(grid_for(p.n_total, 256)),
                            dim3(256), 0, s, p, b.inst, b.P[src], b.S_src, b.S_upt);
