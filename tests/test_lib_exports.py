@@ -56,3 +56,29 @@ def test_workspace_bytes_and_validation():
             workspace_bytes(_spec(**over))
     L = _lib.load()
     assert L.pc_strerror(-2).decode().startswith("explicit PDE")
+
+
+def test_validation_of_variant_parameters():
+    """Host-side checks of the switching, deposit and potential options."""
+    from paper_1805_11007_amd import PcError, SpeciesSpec, workspace_bytes
+    from paper_1805_11007_amd import _lib
+    if not _lib.LIB_PATH.exists():
+        pytest.skip("libpc.so not built")
+    two = [SpeciesSpec(0.01, 1.0), SpeciesSpec(0.01, 1.0)]
+    ok = [dict(species=[SpeciesSpec(0.01, 1.0, react_to=1, react_rate=5.0), two[1]]),
+          dict(species=[SpeciesSpec(0.01, 1.0, react_to=0, react_rate=0.0)]),  # no rate: no switch
+          dict(deposit_kernel=1, kde_radius=4.0), dict(potential=1, pot_range=2.0),
+          dict(potential=2), dict(tamed=True), dict(deposit_mode=2)]
+    for over in ok:
+        assert workspace_bytes(_spec(**over)) > 0, over
+    bad = [dict(species=[SpeciesSpec(0.01, 1.0, react_to=2, react_rate=5.0), two[1]]),
+           dict(species=[SpeciesSpec(0.01, 1.0, react_to=0, react_rate=5.0)]),   # to itself
+           dict(species=[SpeciesSpec(0.01, 1.0, react_to=1, react_rate=-1.0), two[1]]),
+           dict(species=[SpeciesSpec(0.01, 1.0, react_to=1, react_rate_c=float("inf")), two[1]]),
+           dict(deposit_kernel=2), dict(deposit_kernel=1, kde_radius=60.0),
+           dict(deposit_kernel=1, deposit_mode=3), dict(deposit_kernel=1, potential=2),
+           dict(potential=3), dict(potential=1, pot_range=0.5), dict(potential=1, pot_range=60.0),
+           dict(deposit_mode=4)]
+    for over in bad:
+        with pytest.raises(PcError):
+            workspace_bytes(_spec(**over))
