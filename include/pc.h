@@ -89,7 +89,7 @@ typedef struct {
     double bin_size;        /* 0: automatic; else the cell-list bin side (>= cutoff)    */
     int32_t deterministic;  /* 1: agents ordered by id inside each bin, so results are
                                bitwise reproducible run to run                          */
-    int32_t block;          /* 0: automatic; else work-group size of the agent kernels
+    int32_t block;          /* 0: 128; else work-group size of the agent kernels
                                (64, 128, 256, 512 or 1024)                              */
     int32_t bin_order;      /* 0: row-major bins (x fastest); 1: 2x2(x2) brick order     */
     int32_t deposit_mode;   /* 0: automatic; 1: contributions summed per work-group in

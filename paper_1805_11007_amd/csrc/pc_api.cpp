@@ -185,7 +185,7 @@ int derive(const pc_config *cfg, const pc_species_t *sp, int ns, const pc_instan
         d.n_sub = (int)ceil(r / (0.9 * lim));
         if (d.n_sub < 1) d.n_sub = 1;
     }
-    d.block = cfg->block ? cfg->block : 256;
+    d.block = cfg->block ? cfg->block : 128;
     d.warn = 0;
     for (int a = 0; a < ns; ++a)
         for (int b = 0; b < ns; ++b) {
