@@ -204,8 +204,8 @@ k_adj_agent(StepParams p, AdjArgs A, const InstInfo *__restrict__ inst,
         const InstInfo ii = inst[k];
         const size_t row = ii.agent_base + id;
         // recompute the forward update up to the boundary map
-        ForceVisitor fv{p.k, {0.f, 0.f, 0.f}};
-        pair_loop<DIM, NS, STENCIL>(p, tab, Ps, start, ii.bin_base, pi, si, fv);
+        ForceVisitor fv{p.k, p.fcap, {0.f, 0.f, 0.f}};
+        if (p.k != 0.0f) pair_loop<DIM, NS, STENCIL>(p, tab, Ps, start, ii.bin_base, pi, si, fv);
         const float chi = sel<NS>(p.chi, tab.chi, si) * ii.chi_scale;
         float Ig[3] = {0.f, 0.f, 0.f}, dI[3][3] = {{0.f}};
         Corners<DIM> C0;

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 #include <string>
 #include <vector>
@@ -289,6 +290,9 @@ static void fill_params(pc_sim *s) {
     p.inv_h2 = (float)(1.0 / (d.h * d.h));
     p.dt = (float)c.dt;
     p.k = (float)c.k_rep;
+    // the factor k (d / r - 1) reaches this only for r < 1e-10 d; it keeps
+    // the factor finite at r = 0, where it multiplies dx = 0
+    p.fcap = (float)std::min(1e10 * c.k_rep * d.contact_max, 1e38);
     p.cell_top = (float)(d.periodic ? c.grid_n - 1 : c.grid_n - 2);
     for (int a = 0; a < d.ns; ++a) {
         for (int b = 0; b < d.ns; ++b) {

@@ -206,12 +206,16 @@ __device__ __forceinline__ void pair_range(const StepParams &p, const SpTab &tab
 // through the product with dx; the 1e-20 added to r2 keeps f finite there
 // and leaves r2 of any two distinct float32 positions in the box unchanged.
 struct ForceVisitor {
-    float k;
+    float k, fcap;
     float F[3];
+    // The factor k (d / r - 1) is positive exactly for overlapping pairs
+    // (r < d, up to the rounding of rsq; at r = d the force vanishes), so
+    // clamping it to [0, fcap] selects them without a compare.  At r = 0
+    // rsq gives +inf and the clamp leaves fcap * dx = 0.
     __device__ __forceinline__ void operator()(uint32_t, float dx, float dy, float dz, float r2,
-                                               float c2, float dd, int) {
-        const float fr = fmaf(k * dd, __builtin_amdgcn_rsqf(r2 + 1e-20f), -k);
-        const float f = r2 < c2 ? fr : 0.0f;
+                                               float, float dd, int) {
+        const float fr = fmaf(k * dd, __builtin_amdgcn_rsqf(r2), -k);
+        const float f = __builtin_amdgcn_fmed3f(fr, 0.0f, fcap);
         F[0] = fmaf(-f, dx, F[0]);
         F[1] = fmaf(-f, dy, F[1]);
         F[2] = fmaf(-f, dz, F[2]);

@@ -38,6 +38,7 @@ struct StepParams {
     float inv_bin;         // nb / L
     float h, inv_h, inv_2h, inv_h2;
     float dt, k;
+    float fcap;            // upper clamp of the harmonic force factor, 1e10 k max d
     float cell_top;        // largest lower-corner index as float (n-1 periodic, n-2 walls)
     float cut2[kMaxSpecies * kMaxSpecies];  // float32 squared contact distances
     float dij[kMaxSpecies * kMaxSpecies];   // contact distances

@@ -222,7 +222,7 @@ k_update(StepParams p, const InstInfo *__restrict__ inst, const float4 *__restri
 
     float F[3] = {0.f, 0.f, 0.f};
     if (POT == 0) {
-        ForceVisitor fv{p.k, {0.f, 0.f, 0.f}};
+        ForceVisitor fv{p.k, p.fcap, {0.f, 0.f, 0.f}};
         pair_loop<DIM, NS, STENCIL>(p, tab, Ps, start, ii.bin_base, pi, si, fv);
         F[0] = fv.F[0];
         F[1] = fv.F[1];
@@ -629,13 +629,17 @@ k_debug_pairs(StepParams p, const InstInfo *__restrict__ inst, const float4 *__r
         hs = dv.hs;
         F[0] = dv.fv.F[0], F[1] = dv.fv.F[1], F[2] = dv.fv.F[2];
     } else {
-        // hard spheres exert no force
+        // hard spheres exert no force; with k = 0 the factor is 0 * inf at r = 0
         const float k = POT == 0 ? p.k : 0.0f;
-        DebugVisitor<ForceVisitor> dv{ForceVisitor{k, {0.f, 0.f, 0.f}}, (uint32_t)i, Is, 0u, 0ull};
+        DebugVisitor<ForceVisitor> dv{ForceVisitor{k, p.fcap, {0.f, 0.f, 0.f}}, (uint32_t)i, Is,
+                                      0u, 0ull};
         pair_loop<DIM, NS, STENCIL>(p, tab, Ps, start, ii.bin_base, pi, si, dv);
         cnt = dv.cnt;
         hs = dv.hs;
-        F[0] = dv.fv.F[0], F[1] = dv.fv.F[1], F[2] = dv.fv.F[2];
+        const bool force = k != 0.0f;
+        F[0] = force ? dv.fv.F[0] : 0.0f;
+        F[1] = force ? dv.fv.F[1] : 0.0f;
+        F[2] = force ? dv.fv.F[2] : 0.0f;
     }
     if (count) count[row] = cnt;
     if (hash) hash[row] = hs;
@@ -797,7 +801,9 @@ static void dbg(const StepParams &p, const Buffers &b, int src, uint32_t *count,
 
 void launch_update(const StepParams &p, const Buffers &b, int src, int dst, int cbuf, int block,
                    hipStream_t s) {
-    if (p.potential == 0) {
+    // the harmonic pair loop needs k > 0 (its force factor is 0 * inf at
+    // r = 0 when k = 0); with k = 0 the pair-free variant gives the same bits
+    if (p.potential == 0 && p.k != 0.0f) {
         PC_DISPATCH(upd, p, b, src, dst, cbuf, block, s);
         return;
     }
