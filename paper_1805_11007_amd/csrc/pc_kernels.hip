@@ -103,31 +103,51 @@ __global__ void __launch_bounds__(256) k_tile_sums(const uint32_t *__restrict__ 
     if (threadIdx.x == 0) tile_sum[blockIdx.x] = tot;
 }
 
+// Exclusive scan of the T tile sums in place by one work-group of 1024
+// threads: passes of 8192 sums, 8 consecutive sums per thread (two 16-byte
+// loads and stores), carrying the running total between passes.
 __global__ void __launch_bounds__(1024) k_scan_tiles(uint32_t *__restrict__ tile_sum, int T) {
     __shared__ uint32_t lds[16];
-    const int per = (T + 1023) / 1024;
-    const int b0 = threadIdx.x * per;
-    uint32_t s = 0;
-    for (int k = 0; k < per; ++k)
-        if (b0 + k < T) s += tile_sum[b0 + k];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    uint32_t x = s;
+    uint32_t carry = 0;
+    for (int64_t off = 0; off < T; off += 8192) {
+        const int64_t b0 = off + threadIdx.x * 8;
+        uint32_t v[8];
+        load8(tile_sum, b0, T, v);
+        const uint32_t s = ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]));
+        uint32_t x = s;
 #pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const uint32_t y = __shfl_up(x, d, 64);
-        if (lane >= d) x += y;
-    }
-    if (lane == 63) lds[wv] = x;
-    __syncthreads();
-    uint32_t base = 0;
-    for (int k = 0; k < wv; ++k) base += lds[k];
-    uint32_t run = base + x - s;
-    for (int k = 0; k < per; ++k)
-        if (b0 + k < T) {
-            const uint32_t t = tile_sum[b0 + k];
-            tile_sum[b0 + k] = run;
-            run += t;
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint32_t y = __shfl_up(x, d, 64);
+            if (lane >= d) x += y;
         }
+        if (lane == 63) lds[wv] = x;
+        __syncthreads();
+        uint32_t base = carry, total = 0;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const uint32_t t = lds[k];
+            if (k < wv) base += t;
+            total += t;
+        }
+        uint32_t run = base + x - s;
+        uint32_t o[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            o[k] = run;
+            run += v[k];
+        }
+        if (b0 + 8 <= T) {
+            uint4 *p4 = reinterpret_cast<uint4 *>(tile_sum + b0);
+            p4[0] = make_uint4(o[0], o[1], o[2], o[3]);
+            p4[1] = make_uint4(o[4], o[5], o[6], o[7]);
+        } else {
+            for (int k = 0; k < 8; ++k)
+                if (b0 + k < T) tile_sum[b0 + k] = o[k];
+        }
+        carry += total;
+        __syncthreads();
+    }
 }
 
 __global__ void __launch_bounds__(256) k_scan_apply(uint32_t *__restrict__ count, int64_t n,

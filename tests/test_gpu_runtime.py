@@ -1,5 +1,7 @@
 """GPU tests of the library's runtime behaviour: determinism, batching,
 graph replay, checkpoint / resume, error paths and edge cases."""
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -141,6 +143,30 @@ def test_edge_cases_single_agent_and_one_bin_pileup():
     X, c = oracle_steps(w, inp, 1)
     assert pos_err(sim.positions().cpu().numpy(), X, 1.0, True) <= 1e-5
     assert field_err(sim.field().cpu().numpy(), c) <= 1e-5
+
+
+def test_cell_list_with_more_than_8192_scan_tiles():
+    """265^3 bins + 1 = 9087 scan tiles of 2048 bins: the tile-sum scan runs
+    in two passes of 8192 with a ragged tail.  Neighbour sets stay bit-exact
+    against the float32 brute force, at creation and after the cell list has
+    been rebuilt by the steps (checked on the GPU's own positions)."""
+    w = W.scaled(W.config(3), n_agents=150000, grid_n=32)
+    w = dataclasses.replace(w, species=(dataclasses.replace(w.species[0], diameter=0.0037),))
+    inp = W.make_inputs(w)
+    sim = make_sim(w, inp, bin_size=1.0 / 265.5)
+    assert sim.info["n_bins_total"] == 265 ** 3
+    assert -(-(265 ** 3 + 1) // 2048) == 9087
+    cnt, hsh = sim.debug_neighbours()
+    ocnt, ohsh = oracle_neighbours(w, inp)
+    assert ocnt.sum() > 100000
+    assert np.array_equal(cnt.cpu().numpy().astype(np.uint32), ocnt)
+    assert np.array_equal(hsh.cpu().numpy().view(np.uint64), ohsh)
+    sim.step(3)
+    x = sim.positions().cpu().numpy()
+    cnt, hsh = sim.debug_neighbours()
+    ocnt, ohsh = oracle_neighbours(w, dict(inp, x0=x))
+    assert np.array_equal(cnt.cpu().numpy().astype(np.uint32), ocnt)
+    assert np.array_equal(hsh.cpu().numpy().view(np.uint64), ohsh)
 
 
 def test_error_paths():
