@@ -332,18 +332,27 @@ __device__ __forceinline__ void pair_loop(const StepParams &p, const SpTab &tab,
     }
     cmax2 *= 1.001f;
     const float L = p.L;
-    // When every lane of the wave sits in the same bin (the rule in dense
-    // clusters), the stencil rows and candidate ranges are the same for all
-    // lanes: the loop runs on wave-uniform indices (scalar registers), and a
-    // row or edge bin is skipped only if no lane of the wave can reach it.
-    const uint32_t own = (uint32_t)(lo[0] + 1) + 1024u * (uint32_t)(lo[1] + 1) +
-                         1048576u * (uint32_t)(DIM == 3 ? lo[2] + 1 : 0);
-    const bool uniform = STENCIL == 3 && __all(own == __builtin_amdgcn_readfirstlane(own));
+    // When every lane of the wave sits in one (y, z) row of bins and in at
+    // most two adjacent bins along x (the rule in dense clusters, where a bin
+    // holds about a wave of agents), every stencil row is one x range common
+    // to all lanes: the loop runs on wave-uniform indices (scalar registers).
+    // The range covers the lanes' own x bins plus the bin on either side if
+    // a lane there can reach it; a lane meets candidates of a bin outside its
+    // own stencil only beyond the cutoff, and with nb >= 4 the range never
+    // holds a bin twice.  A row is skipped only if no lane can reach it.
+    const int xo = lo[0] + 1;
+    const int xf = __builtin_amdgcn_readfirstlane(xo);
+    const int yf = __builtin_amdgcn_readfirstlane(lo[1]);
+    const int zf = DIM == 3 ? __builtin_amdgcn_readfirstlane(lo[2]) : 0;
+    const bool xdown = __any(xo == xf - 1), xup = __any(xo == xf + 1);
+    const bool uniform = STENCIL == 3 && nb >= 4 && !(xdown && xup) &&
+                         __all(lo[1] == yf && (DIM == 2 || lo[2] == zf) && xo >= xf - 1 &&
+                               xo <= xf + 1);
     if (uniform) {
-        const int zlo = DIM == 3 ? __builtin_amdgcn_readfirstlane(lo[2]) : 0;
+        const int zlo = zf;
         const int zhi = DIM == 3 ? zlo + 2 : 0;
-        const int ylo = __builtin_amdgcn_readfirstlane(lo[1]);
-        const int xb = __builtin_amdgcn_readfirstlane(lo[0]) + 1;
+        const int ylo = yf;
+        const int xmin = xdown ? xf - 1 : xf, xmax = xup ? xf + 1 : xf;
         for (int oz = zlo; oz <= zhi; ++oz) {
             int qz = oz;
             float sz = 0.0f;
@@ -373,8 +382,8 @@ __device__ __forceinline__ void pair_loop(const StepParams &p, const SpTab &tab,
                 float d2 = oy < ylo + 1 ? glo2[1] : (oy > ylo + 1 ? ghi2[1] : 0.0f);
                 if (DIM == 3) d2 += oz < zlo + 1 ? glo2[2] : (oz > zlo + 1 ? ghi2[2] : 0.0f);
                 if (!__any(d2 < cmax2)) continue;
-                const int xlo = __any(d2 + glo2[0] < cmax2) ? xb - 1 : xb;
-                const int xhi = __any(d2 + ghi2[0] < cmax2) ? xb + 1 : xb;
+                const int xlo = __any(xo == xmin && d2 + glo2[0] < cmax2) ? xmin - 1 : xmin;
+                const int xhi = __any(xo == xmax && d2 + ghi2[0] < cmax2) ? xmax + 1 : xmax;
                 const uint32_t row = bin_base + (uint32_t)((qz * nb + qy) * nb);
                 const int m0 = max(xlo, 0), m1 = min(xhi, nb - 1);
                 const uint32_t a0 = __builtin_amdgcn_readfirstlane(start[row + m0]);

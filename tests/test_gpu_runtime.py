@@ -169,6 +169,32 @@ def test_cell_list_with_more_than_8192_scan_tiles():
     assert np.array_equal(hsh.cpu().numpy().view(np.uint64), ohsh)
 
 
+def test_wave_across_bin_rows_with_more_than_1024_bins_per_side():
+    """1100 bins per side; 32 agents in bin (1030, 5) and 32 in bin (6, 6)
+    form one wave in cell order.  A bin id packed as x + 1024 y is the same
+    for both bins, so a wave-uniform test built on it would give the second
+    half the first half's stencil and lose its neighbours."""
+    w = W.scaled(W.config(1), n_agents=64)
+    w = dataclasses.replace(w, species=(dataclasses.replace(w.species[0], diameter=0.0009),))
+    inp = W.make_inputs(w)
+    rng = np.random.default_rng(7)
+    x0 = np.empty((64, 2), np.float32)
+    x0[:32] = ((np.array([1030.0, 5.0]) + rng.uniform(0.05, 0.95, (32, 2))) / 1100).astype(np.float32)
+    x0[32:] = ((np.array([6.0, 6.0]) + rng.uniform(0.05, 0.95, (32, 2))) / 1100).astype(np.float32)
+    assert 1030 + 1024 * 5 == 6 + 1024 * 6
+    inp = dict(inp, x0=x0)
+    sim = make_sim(w, inp, bin_size=1.0 / 1100.5)
+    assert sim.info["bins_per_axis"] == 1100
+    cnt, hsh = sim.debug_neighbours()
+    ocnt, ohsh = oracle_neighbours(w, inp)
+    assert ocnt[:32].sum() > 32 and ocnt[32:].sum() > 32
+    assert np.array_equal(cnt.cpu().numpy().astype(np.uint32), ocnt)
+    assert np.array_equal(hsh.cpu().numpy().view(np.uint64), ohsh)
+    sim.step(1)
+    X, c = oracle_steps(w, inp, 1)
+    assert pos_err(sim.positions().cpu().numpy(), X, 1.0, True) <= 1e-5
+
+
 def test_error_paths():
     import torch
     from paper_1805_11007_amd import ModelSpec, PcError, Sim
