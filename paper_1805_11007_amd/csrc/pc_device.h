@@ -281,6 +281,9 @@ struct DebugVisitor {
 // because the seam is crossed iff |x_j - x_i| > L/2 for such pairs.
 // Along x, neighbouring bins are adjacent in memory, so each (y, z) row of
 // the stencil is one contiguous agent range (two at the seam).
+// widest run of x bins a wave may span on the wave-uniform pair path
+constexpr int kSpan = 3;
+
 template <int DIM, int NS, int STENCIL, class V>
 __device__ __forceinline__ void pair_loop(const StepParams &p, const SpTab &tab,
                                           const float4 *__restrict__ Ps,
@@ -332,27 +335,32 @@ __device__ __forceinline__ void pair_loop(const StepParams &p, const SpTab &tab,
     }
     cmax2 *= 1.001f;
     const float L = p.L;
-    // When every lane of the wave sits in one (y, z) row of bins and in at
-    // most two adjacent bins along x (the rule in dense clusters, where a bin
+    // When every lane of the wave sits in one (y, z) row of bins and within
+    // kSpan adjacent bins along x (the rule in dense clusters, where a bin
     // holds about a wave of agents), every stencil row is one x range common
     // to all lanes: the loop runs on wave-uniform indices (scalar registers).
     // The range covers the lanes' own x bins plus the bin on either side if
     // a lane there can reach it; a lane meets candidates of a bin outside its
-    // own stencil only beyond the cutoff, and with nb >= 4 the range never
-    // holds a bin twice.  A row is skipped only if no lane can reach it.
+    // own stencil only beyond the cutoff, and with nb >= kSpan + 2 the range
+    // never holds a bin twice.  A row is skipped only if no lane can reach
+    // it.  The span is found with one ballot per offset (active lanes only).
     const int xo = lo[0] + 1;
     const int xf = __builtin_amdgcn_readfirstlane(xo);
     const int yf = __builtin_amdgcn_readfirstlane(lo[1]);
     const int zf = DIM == 3 ? __builtin_amdgcn_readfirstlane(lo[2]) : 0;
-    const bool xdown = __any(xo == xf - 1), xup = __any(xo == xf + 1);
-    const bool uniform = STENCIL == 3 && nb >= 4 && !(xdown && xup) &&
-                         __all(lo[1] == yf && (DIM == 2 || lo[2] == zf) && xo >= xf - 1 &&
-                               xo <= xf + 1);
+    int xmin = xf, xmax = xf;
+#pragma unroll
+    for (int o = 1; o < kSpan; ++o) {
+        if (__any(xo == xf - o)) xmin = xf - o;
+        if (__any(xo == xf + o)) xmax = xf + o;
+    }
+    const bool uniform = STENCIL == 3 && nb >= kSpan + 2 && xmax - xmin < kSpan &&
+                         __all(lo[1] == yf && (DIM == 2 || lo[2] == zf) && xo >= xmin &&
+                               xo <= xmax);
     if (uniform) {
         const int zlo = zf;
         const int zhi = DIM == 3 ? zlo + 2 : 0;
         const int ylo = yf;
-        const int xmin = xdown ? xf - 1 : xf, xmax = xup ? xf + 1 : xf;
         for (int oz = zlo; oz <= zhi; ++oz) {
             int qz = oz;
             float sz = 0.0f;
