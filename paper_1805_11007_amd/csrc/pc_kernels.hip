@@ -371,7 +371,10 @@ __device__ __forceinline__ void lds_insert(uint32_t *keys, unsigned long long *v
                                            unsigned long long *Supt) {
     uint32_t h = (key * 2654435761u) >> 20;  // 12 bits: kDepSlots = 4096
     for (int probe = 0; probe < 16; ++probe) {
-        const uint32_t old = atomicCAS(&keys[h], kEmpty, key);
+        // a plain read finds a node already in the table (the rule in dense
+        // regions); only a free slot takes the compare-and-swap
+        uint32_t old = __hip_atomic_load(&keys[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (old == kEmpty) old = atomicCAS(&keys[h], kEmpty, key);
         if (old == kEmpty || old == key) {
             if (a) atomicAdd(&vs[h], a);
             if (upt && b) atomicAdd(&vu[h], b);
