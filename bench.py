@@ -52,7 +52,7 @@ def update_traffic(workload: str):
     """Counter traffic of the update kernel, or None if the kernel sources
     changed since the counters were taken or the workload differs."""
     import hashlib
-    if workload != "cfg3_3d_periodic_1M_blobs":
+    if workload != "3d_periodic_1M_blobs":
         return None
     h = hashlib.sha256()
     csrc = Path(__file__).resolve().parent / "paper_1805_11007_amd" / "csrc"
@@ -133,7 +133,7 @@ def ensemble_leg(steps: int = 500, plain_steps: int = 50) -> dict:
     import workloads as W
     from paper_1805_11007_amd import ModelSpec, Sim
     from paper_1805_11007_amd.autotune import tune
-    w = W.config(4)
+    w = W.workload(W.ENSEMBLE_256)
     inp = W.make_inputs(w)
     x0, s0, c0 = (torch.from_numpy(inp[k]).cuda() for k in ("x0", "species0", "c0"))
     spec, rep = tune(ModelSpec.from_workload(w), x0, s0, c0)
@@ -180,7 +180,7 @@ def fig1_leg(hist_n: int = 52) -> dict:
     import workloads as W
     from paper_1805_11007_amd import ModelSpec, Sim
     from paper_1805_11007_amd.autotune import tune
-    w = W.config(6)
+    w = W.workload(W.FIG1_2000)
     inp = W.make_inputs(w)
     x0, s0, c0 = (torch.from_numpy(inp[k]).cuda() for k in ("x0", "species0", "c0"))
     spec, _ = tune(ModelSpec.from_workload(w), x0, s0, c0)
@@ -228,7 +228,7 @@ def reaction_overhead_leg(steps: int = 500) -> dict:
     import torch
     import workloads as W
     from paper_1805_11007_amd import ModelSpec, Sim
-    w = W.config(2)
+    w = W.workload(W.WALLS_100K)
     inp = W.make_inputs(w)
     x0, s0, c0 = (torch.from_numpy(inp[k]).cuda() for k in ("x0", "species0", "c0"))
     a, b = w.species
@@ -263,8 +263,8 @@ def kde_leg(steps: int = 100, sample_nodes: int = 4000) -> dict:
     import workloads as W
     from paper_1805_11007_amd import ModelSpec, Sim
     out = {}
-    for cfg in (2, 3):
-        w = W.config(cfg)
+    for wname in (W.WALLS_100K, W.BLOBS_1M):
+        w = W.workload(wname)
         inp = W.make_inputs(w)
         x0, s0, c0 = (torch.from_numpy(inp[k]).cuda() for k in ("x0", "species0", "c0"))
         r = {}
@@ -310,8 +310,8 @@ def variants_leg(steps: int = 100) -> dict:
     variants = {"harmonic": {}, "exponential": {"potential": 1, "pot_range": 3.0, "k": 1.0},
                 "tamed": {"tamed": True}, "hard_spheres": {"potential": 2}}
     out = {}
-    for cfg in (2, 3):
-        w = W.config(cfg)
+    for wname in (W.WALLS_100K, W.BLOBS_1M):
+        w = W.workload(wname)
         inp = W.make_inputs(w)
         x0, s0, c0 = (torch.from_numpy(inp[k]).cuda() for k in ("x0", "species0", "c0"))
         r = {}
@@ -340,12 +340,12 @@ def adjoint_leg(steps: int = 200, K: int = 20) -> dict:
     import workloads as W
     from paper_1805_11007_amd import ModelSpec, Sim
     from paper_1805_11007_amd.adjoint import density_loss_run
-    w = W.config5()
+    w = W.adjoint_2d()
     inp = W.make_inputs(w)
     x0, s0, c0 = (torch.from_numpy(inp[k]).cuda() for k in ("x0", "species0", "c0"))
     base = ModelSpec.from_workload(w)
     # target: a run at theta* = (1.5, 800, 0.8) with another noise key
-    tw = W.config5(chi=1.5, k=800, D=0.8, seed=2005)
+    tw = W.adjoint_2d(chi=1.5, k=800, D=0.8, seed=2005)
     tsim = Sim(ModelSpec.from_workload(tw), x0, s0, c0)
     tsim.step(steps)
     target = tsim.density_hist(64, 2.0)
@@ -385,7 +385,8 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--config", type=int, default=3)
+    ap.add_argument("--workload", default="3d_periodic_1M_blobs",
+                    help="workload name (the workloads module lists them)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the ensemble and forward+backward legs")
@@ -423,7 +424,7 @@ def main() -> int:
     import workloads as W
     from paper_1805_11007_amd import ModelSpec, Sim
 
-    w = W.config(args.config)
+    w = W.workload(args.workload)
     inp = W.make_inputs(w)
     spec = ModelSpec.from_workload(w, deterministic=args.deterministic,
                                    bin_size=args.bin_size, block=args.block)

@@ -52,11 +52,11 @@ def _check(name, grad, fun, theta, rel_tol=1e-3):
         assert abs(grad[j] - ref) <= max(rel_tol * abs(ref), unc, 1e-6 * scale)
 
 
-@pytest.mark.parametrize("cfg,n,g", [(5, 6000, 64), (5, 50_000, 256)])
-def test_density_loss_matches_oracle(cfg, n, g):
-    w = W.scaled(W.config(cfg), n_agents=n, grid_n=g)
+@pytest.mark.parametrize("n,g", [(6000, 64), (50_000, 256)])
+def test_density_loss_matches_oracle(n, g):
+    w = W.scaled(W.workload(W.ADJOINT_50K), n_agents=n, grid_n=g)
     inp = W.make_inputs(w)
-    tw = W.scaled(W.config5(chi=1.5, k=800, D=0.8, seed=2005), n_agents=n, grid_n=g)
+    tw = W.scaled(W.adjoint_2d(chi=1.5, k=800, D=0.8, seed=2005), n_agents=n, grid_n=g)
     target = oracle.target_hist(tw, W.make_inputs(tw), 5, 64, 2.0)
     sim = make_sim(w, inp)
     loss, dLdX = sim.density_loss(torch.from_numpy(target.astype(np.float32)), 64, 2.0)
@@ -117,17 +117,17 @@ def _theta_grad_gpu(w, inp, theta, target, n_steps, K, hist_n):
     return float(loss.detach()), th.grad.numpy()
 
 
-@pytest.mark.parametrize("cfg,n,g,steps,K,hist", [
-    (5, 4000, 64, 30, 10, 32),
-    (3, 3000, 16, 12, 5, 16),
+@pytest.mark.parametrize("name,n,g,steps,K,hist", [
+    (W.ADJOINT_50K, 4000, 64, 30, 10, 32),
+    (W.BLOBS_1M, 3000, 16, 12, 5, 16),
 ])
-def test_adjoint_vs_oracle_fd_small(cfg, n, g, steps, K, hist):
-    if cfg == 5:
-        w = W.scaled(W.config5(), n_agents=n, grid_n=g, steps=steps)
-        tw = W.scaled(W.config5(chi=1.5, k=800, D=0.8, seed=2005), n_agents=n, grid_n=g)
+def test_adjoint_vs_oracle_fd_small(name, n, g, steps, K, hist):
+    if name == W.ADJOINT_50K:
+        w = W.scaled(W.adjoint_2d(), n_agents=n, grid_n=g, steps=steps)
+        tw = W.scaled(W.adjoint_2d(chi=1.5, k=800, D=0.8, seed=2005), n_agents=n, grid_n=g)
         theta = np.array([1.0, 100.0, 1.0])
     else:
-        base3 = W.config(3)
+        base3 = W.workload(W.BLOBS_1M)
         w = W.scaled(base3, n_agents=n, grid_n=g, steps=steps, dt=1e-5, k=100.0)
         w = dataclasses.replace(w, species=(W.Species(0.04, 1.0, 1.0, 1.0, 0.0),))
         tw = oracle.workload_at(dataclasses.replace(w, instances=(W.Instance(n, 2005),)),
@@ -139,13 +139,13 @@ def test_adjoint_vs_oracle_fd_small(cfg, n, g, steps, K, hist):
     f = lambda th: oracle.loss_at(w, inp, th, target, steps, hist, 2.0)
     lo = f(theta)
     assert abs(loss - lo) <= 1e-4 * lo
-    _check(f"cfg{cfg}", grad, f, theta)
+    _check(name, grad, f, theta)
 
 
 def test_adjoint_vs_oracle_fd_walls_linear_functional():
     """Reflecting walls: L = sum_i w_i . X_T,i for fixed weights."""
     n, steps, K = 5000, 16, 8
-    w = W.scaled(W.config(2), n_agents=n, grid_n=65, steps=steps, dt=2e-5, k=100.0)
+    w = W.scaled(W.workload(W.WALLS_100K), n_agents=n, grid_n=65, steps=steps, dt=2e-5, k=100.0)
     w = dataclasses.replace(w, species=(W.Species(0.01, 1.0, 0.0, 1.0, 0.0),
                                         W.Species(0.015, 1.0, 2.0, 0.0, 1.0)))
     inp = W.make_inputs(w)
@@ -179,7 +179,7 @@ def test_adjoint_vs_oracle_fd_walls_linear_functional():
 
 
 @pytest.mark.parametrize("steps,K,tol", [(10, 5, 1e-3), (20, 10, 3e-3)])
-def test_adjoint_vs_oracle_fd_full_size_config5(steps, K, tol):
+def test_adjoint_vs_oracle_fd_full_size_2d_50k(steps, K, tol):
     """The full differentiation workload (50k agents, 256^2 grid, three PDE
     substeps, 64^2 histogram, 2-bin smoothing) over short horizons, where
     the FP64 loss is smooth enough for a converged finite-difference
@@ -187,37 +187,37 @@ def test_adjoint_vs_oracle_fd_full_size_config5(steps, K, tol):
     state's rounding, amplified by near-coincident pairs (area fraction
     3.9), already moves the gradient by ~2e-3, so that horizon is checked at
     3e-3."""
-    w = W.scaled(W.config5(), steps=steps)
+    w = W.scaled(W.adjoint_2d(), steps=steps)
     inp = W.make_inputs(w)
-    tw = W.config5(chi=1.5, k=800, D=0.8, seed=2005)
+    tw = W.adjoint_2d(chi=1.5, k=800, D=0.8, seed=2005)
     target = oracle.target_hist(tw, W.make_inputs(tw), steps, 64, 2.0)
     theta = np.array([1.0, 100.0, 1.0])
     loss, grad = _theta_grad_gpu(w, inp, theta, target, steps, K, 64)
     f = lambda th: oracle.loss_at(w, inp, th, target, steps, 64, 2.0)
-    _check(f"cfg5-full-{steps}", grad, f, theta, rel_tol=tol)
+    _check(f"2d-50k-full-{steps}", grad, f, theta, rel_tol=tol)
 
 
-def test_adjoint_full_config5_200_steps_reported():
+def test_adjoint_full_2d_50k_200_steps_reported():
     """The whole 200-step run.  Its dynamics amplify rounding about a
     thousandfold (FP32 and FP64 positions differ by ~1e-4 at the end), so
     the loss is rough and finite differences have no plateau; the
     comparison is printed and only checked for sign and magnitude."""
-    w = W.config5()
+    w = W.adjoint_2d()
     inp = W.make_inputs(w)
-    tw = W.config5(chi=1.5, k=800, D=0.8, seed=2005)
+    tw = W.adjoint_2d(chi=1.5, k=800, D=0.8, seed=2005)
     target = oracle.target_hist(tw, W.make_inputs(tw), 200, 64, 2.0)
     theta = np.array([1.0, 100.0, 1.0])
     loss, grad = _theta_grad_gpu(w, inp, theta, target, 200, 20, 64)
     f = lambda th: oracle.loss_at(w, inp, th, target, 200, 64, 2.0)
     for j in range(3):
         fds = [_fd(f, theta, j, r) for r in (1e-3, 1e-4, 1e-5)]
-        print(f"cfg5-200 theta[{j}] adjoint {grad[j]:.6e} fd {['%.5e' % v for v in fds]}")
+        print(f"2d-50k-200 theta[{j}] adjoint {grad[j]:.6e} fd {['%.5e' % v for v in fds]}")
         ref = float(np.median(fds))
         assert np.sign(grad[j]) == np.sign(ref) and 0.5 < grad[j] / ref < 2.0
 
 
 def test_density_hist_matches_oracle():
-    w = W.scaled(W.config5(), n_agents=7000, grid_n=64)
+    w = W.scaled(W.adjoint_2d(), n_agents=7000, grid_n=64)
     inp = W.make_inputs(w)
     sim = make_sim(w, inp)
     rho = sim.density_hist(48, 1.5).cpu().numpy()

@@ -14,7 +14,7 @@ def test_autotune_picks_a_valid_configuration(tmp_path, monkeypatch):
     from paper_1805_11007_amd import ModelSpec, Sim
     from paper_1805_11007_amd import autotune as AT
     monkeypatch.setenv("PC_AUTOTUNE_CACHE", str(tmp_path / "tune.json"))
-    w = W.scaled(W.config(4), n_agents=[900, 40, 3000, 1, 250], grid_n=48)
+    w = W.scaled(W.workload(W.ENSEMBLE_256), n_agents=[900, 40, 3000, 1, 250], grid_n=48)
     inp = W.make_inputs(w)
     x0, s0, c0 = (torch.from_numpy(inp[k]) for k in ("x0", "species0", "c0"))
     spec, rep = AT.tune(ModelSpec.from_workload(w), x0, s0, c0, steps=4)
@@ -32,7 +32,7 @@ def test_autotune_picks_a_valid_configuration(tmp_path, monkeypatch):
 @pytest.mark.parametrize("bin_mult,block", [(1.0, 64), (1.25, 512), (2.0, 128), (3.0, 1024)])
 def test_every_candidate_is_parity_green(bin_mult, block):
     from paper_1805_11007_amd import ModelSpec, Sim
-    w = W.scaled(W.config(3), n_agents=30000, grid_n=32)
+    w = W.scaled(W.workload(W.BLOBS_1M), n_agents=30000, grid_n=32)
     inp = W.make_inputs(w)
     spec = ModelSpec.from_workload(w, bin_size=bin_mult * 0.004 * (1 + 2e-4), block=block)
     sim = Sim(spec, torch.from_numpy(inp["x0"]), torch.from_numpy(inp["species0"]),

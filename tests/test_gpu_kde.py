@@ -23,12 +23,12 @@ def _kde(w, kappa=3.0):
     return dataclasses.replace(w, deposit_kernel=1, kde_radius=kappa)
 
 
-def _case(cfg, n, g, kappa=3.0):
-    if cfg == 4:
-        w = W.scaled(W.config(4), n_agents=list(np.random.default_rng(9).integers(1, 900, 6)),
-                     grid_n=g)
+def _case(name, n, g, kappa=3.0):
+    if name == W.ENSEMBLE_256:
+        w = W.scaled(W.workload(W.ENSEMBLE_256),
+                     n_agents=list(np.random.default_rng(9).integers(1, 900, 6)), grid_n=g)
     else:
-        w = W.scaled(W.config(cfg), n_agents=n, grid_n=g)
+        w = W.scaled(W.workload(name), n_agents=n, grid_n=g)
     return _kde(w, kappa)
 
 
@@ -45,13 +45,15 @@ def _within(c, lo, hi, tol):
     return np.all(c >= a - tol) and np.all(c <= b + tol)
 
 
-CASES = [(1, 3001, 37, 3.0), (2, 20011, 129, 3.0), (3, 8000, 32, 3.0), (5, 6000, 48, 3.0),
-         (4, None, 24, 3.0), (1, 3001, 37, 1.5), (2, 5000, 65, 6.0)]
+CASES = [(W.PERIODIC_1K, 3001, 37, 3.0), (W.WALLS_100K, 20011, 129, 3.0),
+         (W.BLOBS_1M, 8000, 32, 3.0), (W.ADJOINT_50K, 6000, 48, 3.0),
+         (W.ENSEMBLE_256, None, 24, 3.0), (W.PERIODIC_1K, 3001, 37, 1.5),
+         (W.WALLS_100K, 5000, 65, 6.0)]
 
 
-@pytest.mark.parametrize("cfg,n,g,kappa", CASES)
-def test_one_step_matches_oracle(cfg, n, g, kappa):
-    w = _case(cfg, n, g, kappa)
+@pytest.mark.parametrize("name,n,g,kappa", CASES)
+def test_one_step_matches_oracle(name, n, g, kappa):
+    w = _case(name, n, g, kappa)
     inp = W.make_inputs(w)
     sim = make_sim(w, inp)
     assert sim.info["deposit_path"] == 4
@@ -63,9 +65,10 @@ def test_one_step_matches_oracle(cfg, n, g, kappa):
     assert _within(c.cpu().numpy().astype(np.float64), clo, chi_, 1e-5 * scale)
 
 
-@pytest.mark.parametrize("cfg,n,g,steps", [(1, 2000, 37, 10), (2, 8000, 65, 6)])
-def test_trajectory_matches_oracle(cfg, n, g, steps):
-    w = _case(cfg, n, g)
+@pytest.mark.parametrize("name,n,g,steps", [(W.PERIODIC_1K, 2000, 37, 10),
+                                            (W.WALLS_100K, 8000, 65, 6)])
+def test_trajectory_matches_oracle(name, n, g, steps):
+    w = _case(name, n, g)
     inp = W.make_inputs(w)
     sim = make_sim(w, inp)
     sim.use_graph(True)
@@ -78,7 +81,7 @@ def test_trajectory_matches_oracle(cfg, n, g, steps):
 
 
 def test_graph_equals_eager_and_deterministic_repeats():
-    w = _case(2, 6000, 65)
+    w = _case(W.WALLS_100K, 6000, 65)
     inp = W.make_inputs(w)
     runs = []
     for graph in (False, True, True):
@@ -96,7 +99,7 @@ def test_graph_equals_eager_and_deterministic_repeats():
 
 def test_profile_and_set_state_round_trip():
     import torch
-    w = _case(1, 3000, 37)
+    w = _case(W.PERIODIC_1K, 3000, 37)
     inp = W.make_inputs(w)
     sim = make_sim(w, inp)
     prof = sim.profile_steps(3)
@@ -112,7 +115,7 @@ def test_profile_and_set_state_round_trip():
 def test_rejections():
     import torch
     from paper_1805_11007_amd import PcError
-    w = _case(5, 2000, 32)
+    w = _case(W.ADJOINT_50K, 2000, 32)
     inp = W.make_inputs(w)
     with pytest.raises(PcError):
         make_sim(w, inp, deposit_mode=3)

@@ -15,24 +15,24 @@ from gpu_helpers import (field_err, make_sim, oracle_forces, oracle_neighbours, 
 
 pytestmark = pytest.mark.gpu
 
-# (config, agents, grid) cases: several bins / tiles with ragged tails
-SMALL = [(1, 1000, None), (1, 3001, 37), (2, 20011, 129), (3, 40000, 48), (4, None, 32),
-         (5, 9000, 64)]
-FULL = [1, 2, 3, 5]
+# (workload, agents, grid) cases: several bins / tiles with ragged tails
+SMALL = [(W.PERIODIC_1K, 1000, None), (W.PERIODIC_1K, 3001, 37), (W.WALLS_100K, 20011, 129),
+         (W.BLOBS_1M, 40000, 48), (W.ENSEMBLE_256, None, 32), (W.ADJOINT_50K, 9000, 64)]
+FULL = [W.PERIODIC_1K, W.WALLS_100K, W.BLOBS_1M, W.ADJOINT_50K]
 
 
-def _w(cfg, n, g):
-    w = W.config(cfg)
-    if cfg == 4:
+def _w(name, n, g):
+    w = W.workload(name)
+    if name == W.ENSEMBLE_256:
         rng = np.random.default_rng(4)
         sizes = list(rng.integers(1, 900, 12)) + [1, 2]
         return W.scaled(w, n_agents=sizes, grid_n=g)
     return W.scaled(w, n_agents=n, grid_n=g)
 
 
-@pytest.mark.parametrize("cfg,n,g", SMALL)
-def test_neighbour_sets_bit_exact(cfg, n, g):
-    w = _w(cfg, n, g)
+@pytest.mark.parametrize("name,n,g", SMALL)
+def test_neighbour_sets_bit_exact(name, n, g):
+    w = _w(name, n, g)
     inp = W.make_inputs(w)
     sim = make_sim(w, inp)
     cnt, hsh = sim.debug_neighbours()
@@ -41,9 +41,9 @@ def test_neighbour_sets_bit_exact(cfg, n, g):
     assert np.array_equal(hsh.cpu().numpy().view(np.uint64), ohsh)
 
 
-@pytest.mark.parametrize("cfg", FULL)
-def test_neighbour_sets_bit_exact_full_size(cfg):
-    w = W.config(cfg)
+@pytest.mark.parametrize("name", FULL)
+def test_neighbour_sets_bit_exact_full_size(name):
+    w = W.workload(name)
     inp = W.make_inputs(w)
     sim = make_sim(w, inp)
     cnt, hsh = sim.debug_neighbours()
@@ -52,9 +52,9 @@ def test_neighbour_sets_bit_exact_full_size(cfg):
     assert np.array_equal(hsh.cpu().numpy().view(np.uint64), ohsh)
 
 
-@pytest.mark.parametrize("cfg,n,g", SMALL)
-def test_forces(cfg, n, g):
-    w = _w(cfg, n, g)
+@pytest.mark.parametrize("name,n,g", SMALL)
+def test_forces(name, n, g):
+    w = _w(name, n, g)
     inp = W.make_inputs(w)
     sim = make_sim(w, inp)
     F = sim.debug_forces().cpu().numpy().astype(np.float64)
@@ -64,10 +64,10 @@ def test_forces(cfg, n, g):
     assert np.abs(F.sum(0)).max() <= 1e-5 * scale * max(1.0, np.sqrt(len(F)))
 
 
-@pytest.mark.parametrize("cfg,n,g", SMALL)
+@pytest.mark.parametrize("name,n,g", SMALL)
 @pytest.mark.parametrize("det", [False, True])
-def test_one_step(cfg, n, g, det):
-    w = _w(cfg, n, g)
+def test_one_step(name, n, g, det):
+    w = _w(name, n, g)
     inp = W.make_inputs(w)
     sim = make_sim(w, inp, deterministic=det)
     sim.step(1)
@@ -79,9 +79,9 @@ def test_one_step(cfg, n, g, det):
     assert field_err(c, c1) <= 1e-5
 
 
-@pytest.mark.parametrize("cfg", FULL)
-def test_one_step_full_size(cfg):
-    w = W.config(cfg)
+@pytest.mark.parametrize("name", FULL)
+def test_one_step_full_size(name):
+    w = W.workload(name)
     inp = W.make_inputs(w)
     sim = make_sim(w, inp)
     sim.step(1)
@@ -93,11 +93,11 @@ def test_one_step_full_size(cfg):
     assert field_err(c, c1) <= 1e-5
 
 
-def test_one_step_later_counter_config3():
+def test_one_step_later_counter_3d_blobs():
     """Per-step parity at a later step counter and evolved state: the oracle
     evolves the state for 5 steps, both sides take step 5 -> 6 from it."""
     import torch
-    w = W.config(3)
+    w = W.workload(W.BLOBS_1M)
     inp = W.make_inputs(w)
     X5, c5 = oracle_steps(w, inp, 5)
     sim = make_sim(w, inp)
@@ -112,10 +112,11 @@ def test_one_step_later_counter_config3():
     assert field_err(sim.field().cpu().numpy(), c6) <= 1e-5
 
 
-@pytest.mark.parametrize("cfg,steps", [(1, 100), (2, 20), (5, 20)])
-def test_trajectory(cfg, steps):
-    w = W.config(cfg)
-    if cfg != 1:
+@pytest.mark.parametrize("name,steps", [(W.PERIODIC_1K, 100), (W.WALLS_100K, 20),
+                                        (W.ADJOINT_50K, 20)])
+def test_trajectory(name, steps):
+    w = W.workload(name)
+    if name != W.PERIODIC_1K:
         w = W.scaled(w, n_agents=20000)
     inp = W.make_inputs(w)
     sim = make_sim(w, inp)
@@ -124,5 +125,5 @@ def test_trajectory(cfg, steps):
     Xn, cn = oracle_steps(w, inp, steps)
     ex = pos_err(sim.positions().cpu().numpy(), Xn, w.L, w.periodic)
     ec = field_err(sim.field().cpu().numpy(), cn)
-    print(f"cfg{cfg} {steps} steps: position err {ex:.3e} field err {ec:.3e}")
+    print(f"{name} {steps} steps: position err {ex:.3e} field err {ec:.3e}")
     assert ex <= 1e-5 * steps and ec <= 1e-5 * steps

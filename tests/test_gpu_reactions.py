@@ -28,7 +28,7 @@ def _reacting(w, r01=0.0, r01c=0.0, r10=0.0, r10c=0.0):
 
 
 def _w_walls(n=20011, g=129, **rates):
-    return _reacting(W.scaled(W.config(2), n_agents=n, grid_n=g), **rates)
+    return _reacting(W.scaled(W.workload(W.WALLS_100K), n_agents=n, grid_n=g), **rates)
 
 
 def _uniforms(seed, stream, step, n):
@@ -93,7 +93,7 @@ def test_constant_rates_species_bit_exact_over_steps(graph):
 
 def test_batched_reactions_equal_instances_run_alone():
     rng = np.random.default_rng(12)
-    w = W.scaled(W.config(4), n_agents=list(rng.integers(1, 700, 7)), grid_n=24)
+    w = W.scaled(W.workload(W.ENSEMBLE_256), n_agents=list(rng.integers(1, 700, 7)), grid_n=24)
     s = w.species[0]
     sp = (dataclasses.replace(s, react_to=1, react_rate=3e3),
           dataclasses.replace(s, chi=0.0, source=0.0, uptake=0.5, react_to=0, react_rate_c=4e3))
@@ -168,7 +168,7 @@ def test_certain_switch_sets_warning():
 def test_reverse_mode_rejects_switching():
     import torch
     from paper_1805_11007_amd import PcError
-    w = _reacting(W.scaled(W.config(5), n_agents=2000, grid_n=32), r01=10.0)
+    w = _reacting(W.scaled(W.workload(W.ADJOINT_50K), n_agents=2000, grid_n=32), r01=10.0)
     inp = W.make_inputs(w)
     sim = make_sim(w, inp, adjoint_steps=2)
     lx = torch.zeros(w.n_total, 2)

@@ -17,7 +17,7 @@ def _state(sim):
 
 
 def test_deterministic_mode_bitwise_repeatable():
-    w = W.scaled(W.config(3), n_agents=60000, grid_n=40)
+    w = W.scaled(W.workload(W.BLOBS_1M), n_agents=60000, grid_n=40)
     inp = W.make_inputs(w)
     a = make_sim(w, inp, deterministic=True)
     b = make_sim(w, inp, deterministic=True)
@@ -33,7 +33,7 @@ def test_batch_equals_instances_run_alone():
     and noise stream), bit for bit in deterministic mode; the batch also
     matches the oracle."""
     rng = np.random.default_rng(11)
-    w = W.scaled(W.config(4), n_agents=list(rng.integers(1, 700, 9)), grid_n=24)
+    w = W.scaled(W.workload(W.ENSEMBLE_256), n_agents=list(rng.integers(1, 700, 9)), grid_n=24)
     inp = W.make_inputs(w)
     sim = make_sim(w, inp, deterministic=True)
     sim.step(5)
@@ -57,7 +57,7 @@ def test_batch_equals_instances_run_alone():
 
 
 def test_graph_replay_equals_eager():
-    w = W.scaled(W.config(1), n_agents=2000)
+    w = W.scaled(W.workload(W.PERIODIC_1K), n_agents=2000)
     inp = W.make_inputs(w)
     a = make_sim(w, inp, deterministic=True)
     b = make_sim(w, inp, deterministic=True)
@@ -79,7 +79,7 @@ def test_graph_replay_equals_eager():
 
 
 def test_checkpoint_resume_bitwise():
-    w = W.scaled(W.config(5), n_agents=5000, grid_n=64)
+    w = W.scaled(W.workload(W.ADJOINT_50K), n_agents=5000, grid_n=64)
     inp = W.make_inputs(w)
     sim = make_sim(w, inp, deterministic=True)
     sim.step(3)
@@ -94,7 +94,7 @@ def test_checkpoint_resume_bitwise():
 
 
 def test_species_and_warnings():
-    w = W.scaled(W.config(2), n_agents=5000, grid_n=65)
+    w = W.scaled(W.workload(W.WALLS_100K), n_agents=5000, grid_n=65)
     inp = W.make_inputs(w)
     sim = make_sim(w, inp)
     assert np.array_equal(sim.species().cpu().numpy(), inp["species0"])
@@ -103,7 +103,7 @@ def test_species_and_warnings():
 
 
 def test_walls_keep_agents_in_box_and_nonfinite_flag():
-    w = W.scaled(W.config(2), n_agents=20000, grid_n=65)
+    w = W.scaled(W.workload(W.WALLS_100K), n_agents=20000, grid_n=65)
     inp = W.make_inputs(w)
     x0 = inp["x0"].copy()
     x0[:500] = 0.0
@@ -119,14 +119,14 @@ def test_walls_keep_agents_in_box_and_nonfinite_flag():
 
 def test_edge_cases_single_agent_and_one_bin_pileup():
     # one agent
-    w = W.scaled(W.config(1), n_agents=1)
+    w = W.scaled(W.workload(W.PERIODIC_1K), n_agents=1)
     inp = W.make_inputs(w)
     sim = make_sim(w, inp)
     sim.step(3)
     X, c = oracle_steps(w, inp, 3)
     assert pos_err(sim.positions().cpu().numpy(), X, 1.0, True) <= 3e-5
     # 300 agents piled up inside one bin, plus agents on bin faces and at 0 / L^-
-    w = W.scaled(W.config(1), n_agents=400)
+    w = W.scaled(W.workload(W.PERIODIC_1K), n_agents=400)
     inp = W.make_inputs(w)
     x0 = inp["x0"].copy()
     x0[:300] = np.float32(0.5) + np.random.default_rng(1).uniform(0, 0.004, (300, 2)).astype(np.float32)
@@ -150,7 +150,7 @@ def test_cell_list_with_more_than_8192_scan_tiles():
     in two passes of 8192 with a ragged tail.  Neighbour sets stay bit-exact
     against the float32 brute force, at creation and after the cell list has
     been rebuilt by the steps (checked on the GPU's own positions)."""
-    w = W.scaled(W.config(3), n_agents=150000, grid_n=32)
+    w = W.scaled(W.workload(W.BLOBS_1M), n_agents=150000, grid_n=32)
     w = dataclasses.replace(w, species=(dataclasses.replace(w.species[0], diameter=0.0037),))
     inp = W.make_inputs(w)
     sim = make_sim(w, inp, bin_size=1.0 / 265.5)
@@ -174,7 +174,7 @@ def test_wave_across_bin_rows_with_more_than_1024_bins_per_side():
     form one wave in cell order.  A bin id packed as x + 1024 y is the same
     for both bins, so a wave-uniform test built on it would give the second
     half the first half's stencil and lose its neighbours."""
-    w = W.scaled(W.config(1), n_agents=64)
+    w = W.scaled(W.workload(W.PERIODIC_1K), n_agents=64)
     w = dataclasses.replace(w, species=(dataclasses.replace(w.species[0], diameter=0.0009),))
     inp = W.make_inputs(w)
     rng = np.random.default_rng(7)
@@ -198,7 +198,7 @@ def test_wave_across_bin_rows_with_more_than_1024_bins_per_side():
 def test_error_paths():
     import torch
     from paper_1805_11007_amd import ModelSpec, PcError, Sim
-    w = W.scaled(W.config(1), n_agents=100)
+    w = W.scaled(W.workload(W.PERIODIC_1K), n_agents=100)
     inp = W.make_inputs(w)
     bad = inp["species0"].copy()
     bad[5] = 3
@@ -210,23 +210,24 @@ def test_error_paths():
             torch.from_numpy(inp["species0"]), torch.from_numpy(inp["c0"]))
 
 
-def _dep_case(cfg, n, g):
-    if cfg == 4:
-        return W.scaled(W.config(4), n_agents=list(np.random.default_rng(7).integers(1, 600, 70)),
-                        grid_n=g)
-    if cfg == 6:
-        return W.config6(n_real=n)
-    return W.scaled(W.config(cfg), n_agents=n, grid_n=g)
+def _dep_case(name, n, g):
+    if name == W.ENSEMBLE_256:
+        return W.scaled(W.workload(W.ENSEMBLE_256),
+                        n_agents=list(np.random.default_rng(7).integers(1, 600, 70)), grid_n=g)
+    if name == W.FIG1_2000:
+        return W.fig1_walls_2d(n_real=n)
+    return W.scaled(W.workload(name), n_agents=n, grid_n=g)
 
 
-@pytest.mark.parametrize("cfg,n,g,modes", [(3, 40000, 32, (2,)), (2, 20011, 129, (2,)),
-                                           (1, 3001, 37, (2, 3)), (4, None, 24, (2, 3)),
-                                           (5, 3000, 32, (2, 3)), (6, 70, None, (2, 3))])
-def test_deposit_modes_bitwise_equal(cfg, n, g, modes):
+@pytest.mark.parametrize("name,n,g,modes", [
+    (W.BLOBS_1M, 40000, 32, (2,)), (W.WALLS_100K, 20011, 129, (2,)),
+    (W.PERIODIC_1K, 3001, 37, (2, 3)), (W.ENSEMBLE_256, None, 24, (2, 3)),
+    (W.ADJOINT_50K, 3000, 32, (2, 3)), (W.FIG1_2000, 70, None, (2, 3))])
+def test_deposit_modes_bitwise_equal(name, n, g, modes):
     """The deposit is an integer sum: LDS-aggregated, direct-atomic and
     per-instance fused (deposit + PDE substeps in one work-group) paths give
     the same bits, step after step."""
-    w = _dep_case(cfg, n, g)
+    w = _dep_case(name, n, g)
     inp = W.make_inputs(w)
     a = make_sim(w, inp, deterministic=True, deposit_mode=1)
     assert a.info["deposit_path"] == 1
@@ -243,8 +244,8 @@ def test_deposit_modes_bitwise_equal(cfg, n, g, modes):
 
 def test_fused_path_chosen_for_many_small_instances_and_rejected_when_too_big():
     from paper_1805_11007_amd import PcError
-    w = W.config6(n_real=64)
+    w = W.fig1_walls_2d(n_real=64)
     assert make_sim(w, W.make_inputs(w)).info["deposit_path"] == 3
-    w = W.scaled(W.config(3), n_agents=1000, grid_n=64)  # 64^3 sums do not fit in LDS
+    w = W.scaled(W.workload(W.BLOBS_1M), n_agents=1000, grid_n=64)  # 64^3 sums do not fit in LDS
     with pytest.raises(PcError):
         make_sim(w, W.make_inputs(w), deposit_mode=3)

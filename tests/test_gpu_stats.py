@@ -33,7 +33,7 @@ def _check_stats(sim, w, hist_n):
 
 @pytest.mark.parametrize("n_real,hist_n", [(37, 52), (5, 1), (13, 7)])
 def test_stats_small_ensembles(n_real, hist_n):
-    w = W.config6(n_real=n_real)
+    w = W.fig1_walls_2d(n_real=n_real)
     inp = W.make_inputs(w)
     sim = make_sim(w, inp)
     _check_stats(sim, w, hist_n)
@@ -42,7 +42,7 @@ def test_stats_small_ensembles(n_real, hist_n):
 
 
 def test_stats_full_fig1_ensemble_conserves_agents():
-    w = W.config(6)
+    w = W.workload(W.FIG1_2000)
     inp = W.make_inputs(w)
     sim = make_sim(w, inp)
     sim.use_graph(True)
@@ -56,7 +56,7 @@ def test_stats_full_fig1_ensemble_conserves_agents():
 
 
 def test_stats_global_atomic_path_3d():
-    w = W.scaled(W.config(3), n_agents=50000, grid_n=32)
+    w = W.scaled(W.workload(W.BLOBS_1M), n_agents=50000, grid_n=32)
     inp = W.make_inputs(w)
     sim = make_sim(w, inp)
     sim.step(3)
@@ -66,7 +66,7 @@ def test_stats_global_atomic_path_3d():
 @pytest.mark.parametrize("n_real", [24, 80])
 def test_stats_along_a_trajectory_match_oracle_run(n_real):
     """80 realisations take the per-instance fused deposit + PDE path."""
-    w = W.config6(n_real=n_real)
+    w = W.fig1_walls_2d(n_real=n_real)
     inp = W.make_inputs(w)
     sim = make_sim(w, inp)
     assert sim.info["deposit_path"] == (3 if n_real >= 64 else 2)
@@ -90,7 +90,7 @@ def test_fig1_full_size_sampled_realisations_match_oracle():
     replay) against the oracle run of three realisations on their own:
     species bit-exact (constant switching rate), positions within 1e-5 L per
     step, field within 1e-5 max|c| per step."""
-    w = W.config(6)
+    w = W.workload(W.FIG1_2000)
     inp = W.make_inputs(w)
     sim = make_sim(w, inp)
     assert sim.info["deposit_path"] == 3

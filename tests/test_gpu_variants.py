@@ -21,8 +21,8 @@ from gpu_helpers import field_err, make_sim, oracle_forces, pos_err
 pytestmark = pytest.mark.gpu
 
 
-def _v(cfg, n, g, **kw):
-    return dataclasses.replace(W.scaled(W.config(cfg), n_agents=n, grid_n=g), **kw)
+def _v(name, n, g, **kw):
+    return dataclasses.replace(W.scaled(W.workload(name), n_agents=n, grid_n=g), **kw)
 
 
 def _oracle_nbrs_scaled(w, inp, scale):
@@ -32,9 +32,9 @@ def _oracle_nbrs_scaled(w, inp, scale):
     return cnt, hs
 
 
-@pytest.mark.parametrize("cfg,n,g", [(1, 3001, 37), (2, 20011, 129), (3, 20000, 32)])
-def test_exponential_neighbours_and_forces(cfg, n, g):
-    w = _v(cfg, n, g, potential=1, pot_range=2.5, k=5.0)
+@pytest.mark.parametrize("name,n,g", [(W.PERIODIC_1K, 3001, 37), (W.WALLS_100K, 20011, 129), (W.BLOBS_1M, 20000, 32)])
+def test_exponential_neighbours_and_forces(name, n, g):
+    w = _v(name, n, g, potential=1, pot_range=2.5, k=5.0)
     inp = W.make_inputs(w)
     sim = make_sim(w, inp)
     cnt, hsh = sim.debug_neighbours()
@@ -48,20 +48,20 @@ def test_exponential_neighbours_and_forces(cfg, n, g):
 
 
 CASES = [
-    (1, 3001, 37, dict(potential=1, pot_range=3.0, k=2.0)),
-    (2, 20011, 129, dict(potential=1, pot_range=2.0, k=0.5)),
-    (1, 3001, 37, dict(potential=0, tamed=True, k=1e5)),
-    (3, 20000, 32, dict(potential=0, tamed=True, k=1e6)),
-    (1, 3001, 37, dict(potential=2)),
-    (2, 20011, 129, dict(potential=2)),
-    (3, 20000, 32, dict(potential=2)),
-    (5, 6000, 48, dict(potential=2)),
+    (W.PERIODIC_1K, 3001, 37, dict(potential=1, pot_range=3.0, k=2.0)),
+    (W.WALLS_100K, 20011, 129, dict(potential=1, pot_range=2.0, k=0.5)),
+    (W.PERIODIC_1K, 3001, 37, dict(potential=0, tamed=True, k=1e5)),
+    (W.BLOBS_1M, 20000, 32, dict(potential=0, tamed=True, k=1e6)),
+    (W.PERIODIC_1K, 3001, 37, dict(potential=2)),
+    (W.WALLS_100K, 20011, 129, dict(potential=2)),
+    (W.BLOBS_1M, 20000, 32, dict(potential=2)),
+    (W.ADJOINT_50K, 6000, 48, dict(potential=2)),
 ]
 
 
-@pytest.mark.parametrize("cfg,n,g,kw", CASES)
-def test_one_step(cfg, n, g, kw):
-    w = _v(cfg, n, g, **kw)
+@pytest.mark.parametrize("name,n,g,kw", CASES)
+def test_one_step(name, n, g, kw):
+    w = _v(name, n, g, **kw)
     inp = W.make_inputs(w)
     sim = make_sim(w, inp)
     sim.step(1)
@@ -71,20 +71,20 @@ def test_one_step(cfg, n, g, kw):
     assert field_err(c.cpu().numpy(), co) <= 1e-5
 
 
-@pytest.mark.parametrize("cfg,n,g,kw,steps", [
-    (1, 2000, 37, dict(potential=2), 10),
-    (2, 8000, 65, dict(potential=2), 8),
-    (1, 2000, 37, dict(potential=1, pot_range=3.0, k=2.0), 10),
-    (1, 2000, 37, dict(potential=0, tamed=True, k=1e5), 10),
+@pytest.mark.parametrize("name,n,g,kw,steps", [
+    (W.PERIODIC_1K, 2000, 37, dict(potential=2), 10),
+    (W.WALLS_100K, 8000, 65, dict(potential=2), 8),
+    (W.PERIODIC_1K, 2000, 37, dict(potential=1, pot_range=3.0, k=2.0), 10),
+    (W.PERIODIC_1K, 2000, 37, dict(potential=0, tamed=True, k=1e5), 10),
 ])
-def test_trajectory(cfg, n, g, kw, steps):
+def test_trajectory(name, n, g, kw, steps):
     """Soft potentials: the whole trajectory within 1e-5 per step.  Hard
     spheres: the overlap correction maps a pair's distance r to 2d - r, and
     clusters of overlaps pass a rounding difference on to every member, so
     trajectories of the two precisions separate faster than linearly; every
     step is checked from the GPU's own state instead (1e-5), and the whole
     trajectory within 1e-3."""
-    w = _v(cfg, n, g, **kw)
+    w = _v(name, n, g, **kw)
     inp = W.make_inputs(w)
     sim = make_sim(w, inp)
     if kw.get("potential") == 2:
@@ -109,7 +109,7 @@ def test_trajectory(cfg, n, g, kw, steps):
 
 
 def test_hard_spheres_reduce_overlap_and_repeat_bitwise():
-    w = _v(1, 4000, 37, potential=2)
+    w = _v(W.PERIODIC_1K, 4000, 37, potential=2)
     inp = W.make_inputs(w)
     runs = []
     for graph in (False, True):
@@ -137,13 +137,13 @@ def test_hard_spheres_reduce_overlap_and_repeat_bitwise():
 def test_rejections():
     import torch
     from paper_1805_11007_amd import PcError
-    w = _v(5, 2000, 32, potential=2, deposit_kernel=1)
+    w = _v(W.ADJOINT_50K, 2000, 32, potential=2, deposit_kernel=1)
     with pytest.raises(PcError):
         make_sim(w, W.make_inputs(w))
-    w = _v(5, 2000, 32, potential=1, pot_range=0.5)
+    w = _v(W.ADJOINT_50K, 2000, 32, potential=1, pot_range=0.5)
     with pytest.raises(PcError):
         make_sim(w, W.make_inputs(w))
-    w = _v(5, 2000, 32, potential=1)
+    w = _v(W.ADJOINT_50K, 2000, 32, potential=1)
     sim = make_sim(w, W.make_inputs(w), adjoint_steps=2)
     with pytest.raises(PcError):
         sim.adjoint_segment(torch.zeros(w.n_total, 2), torch.zeros(w.n_nodes), 1)

@@ -75,9 +75,9 @@ def test_hist_matches_loss_definition(oracle_lib):
 def test_theta_finite_differences_have_a_plateau(oracle_lib):
     """Central differences of loss(theta) agree across step sizes, so the FD
     reference of the reverse-mode tests is well defined."""
-    w = W.scaled(W.config5(), n_agents=1500, grid_n=32, steps=10)
+    w = W.scaled(W.adjoint_2d(), n_agents=1500, grid_n=32, steps=10)
     inp = W.make_inputs(w)
-    tw = W.scaled(W.config5(chi=1.5, k=800, D=0.8, seed=2005), n_agents=1500, grid_n=32)
+    tw = W.scaled(W.adjoint_2d(chi=1.5, k=800, D=0.8, seed=2005), n_agents=1500, grid_n=32)
     m = 16
     target = oracle.target_hist(tw, W.make_inputs(tw), 10, m, 2.0)
     theta = np.array([1.0, 100.0, 1.0])

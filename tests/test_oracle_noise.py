@@ -56,7 +56,7 @@ def test_uniform_mapping_range_and_lattice(oracle_lib):
     # The normals of id i at step s come from one Philox block; their uniforms
     # are odd multiples of 2^-24 in (0, 1): check via the inverse Box-Muller
     # radius of the first pair, which must be one of those lattice values.
-    w = W.config(1)
+    w = W.workload(W.PERIODIC_1K)
     p = oracle.params(w)
     ids = np.arange(20000, dtype=np.uint32)
     xi = oracle.normals(p, 3, ids)
@@ -74,7 +74,7 @@ def test_uniform_mapping_range_and_lattice(oracle_lib):
 
 @pytest.mark.parametrize("dim", [2, 3])
 def test_normals_are_standard(dim, oracle_lib):
-    w = W.scaled(W.config(3 if dim == 3 else 1), n_agents=10)
+    w = W.scaled(W.workload(W.BLOBS_1M if dim == 3 else W.PERIODIC_1K), n_agents=10)
     p = oracle.params(w)
     ids = np.arange(400_000, dtype=np.uint32)
     xi = np.concatenate([oracle.normals(p, s, ids) for s in (0, 1)], 0)
@@ -94,7 +94,7 @@ def test_normals_are_standard(dim, oracle_lib):
 
 
 def test_instances_draw_different_streams(oracle_lib):
-    w = W.config(4)
+    w = W.workload(W.ENSEMBLE_256)
     ids = np.arange(5000, dtype=np.uint32)
     x0 = oracle.normals(oracle.params(w, 0), 0, ids)
     x1 = oracle.normals(oracle.params(w, 1), 0, ids)

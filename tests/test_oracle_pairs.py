@@ -22,15 +22,16 @@ def _pairs_kdtree(X, diam_of, L, periodic, cutoff):
     return pairs
 
 
-@pytest.mark.parametrize("cfg,n", [(1, 3000), (2, 6000), (3, 6000), (5, 4000)])
-def test_neighbour_sets_vs_kdtree(cfg, n, oracle_lib):
-    w = W.scaled(W.config(cfg), n_agents=n)
-    if cfg == 3:
+@pytest.mark.parametrize("name,n", [(W.PERIODIC_1K, 3000), (W.WALLS_100K, 6000),
+                                    (W.BLOBS_1M, 6000), (W.ADJOINT_50K, 4000)])
+def test_neighbour_sets_vs_kdtree(name, n, oracle_lib):
+    w = W.scaled(W.workload(name), n_agents=n)
+    if name == W.BLOBS_1M:
         # blobs shrunk so that 6000 agents still have many contacts
         w = W.scaled(w, n_agents=n)
     inp = W.make_inputs(w)
     X32, sp = inp["x0"], inp["species0"]
-    if cfg == 3:
+    if name == W.BLOBS_1M:
         X32 = np.mod(X32 * np.float32(0.2), np.float32(1.0)).astype(np.float32)
     ids = np.arange(n, dtype=np.uint32)
     diam = [s.diameter for s in w.species]
@@ -116,11 +117,11 @@ def test_coincident_agents_no_force_and_contact_mean(oracle_lib):
     np.testing.assert_allclose(F[2], [2 * mag, 0], rtol=1e-9)
 
 
-@pytest.mark.parametrize("cfg", [1, 2, 5])
-def test_newton_third_law_and_modes(cfg, oracle_lib):
-    w = W.scaled(W.config(cfg), n_agents=3000)
+@pytest.mark.parametrize("name", [W.PERIODIC_1K, W.WALLS_100K, W.ADJOINT_50K])
+def test_newton_third_law_and_modes(name, oracle_lib):
+    w = W.scaled(W.workload(name), n_agents=3000)
     inp = W.make_inputs(w)
-    X = inp["x0"].astype(np.float64) * (0.3 if cfg != 2 else 0.2)
+    X = inp["x0"].astype(np.float64) * (0.3 if name != W.WALLS_100K else 0.2)
     Fb = oracle.forces(oracle.params(w, mode=0), X, inp["species0"])
     Fc = oracle.forces(oracle.params(w, mode=1), X, inp["species0"])
     assert np.array_equal(Fb, Fc)
@@ -130,7 +131,7 @@ def test_newton_third_law_and_modes(cfg, oracle_lib):
 
 
 def test_forces_subset_matches_full(oracle_lib):
-    w = W.scaled(W.config(3), n_agents=5000)
+    w = W.scaled(W.workload(W.BLOBS_1M), n_agents=5000)
     inp = W.make_inputs(w)
     X = inp["x0"].astype(np.float64) * 0.25
     p = oracle.params(w, mode=1)

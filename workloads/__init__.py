@@ -6,21 +6,26 @@ their initial conditions; it contains none of the method's arithmetic
 (no forces, noise, interpolation, deposit or PDE update).  Every array it
 returns is the exact input given to both the GPU library and the oracle.
 
-The paper runs its own simulations only (no public dataset); the five
-workloads below stand in for them:
+The paper runs its own simulations only (no public dataset); the six
+workloads below stand in for them (``workload(name)``):
 
-* ``config(1)``  2D periodic, 1,000 agents, 64^2 grid (parity case)
-* ``config(2)``  2D reflecting walls, 100,000 agents in two species, 512^2 grid
-* ``config(3)``  3D periodic, 1,000,000 agents in 8 Gaussian blobs, 128^3 grid
-* ``config(4)``  256 independent 2D instances of uneven size, 128^2 grids
-* ``config(5)``  2D periodic, 50,000 agents (producers / consumers), 256^2 grid
-* ``config(6)``  2000 realisations of the experiment of Sect. 4 (Fig. 1):
-  100 producers that switch to consumers plus 100 consumers each, reflecting
-  walls, 52^2 grid
+* ``2d_periodic_1k``           2D periodic, 1,000 agents, 64^2 grid (parity case)
+* ``2d_walls_100k``            2D reflecting walls, 100,000 agents in two species,
+  512^2 grid
+* ``3d_periodic_1M_blobs``     3D periodic, 1,000,000 agents in 8 Gaussian blobs,
+  128^3 grid
+* ``2d_ensemble_256``          256 independent 2D instances of uneven size, 128^2
+  grids
+* ``2d_periodic_50k_adjoint``  2D periodic, 50,000 agents (producers /
+  consumers), 256^2 grid; ``adjoint_2d`` sets its parameters
+* ``2d_walls_fig1_2000x200``   2000 realisations of the experiment of Sect. 4
+  (Fig. 1): 100 producers that switch to consumers plus 100 consumers each,
+  reflecting walls, 52^2 grid; ``fig1_walls_2d`` sets its size
 
-Initial conditions follow one recipe: a numpy ``PCG64(1000 + cfg)``
-generator draws everything in float64, which is then rounded to float32
-(positions) so that both sides start from identical float32 arrays.
+Initial conditions follow one recipe: a numpy ``PCG64`` generator with the
+workload's own seed (1001 ... 1006 in the order above) draws everything in
+float64, which is then rounded to float32 (positions) so that both sides
+start from identical float32 arrays.
 """
 from __future__ import annotations
 
@@ -31,8 +36,17 @@ from typing import List, Sequence, Tuple
 
 import numpy as np
 
-__all__ = ["Species", "Instance", "Workload", "config", "scaled", "make_inputs",
-           "node_coords", "CONFIGS"]
+__all__ = ["Species", "Instance", "Workload", "workload", "adjoint_2d", "fig1_walls_2d",
+           "scaled", "make_inputs", "node_coords", "NAMES", "PERIODIC_1K", "WALLS_100K",
+           "BLOBS_1M", "ENSEMBLE_256", "ADJOINT_50K", "FIG1_2000"]
+
+PERIODIC_1K = "2d_periodic_1k"
+WALLS_100K = "2d_walls_100k"
+BLOBS_1M = "3d_periodic_1M_blobs"
+ENSEMBLE_256 = "2d_ensemble_256"
+ADJOINT_50K = "2d_periodic_50k_adjoint"
+FIG1_2000 = "2d_walls_fig1_2000x200"
+NAMES = (PERIODIC_1K, WALLS_100K, BLOBS_1M, ENSEMBLE_256, ADJOINT_50K, FIG1_2000)
 
 
 @dataclass(frozen=True)
@@ -95,40 +109,41 @@ class Workload:
         return self.grid_n ** self.dim
 
 
-def _one_species_cfg1() -> Tuple[Species, ...]:
+def _one_species() -> Tuple[Species, ...]:
     return (Species(diameter=0.01, D=1.0, chi=1.0, source=1.0, uptake=0.0),)
 
 
-def config(n: int) -> Workload:
-    """The five reference workloads (sizes and parameters as specified)."""
-    if n == 1:
-        return Workload("cfg1_2d_periodic_1k", 2, True, 1.0, 64, 1e-5, 100.0, 1.0, 0.1, 100,
-                        _one_species_cfg1(), (Instance(1000, 1001),), gen_seed=1001)
-    if n == 2:
+def workload(name: str) -> Workload:
+    """One of the six workloads by name (sizes and parameters as listed in
+    the module docstring)."""
+    if name == PERIODIC_1K:
+        return Workload(PERIODIC_1K, 2, True, 1.0, 64, 1e-5, 100.0, 1.0, 0.1, 100,
+                        _one_species(), (Instance(1000, 1001),), gen_seed=1001)
+    if name == WALLS_100K:
         sp = (Species(0.002, 1.0, 0.0, 1.0, 0.0), Species(0.003, 0.5, 2.0, 0.0, 1.0))
-        return Workload("cfg2_2d_walls_100k", 2, False, 1.0, 512, 1e-6, 1000.0, 1.0, 0.1, 1000,
+        return Workload(WALLS_100K, 2, False, 1.0, 512, 1e-6, 1000.0, 1.0, 0.1, 1000,
                         sp, (Instance(100_000, 1002),), species_rule="halves", c0="cos",
                         gen_seed=1002)
-    if n == 3:
+    if name == BLOBS_1M:
         sp = (Species(0.004, 1.0, 1.0, 1.0, 0.0),)
-        return Workload("cfg3_3d_periodic_1M_blobs", 3, True, 1.0, 128, 1e-7, 1000.0, 1.0, 0.1,
+        return Workload(BLOBS_1M, 3, True, 1.0, 128, 1e-7, 1000.0, 1.0, 0.1,
                         200, sp, (Instance(1_000_000, 1003),), layout="blobs", gen_seed=1003)
-    if n == 4:
+    if name == ENSEMBLE_256:
         rng = np.random.Generator(np.random.PCG64(1004))
         n_i = np.rint(np.exp(rng.uniform(math.log(500), math.log(20000), 256))).astype(int)
         chi = rng.uniform(0.0, 3.0, 256)
         seeds = rng.integers(0, 2**63, 256, dtype=np.int64)
         inst = tuple(Instance(int(a), int(s), float(c)) for a, s, c in zip(n_i, seeds, chi))
-        return Workload("cfg4_2d_ensemble_256", 2, True, 1.0, 128, 1e-5, 100.0, 1.0, 0.1, 500,
-                        _one_species_cfg1(), inst, gen_seed=1004)
-    if n == 5:
-        return config5()
-    if n == 6:
-        return config6()
-    raise ValueError(f"no workload {n}")
+        return Workload(ENSEMBLE_256, 2, True, 1.0, 128, 1e-5, 100.0, 1.0, 0.1, 500,
+                        _one_species(), inst, gen_seed=1004)
+    if name == ADJOINT_50K:
+        return adjoint_2d()
+    if name == FIG1_2000:
+        return fig1_walls_2d()
+    raise ValueError(f"no workload {name!r}")
 
 
-def config6(n_real: int = 2000, chi: float = 10.0, seed: int = 1006) -> Workload:
+def fig1_walls_2d(n_real: int = 2000, chi: float = 10.0, seed: int = 1006) -> Workload:
     """The experiment of Sect. 4 with the parameters of its Fig. 1 caption:
     N_alpha(0) = N_beta(0) = 100, diameter 0.02, r_alpha = 10, r_beta = 0,
     D_alpha = 0.1, D_beta = 1, D_c = 1, k_alpha = 0.1, k_beta = 0.03,
@@ -142,20 +157,18 @@ def config6(n_real: int = 2000, chi: float = 10.0, seed: int = 1006) -> Workload
     rng = np.random.Generator(np.random.PCG64(seed))
     seeds = rng.integers(0, 2**63, n_real, dtype=np.int64)
     inst = tuple(Instance(200, int(s)) for s in seeds)
-    return Workload("cfg6_2d_walls_fig1_2000x200", 2, False, 1.0, 52, dt, 1e4, 1.0, 0.0,
+    return Workload(FIG1_2000 if n_real == 2000 else f"2d_walls_fig1_{n_real}x200", 2, False, 1.0, 52, dt, 1e4, 1.0, 0.0,
                     int(round(0.05 / dt)), sp, inst, layout="centre_uniform",
                     species_rule="halves", c0="zero", gen_seed=seed)
 
 
-def config5(chi: float = 1.0, k: float = 100.0, D: float = 1.0, seed: int = 1005) -> Workload:
+def adjoint_2d(chi: float = 1.0, k: float = 100.0, D: float = 1.0, seed: int = 1005) -> Workload:
     """Differentiation workload: producers (species 0) and consumers (species 1)."""
     sp = (Species(0.01, D, 0.0, 1.0, 0.0), Species(0.01, D, chi, 0.0, 1.0))
-    return Workload("cfg5_2d_periodic_50k_adjoint", 2, True, 1.0, 256, 1e-5, k, 1.0, 0.1, 200,
+    return Workload(ADJOINT_50K, 2, True, 1.0, 256, 1e-5, k, 1.0, 0.1, 200,
                     sp, (Instance(50_000, seed),), pde_substeps=3, species_rule="halves",
                     gen_seed=1005)
 
-
-CONFIGS = (1, 2, 3, 4, 5, 6)
 
 
 def scaled(w: Workload, n_agents: int | Sequence[int] | None = None,
