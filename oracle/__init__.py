@@ -16,7 +16,28 @@ Function map (all arrays are numpy, float64 unless stated):
 * :func:`drift`             chi * interpolated gradient at every agent
 * :func:`deposit`           piecewise-linear deposit of source / uptake
 * :func:`pde`               n_sub forward-Euler updates of the chemical
+* :func:`pde_density`       the same updates from densities (kernel density deposit)
+* :func:`deposit_kde`       Gaussian kernel density of source / uptake at the nodes
+* :func:`react`             type switching of one step (eq. Chemo_reactions)
+* :func:`hs_correct`        hard-sphere overlap correction
 * :func:`step` / :func:`run` whole time steps of one instance
+* :func:`density_loss`      smoothed-histogram loss of the differentiation runs
+* :func:`species_hist`, :func:`field_mean`  ensemble statistics
+
+Pins (``tests/test_oracle_*.py``, all CPU): Philox against rocRAND's
+philox4x32_10 engine compiled for the host; normals by
+moments and KS; neighbour sets against a k-d tree and all-pairs search;
+forces by two-agent closed forms and Newton's third law; interpolation,
+gradient and deposit by exact affine cases, the deposit / interpolation
+duality and mass; the PDE by its exact discrete Fourier decay and mass
+invariants; free diffusion and constant drift by their MSD and mean laws;
+type switching by the two-state Markov chain; the kernel density by its
+mass, second moment and peak value; the potential variants by the force as
+minus the energy gradient, pair closed forms and the hard-sphere invariants;
+the ensemble statistics by brute-force counts.  The coupled
+multi-step trajectory (``run`` over many steps) has no printed values in the
+paper: beyond the per-step pins and the MSD / drift laws it is **parity
+unpinned**.
 """
 from __future__ import annotations
 

@@ -10,6 +10,10 @@
  *
  * Every function below cites the part of the paper it follows.  Where the
  * paper is silent or garbled the reading taken is stated next to the code.
+ * Each function is pinned by the CPU tests (closed forms, invariants,
+ * library routines, brute force); the coupled multi-step trajectory has no
+ * printed values in the paper and is parity unpinned beyond the per-step
+ * pins and the diffusion / drift laws.
  *
  * State of one instance: positions X (N x dim, float64), species s (uint8),
  * stable ids (uint32), chemical c on the node grid (x fastest), a step
