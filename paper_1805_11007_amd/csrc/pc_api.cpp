@@ -55,7 +55,7 @@ static bool reacts(const pc_species_t &s) {
 }
 
 struct Layout {
-    size_t P[3], I[3], bin, rank, count, start, tile_sum, c[2], S_src, S_upt, inst, species_id,
+    size_t P[3], I[3], bin, rank, count, start, tile_sum, tile_cnt, c[2], S_src, S_upt, inst, species_id,
         step, flags, seg_x, seg_c, lamX[2], lamY, lamC[2], aSrc, aUpt, lamG, csub, dth;
     size_t total;
 };
@@ -208,6 +208,7 @@ Layout layout(const Derived &d, int seg_steps) {
     L.count = take(cur, 4 * ((size_t)d.bins_total + 1));
     L.start = take(cur, 4 * ((size_t)d.bins_total + 1));
     L.tile_sum = take(cur, 4 * (((size_t)d.bins_total + 1 + kScanTile - 1) / kScanTile));
+    L.tile_cnt = take(cur, 4 * (((size_t)d.bins_total + 1 + kScanTile - 1) / kScanTile));
     L.c[0] = take(cur, 4 * (size_t)d.nodes_total);
     L.c[1] = take(cur, 4 * (size_t)d.nodes_total);
     L.S_src = take(cur, 8 * (size_t)d.nodes_total);
@@ -367,6 +368,7 @@ static void carve(pc_sim *s, char *ws) {
     b.count = (uint32_t *)(ws + L.count);
     b.start = (uint32_t *)(ws + L.start);
     b.tile_sum = (uint32_t *)(ws + L.tile_sum);
+    b.tile_cnt = (uint32_t *)(ws + L.tile_cnt);
     b.c[0] = (float *)(ws + L.c[0]);
     b.c[1] = (float *)(ws + L.c[1]);
     b.S_src = (unsigned long long *)(ws + L.S_src);
@@ -389,6 +391,12 @@ static void carve(pc_sim *s, char *ws) {
         b.csub = (float *)(ws + L.csub);
         b.dth = (double *)(ws + L.dth);
     }
+}
+
+// Clear a histogram that no scan consumed: the bin counts and the tile totals.
+static void zero_counts(pc_sim *s, hipStream_t st) {
+    launch_zero_u32(s->b.count, s->d.bins_total + 1, st);
+    launch_zero_u32(s->b.tile_cnt, (s->d.bins_total + kScanTile) / kScanTile, st);
 }
 
 // Cell-sort the current positions (scan of the counts, scatter, optional
@@ -546,6 +554,7 @@ static int common_create(const pc_config *cfg, const pc_species_t *species, int 
     CK(hipMemcpyAsync(s->b.inst, s->inst_host.data(), sizeof(InstInfo) * n_inst,
                       hipMemcpyHostToDevice, st));
     CK(hipMemsetAsync(s->b.count, 0, 4 * ((size_t)d.bins_total + 1), st));
+    CK(hipMemsetAsync(s->b.tile_cnt, 0, 4 * (((size_t)d.bins_total + kScanTile) / kScanTile), st));
     CK(hipMemsetAsync(s->b.S_src, 0, 8 * (size_t)d.nodes_total, st));
     if (d.has_uptake) CK(hipMemsetAsync(s->b.S_upt, 0, 8 * (size_t)d.nodes_total, st));
     CK(hipMemsetAsync(s->b.step, 0, 4, st));
@@ -785,7 +794,7 @@ int pc_get_state(pc_sim *s, float *x_dev, float *c_dev, uint32_t *step) {
 int pc_set_state(pc_sim *s, const float *x_dev, const float *c_dev, uint32_t step) {
     if (!s) return fail(PC_EINVAL, "null handle");
     if (x_dev) {
-        if (s->binned) launch_zero_u32(s->b.count, s->d.bins_total + 1, s->stream);
+        if (s->binned) zero_counts(s, s->stream);
         launch_init_agents(s->sp, s->b, x_dev, s->b.species_id, 0, s->stream);
         launch_bin(s->sp, s->b, 0, s->d.block, s->stream);
         s->binned = 1;
@@ -909,7 +918,7 @@ int pc_debug_forces(pc_sim *s, float *F_dev) {
 
 // Load positions (id order, device) into P[0] without touching the field.
 static void load_positions(pc_sim *s, const float *x, hipStream_t st) {
-    if (s->binned) launch_zero_u32(s->b.count, s->d.bins_total + 1, st);
+    if (s->binned) zero_counts(s, st);
     launch_init_agents(s->sp, s->b, x, s->b.species_id, 0, st);
     s->binned = 0;
     s->sorted = 0;

@@ -9,6 +9,8 @@ namespace pc {
 
 constexpr int kMaxSpecies = 8;
 constexpr int kScanTile = 2048;   // bins per scan tile (256 threads x 8)
+constexpr int kScanTileLog2 = 11;
+static_assert(kScanTile == 1 << kScanTileLog2, "scan tile is a power of two");
 constexpr int kFixShift = 32;     // deposit fixed point: value * 2^32 in uint64
 
 // Per-instance table (device), 32 bytes.
@@ -89,7 +91,8 @@ struct Buffers {
     uint32_t *bin, *rank;
     uint32_t *count;       // bins_total + 1
     uint32_t *start;       // bins_total + 1
-    uint32_t *tile_sum;    // ceil((bins_total + 1) / kScanTile)
+    uint32_t *tile_sum;    // ceil((bins_total + 1) / kScanTile): exclusive tile prefixes
+    uint32_t *tile_cnt;    // same size: agents per scan tile, added with the bin counts
     float *c[2];           // chemical, two buffers for substeps
     unsigned long long *S_src, *S_upt;  // fixed-point deposits
     InstInfo *inst;

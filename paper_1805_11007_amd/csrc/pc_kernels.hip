@@ -45,17 +45,38 @@ __global__ void k_init_agents(StepParams p, const InstInfo *__restrict__ inst,
     I[g] = (uint32_t)g - inst[lo].agent_base;
 }
 
+// Histogram of one agent's bin b: its rank within the bin, and the agent
+// added to the total of b's scan tile.  The tile totals are summed over the
+// wave first, one device atomic per distinct tile (agents come in cell
+// order, so a wave rarely spans more than two tiles); they spare the scan a
+// pass over every bin count.
+__device__ __forceinline__ uint32_t count_bin(uint32_t *__restrict__ count,
+                                              uint32_t *__restrict__ tile_cnt, uint32_t b) {
+    const uint32_t r = atomicAdd(count + b, 1u);
+    const uint32_t t = b >> kScanTileLog2;
+    while (true) {
+        const uint32_t lead = __builtin_amdgcn_readfirstlane(t);
+        const unsigned long long m = __ballot(t == lead);
+        if (t == lead) {
+            if (__lane_id() == __builtin_ctzll(m)) atomicAdd(tile_cnt + lead, (uint32_t)__popcll(m));
+            break;
+        }
+    }
+    return r;
+}
+
 template <int DIM>
 __global__ void k_bin(StepParams p, const InstInfo *__restrict__ inst,
                       const float4 *__restrict__ P, uint32_t *__restrict__ bin,
-                      uint32_t *__restrict__ rank, uint32_t *__restrict__ count) {
+                      uint32_t *__restrict__ rank, uint32_t *__restrict__ count,
+                      uint32_t *__restrict__ tile_cnt) {
     const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
     const int i = blk * blockDim.x + threadIdx.x;
     if (i >= p.n_total) return;
     const float4 x = P[i];
     const uint32_t b = inst[inst_of(x.w)].bin_base + agent_bin<DIM>(p, x);
     bin[i] = b;
-    rank[i] = atomicAdd(count + b, 1u);
+    rank[i] = count_bin(count, tile_cnt, b);
 }
 
 // Block-wide exclusive scan of one value per thread (blockDim = 256).
@@ -91,29 +112,20 @@ __device__ __forceinline__ void load8(const uint32_t *__restrict__ a, int64_t ba
     }
 }
 
-__global__ void __launch_bounds__(256) k_tile_sums(const uint32_t *__restrict__ count,
-                                                   int64_t n, uint32_t *__restrict__ tile_sum) {
-    __shared__ uint32_t lds[4];
-    const int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x * 8;
-    uint32_t v[8];
-    load8(count, base, n, v);
-    const uint32_t s = ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]));
-    uint32_t tot;
-    block_exscan256(s, lds, tot);
-    if (threadIdx.x == 0) tile_sum[blockIdx.x] = tot;
-}
-
-// Exclusive scan of the T tile sums in place by one work-group of 1024
-// threads: passes of 8192 sums, 8 consecutive sums per thread (two 16-byte
-// loads and stores), carrying the running total between passes.
-__global__ void __launch_bounds__(1024) k_scan_tiles(uint32_t *__restrict__ tile_sum, int T) {
+// Exclusive scan of the T tile totals (gathered by the histogram) into
+// tile_sum by one work-group of 1024 threads: passes of 8192 totals, 8
+// consecutive totals per thread (two 16-byte loads and stores), carrying
+// the running total between passes.  The totals are cleared for the next
+// histogram.
+__global__ void __launch_bounds__(1024) k_scan_tiles(uint32_t *__restrict__ tile_cnt,
+                                                     uint32_t *__restrict__ tile_sum, int T) {
     __shared__ uint32_t lds[16];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     uint32_t carry = 0;
     for (int64_t off = 0; off < T; off += 8192) {
         const int64_t b0 = off + threadIdx.x * 8;
         uint32_t v[8];
-        load8(tile_sum, b0, T, v);
+        load8(tile_cnt, b0, T, v);
         const uint32_t s = ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]));
         uint32_t x = s;
 #pragma unroll
@@ -141,9 +153,15 @@ __global__ void __launch_bounds__(1024) k_scan_tiles(uint32_t *__restrict__ tile
             uint4 *p4 = reinterpret_cast<uint4 *>(tile_sum + b0);
             p4[0] = make_uint4(o[0], o[1], o[2], o[3]);
             p4[1] = make_uint4(o[4], o[5], o[6], o[7]);
+            uint4 *z4 = reinterpret_cast<uint4 *>(tile_cnt + b0);
+            z4[0] = make_uint4(0u, 0u, 0u, 0u);
+            z4[1] = make_uint4(0u, 0u, 0u, 0u);
         } else {
             for (int k = 0; k < 8; ++k)
-                if (b0 + k < T) tile_sum[b0 + k] = o[k];
+                if (b0 + k < T) {
+                    tile_sum[b0 + k] = o[k];
+                    tile_cnt[b0 + k] = 0u;
+                }
         }
         carry += total;
         __syncthreads();
@@ -226,6 +244,7 @@ k_update(StepParams p, const InstInfo *__restrict__ inst, const float4 *__restri
          const uint32_t *__restrict__ Is, const uint32_t *__restrict__ start,
          const float *__restrict__ c, float4 *__restrict__ Pout, uint32_t *__restrict__ Iout,
          uint32_t *__restrict__ bin, uint32_t *__restrict__ rank, uint32_t *__restrict__ count,
+         uint32_t *__restrict__ tile_cnt,
          const uint32_t *__restrict__ stepc, uint32_t *__restrict__ flags) {
     __shared__ SpTab tab;
     if (NS == 0) {
@@ -302,7 +321,7 @@ k_update(StepParams p, const InstInfo *__restrict__ inst, const float4 *__restri
     Iout[i] = id;
     const uint32_t b = ii.bin_base + agent_bin<DIM>(p, xn);
     bin[i] = b;
-    rank[i] = atomicAdd(count + b, 1u);
+    rank[i] = count_bin(count, tile_cnt, b);
     if (flag) atomicOr(flags, flag);
 }
 
@@ -681,7 +700,7 @@ k_overlap(StepParams p, const InstInfo *__restrict__ inst, const float4 *__restr
           const uint32_t *__restrict__ Is, const uint32_t *__restrict__ start,
           float4 *__restrict__ Pout, uint32_t *__restrict__ Iout, uint32_t *__restrict__ bin,
           uint32_t *__restrict__ rank, uint32_t *__restrict__ count,
-          uint32_t *__restrict__ flags) {
+          uint32_t *__restrict__ tile_cnt, uint32_t *__restrict__ flags) {
     __shared__ SpTab tab;
     load_tab(p, tab);
     __syncthreads();
@@ -704,7 +723,7 @@ k_overlap(StepParams p, const InstInfo *__restrict__ inst, const float4 *__restr
     Iout[i] = Is[i];
     const uint32_t b = ii.bin_base + agent_bin<DIM>(p, xn);
     bin[i] = b;
-    rank[i] = atomicAdd(count + b, 1u);
+    rank[i] = count_bin(count, tile_cnt, b);
     if (flag) atomicOr(flags, flag);
 }
 
@@ -731,17 +750,18 @@ void launch_init_agents(const StepParams &p, const Buffers &b, const float *x, c
 void launch_bin(const StepParams &p, const Buffers &b, int src, int block, hipStream_t s) {
     const dim3 g(grid_for(p.n_total, block)), t(block);
     if (p.dim == 2)
-        hipLaunchKernelGGL(k_bin<2>, g, t, 0, s, p, b.inst, b.P[src], b.bin, b.rank, b.count);
+        hipLaunchKernelGGL(k_bin<2>, g, t, 0, s, p, b.inst, b.P[src], b.bin, b.rank, b.count,
+                           b.tile_cnt);
     else
-        hipLaunchKernelGGL(k_bin<3>, g, t, 0, s, p, b.inst, b.P[src], b.bin, b.rank, b.count);
+        hipLaunchKernelGGL(k_bin<3>, g, t, 0, s, p, b.inst, b.P[src], b.bin, b.rank, b.count,
+                           b.tile_cnt);
 }
 
 void launch_scan(const Buffers &b, int64_t n_bins_total, int32_t n_total, hipStream_t s) {
     (void)n_total;
     const int64_t n = n_bins_total + 1;  // count[n_bins_total] is always 0
     const int T = (int)((n + kScanTile - 1) / kScanTile);
-    hipLaunchKernelGGL(k_tile_sums, dim3(T), dim3(256), 0, s, b.count, n, b.tile_sum);
-    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, s, b.tile_sum, T);
+    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, s, b.tile_cnt, b.tile_sum, T);
     hipLaunchKernelGGL(k_scan_apply, dim3(T), dim3(256), 0, s, b.count, n, b.tile_sum, b.start);
 }
 
@@ -767,7 +787,7 @@ static void upd(const StepParams &p, const Buffers &b, int src, int dst, int cbu
                 hipStream_t s) {
     hipLaunchKernelGGL((k_update<DIM, NS, ST, 0>), dim3(grid_for(p.n_total, block)), dim3(block),
                        0, s, p, b.inst, b.P[src], b.I[src], b.start, b.c[cbuf], b.P[dst],
-                       b.I[dst], b.bin, b.rank, b.count, b.step, b.flags);
+                       b.I[dst], b.bin, b.rank, b.count, b.tile_cnt, b.step, b.flags);
 }
 
 // the other potentials use the generic (LDS) species table
@@ -776,7 +796,8 @@ static void upd_pot(const StepParams &p, const Buffers &b, int src, int dst, int
                     hipStream_t s) {
     hipLaunchKernelGGL((k_update<DIM, 0, ST, POT>), dim3(grid_for(p.n_total, block)),
                        dim3(block), 0, s, p, b.inst, b.P[src], b.I[src], b.start, b.c[cbuf],
-                       b.P[dst], b.I[dst], b.bin, b.rank, b.count, b.step, b.flags);
+                       b.P[dst], b.I[dst], b.bin, b.rank, b.count, b.tile_cnt, b.step,
+                       b.flags);
 }
 
 template <int DIM, int NS, int ST>
@@ -850,7 +871,7 @@ void launch_overlap(const StepParams &p, const Buffers &b, int src, int dst, int
     const dim3 g(grid_for(p.n_total, block)), t(block);
 #define PC_OV(D, S)                                                                          \
     hipLaunchKernelGGL((k_overlap<D, S>), g, t, 0, s, p, b.inst, b.P[src], b.I[src], b.start, \
-                       b.P[dst], b.I[dst], b.bin, b.rank, b.count, b.flags)
+                       b.P[dst], b.I[dst], b.bin, b.rank, b.count, b.tile_cnt, b.flags)
     if (p.dim == 2) {
         if (p.stencil == 3) PC_OV(2, 3);
         else PC_OV(2, 2);
