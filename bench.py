@@ -43,9 +43,9 @@ FLOP_PER_PAIR, FLOP_PER_AGENT = 18.0, 140.0
 # rocprofv3 FETCH_SIZE and WRITE_SIZE runs (each scaled by the same counter's
 # reading for a plain device copy); valid only for the kernel sources they
 # were taken with, identified by a hash of those files.
-UPDATE_TRAFFIC_BYTES = 104.3e6
+UPDATE_TRAFFIC_BYTES = 106.0e6
 UPDATE_TRAFFIC_SOURCES = ("pc_internal.h", "pc_device.h", "pc_kernels.hip")
-UPDATE_TRAFFIC_SHA = "3e7a410a8a6551c0"
+UPDATE_TRAFFIC_SHA = "063deb764b460cc1"
 
 
 def update_traffic(workload: str):

@@ -291,6 +291,10 @@ static void fill_params(pc_sim *s) {
     p.inv_h2 = (float)(1.0 / (d.h * d.h));
     p.dt = (float)c.dt;
     p.k = (float)c.k_rep;
+    // Tile totals gathered by the histogram spare the scan a pass over every
+    // bin count, which pays where bins far outnumber agents; with fewer bins
+    // per agent the waves would queue on few tile counters.
+    p.tile_totals = d.bins_total + 1 >= 8 * d.n_total ? 1 : 0;
     // the factor k (d / r - 1) reaches this only for r < 1e-10 d; it keeps
     // the factor finite at r = 0, where it multiplies dx = 0
     p.fcap = (float)std::min(1e10 * c.k_rep * d.contact_max, 1e38);
@@ -405,7 +409,7 @@ static void ensure_sorted(pc_sim *s, hipStream_t st) {
     if (s->sorted) return;
     const int blk = s->d.block;
     if (!s->binned) launch_bin(s->sp, s->b, 0, blk, st);
-    launch_scan(s->b, s->d.bins_total, (int32_t)s->d.n_total, st);
+    launch_scan(s->sp, s->b, s->d.bins_total, st);
     s->binned = 0;
     launch_scatter(s->sp, s->b, 0, 1, blk, st);
     s->sorted_src = 1;
@@ -702,7 +706,7 @@ int pc_profile_steps(pc_sim *s, int n_steps, double *stage_ms) {
                 PC_STAGE(PC_STAGE_BIN, launch_bin(s->sp, s->b, 0, blk, st));
                 s->binned = 1;
             }
-            PC_STAGE(PC_STAGE_SCAN, launch_scan(s->b, s->d.bins_total, (int32_t)s->d.n_total, st));
+            PC_STAGE(PC_STAGE_SCAN, launch_scan(s->sp, s->b, s->d.bins_total, st));
             s->binned = 0;
             PC_STAGE(PC_STAGE_SCATTER, launch_scatter(s->sp, s->b, 0, 1, blk, st));
             s->sorted_src = 1;

@@ -40,6 +40,7 @@ struct StepParams {
     float inv_bin;         // nb / L
     float h, inv_h, inv_2h, inv_h2;
     float dt, k;
+    int32_t tile_totals;   // 1: the histogram also totals each scan tile
     float fcap;            // upper clamp of the harmonic force factor, 1e10 k max d
     float cell_top;        // largest lower-corner index as float (n-1 periodic, n-2 walls)
     float cut2[kMaxSpecies * kMaxSpecies];  // float32 squared contact distances
@@ -135,7 +136,7 @@ struct LossArgs {
 void launch_init_agents(const StepParams &p, const Buffers &b, const float *x, const uint8_t *sp,
                         int write_species, hipStream_t s);
 void launch_bin(const StepParams &p, const Buffers &b, int src, int block, hipStream_t s);
-void launch_scan(const Buffers &b, int64_t n_bins_total, int32_t n_total, hipStream_t s);
+void launch_scan(const StepParams &p, const Buffers &b, int64_t n_bins_total, hipStream_t s);
 void launch_scatter(const StepParams &p, const Buffers &b, int src, int dst, int block,
                     hipStream_t s);
 void launch_stable(const StepParams &p, const Buffers &b, int src, int dst, int block,

@@ -45,14 +45,16 @@ __global__ void k_init_agents(StepParams p, const InstInfo *__restrict__ inst,
     I[g] = (uint32_t)g - inst[lo].agent_base;
 }
 
-// Histogram of one agent's bin b: its rank within the bin, and the agent
+// Histogram of one agent's bin b: its rank within the bin and, when the
+// scan takes its tile totals from the histogram (totals != 0), the agent
 // added to the total of b's scan tile.  The tile totals are summed over the
 // wave first, one device atomic per distinct tile (agents come in cell
-// order, so a wave rarely spans more than two tiles); they spare the scan a
-// pass over every bin count.
+// order, so a wave rarely spans more than two tiles).
 __device__ __forceinline__ uint32_t count_bin(uint32_t *__restrict__ count,
-                                              uint32_t *__restrict__ tile_cnt, uint32_t b) {
+                                              uint32_t *__restrict__ tile_cnt, uint32_t b,
+                                              int32_t totals) {
     const uint32_t r = atomicAdd(count + b, 1u);
+    if (!totals) return r;
     const uint32_t t = b >> kScanTileLog2;
     while (true) {
         const uint32_t lead = __builtin_amdgcn_readfirstlane(t);
@@ -76,7 +78,7 @@ __global__ void k_bin(StepParams p, const InstInfo *__restrict__ inst,
     const float4 x = P[i];
     const uint32_t b = inst[inst_of(x.w)].bin_base + agent_bin<DIM>(p, x);
     bin[i] = b;
-    rank[i] = count_bin(count, tile_cnt, b);
+    rank[i] = count_bin(count, tile_cnt, b, p.tile_totals);
 }
 
 // Block-wide exclusive scan of one value per thread (blockDim = 256).
@@ -112,8 +114,22 @@ __device__ __forceinline__ void load8(const uint32_t *__restrict__ a, int64_t ba
     }
 }
 
-// Exclusive scan of the T tile totals (gathered by the histogram) into
-// tile_sum by one work-group of 1024 threads: passes of 8192 totals, 8
+// Totals of the bin counts of each scan tile, for histograms that did not
+// gather them (few bins per agent).
+__global__ void __launch_bounds__(256) k_tile_sums(const uint32_t *__restrict__ count,
+                                                   int64_t n, uint32_t *__restrict__ tile_cnt) {
+    __shared__ uint32_t lds[4];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x * 8;
+    uint32_t v[8];
+    load8(count, base, n, v);
+    const uint32_t s = ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]));
+    uint32_t tot;
+    block_exscan256(s, lds, tot);
+    if (threadIdx.x == 0) tile_cnt[blockIdx.x] = tot;
+}
+
+// Exclusive scan of the T tile totals (gathered by the histogram or by
+// k_tile_sums) into tile_sum by one work-group of 1024 threads: passes of 8192 totals, 8
 // consecutive totals per thread (two 16-byte loads and stores), carrying
 // the running total between passes.  The totals are cleared for the next
 // histogram.
@@ -321,7 +337,7 @@ k_update(StepParams p, const InstInfo *__restrict__ inst, const float4 *__restri
     Iout[i] = id;
     const uint32_t b = ii.bin_base + agent_bin<DIM>(p, xn);
     bin[i] = b;
-    rank[i] = count_bin(count, tile_cnt, b);
+    rank[i] = count_bin(count, tile_cnt, b, p.tile_totals);
     if (flag) atomicOr(flags, flag);
 }
 
@@ -723,7 +739,7 @@ k_overlap(StepParams p, const InstInfo *__restrict__ inst, const float4 *__restr
     Iout[i] = Is[i];
     const uint32_t b = ii.bin_base + agent_bin<DIM>(p, xn);
     bin[i] = b;
-    rank[i] = count_bin(count, tile_cnt, b);
+    rank[i] = count_bin(count, tile_cnt, b, p.tile_totals);
     if (flag) atomicOr(flags, flag);
 }
 
@@ -757,10 +773,11 @@ void launch_bin(const StepParams &p, const Buffers &b, int src, int block, hipSt
                            b.tile_cnt);
 }
 
-void launch_scan(const Buffers &b, int64_t n_bins_total, int32_t n_total, hipStream_t s) {
-    (void)n_total;
+void launch_scan(const StepParams &p, const Buffers &b, int64_t n_bins_total, hipStream_t s) {
     const int64_t n = n_bins_total + 1;  // count[n_bins_total] is always 0
     const int T = (int)((n + kScanTile - 1) / kScanTile);
+    if (!p.tile_totals)
+        hipLaunchKernelGGL(k_tile_sums, dim3(T), dim3(256), 0, s, b.count, n, b.tile_cnt);
     hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, s, b.tile_cnt, b.tile_sum, T);
     hipLaunchKernelGGL(k_scan_apply, dim3(T), dim3(256), 0, s, b.count, n, b.tile_sum, b.start);
 }
