@@ -45,7 +45,7 @@ FLOP_PER_PAIR, FLOP_PER_AGENT = 18.0, 140.0
 # were taken with, identified by a hash of those files.
 UPDATE_TRAFFIC_BYTES = 106.0e6
 UPDATE_TRAFFIC_SOURCES = ("pc_internal.h", "pc_device.h", "pc_kernels.hip")
-UPDATE_TRAFFIC_SHA = "063deb764b460cc1"
+UPDATE_TRAFFIC_SHA = "b37235202ba9e0a2"
 
 
 def update_traffic(workload: str):
