@@ -91,7 +91,7 @@ typedef struct {
                                bitwise reproducible run to run                          */
     int32_t block;          /* 0: 128; else work-group size of the agent kernels
                                (64, 128, 256, 512 or 1024)                              */
-    int32_t bin_order;      /* 0: row-major bins (x fastest); 1: 2x2(x2) brick order     */
+    int32_t bin_order;      /* must be 0: row-major bins (x fastest); others PC_ENOTSUP   */
     int32_t deposit_mode;   /* 0: automatic; 1: contributions summed per work-group in
                                LDS before the device atomics; 2: device atomics only;
                                3: deposit and PDE substeps of each instance in one
