@@ -44,24 +44,33 @@ FLOP_PER_PAIR, FLOP_PER_AGENT = 18.0, 140.0
 # reading for a plain device copy); valid only for the kernel sources they
 # were taken with, identified by a hash of those files.
 UPDATE_TRAFFIC_BYTES = 106.0e6
+# SQ_INSTS_VALU of the same kernel over the chip's issue capacity in its
+# GRBM_GUI_ACTIVE cycles (one wave64 VALU instruction per SIMD per 4 cycles)
+UPDATE_VALU_ISSUE = 0.59
 UPDATE_TRAFFIC_SOURCES = ("pc_internal.h", "pc_device.h", "pc_kernels.hip")
 UPDATE_TRAFFIC_SHA = "b37235202ba9e0a2"
 
 
-def update_traffic(workload: str):
-    """Counter traffic of the update kernel, or None if the kernel sources
-    changed since the counters were taken or the workload differs."""
+def update_counters_valid(workload: str) -> bool:
+    """True while the update kernel's sources and the workload are those the
+    counters were taken with."""
     import hashlib
     if workload != "3d_periodic_1M_blobs":
-        return None
+        return False
     h = hashlib.sha256()
     csrc = Path(__file__).resolve().parent / "paper_1805_11007_amd" / "csrc"
     try:
         for f in UPDATE_TRAFFIC_SOURCES:
             h.update((csrc / f).read_bytes())
     except OSError:
-        return None
-    return UPDATE_TRAFFIC_BYTES if h.hexdigest()[:16] == UPDATE_TRAFFIC_SHA else None
+        return False
+    return h.hexdigest()[:16] == UPDATE_TRAFFIC_SHA
+
+
+def update_traffic(workload: str):
+    """Counter traffic of the update kernel, or None if the kernel sources
+    changed since the counters were taken or the workload differs."""
+    return UPDATE_TRAFFIC_BYTES if update_counters_valid(workload) else None
 
 
 def algorithmic_bytes(stage: str, w, n_sub: int) -> float:
@@ -477,6 +486,7 @@ def main() -> int:
         roof = {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": FP32_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS,
                 "traffic": update_traffic(w.name),
+                "valu_issue_frac": UPDATE_VALU_ISSUE if update_counters_valid(w.name) else None,
                 "algorithmic_flop_per_launch": flops, "mean_neighbours": nbr_mean,
                 "launch_ms": prof[dom]}
     else:
