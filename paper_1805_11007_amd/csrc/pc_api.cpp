@@ -682,7 +682,16 @@ int pc_profile_steps(pc_sim *s, int n_steps, double *stage_ms) {
     if (!s || !stage_ms || n_steps < 1) return fail(PC_EINVAL, "bad argument");
     hipStream_t st = s->stream;
     const int blk = s->d.block;
-    hipEvent_t e0[PC_N_STAGES], e1[PC_N_STAGES];
+    // the events are destroyed on every return path
+    struct Events {
+        hipEvent_t e[2][PC_N_STAGES] = {};
+        ~Events() {
+            for (auto &row : e)
+                for (hipEvent_t ev : row)
+                    if (ev) (void)hipEventDestroy(ev);
+        }
+    } ev;
+    hipEvent_t *e0 = ev.e[0], *e1 = ev.e[1];
     for (int k = 0; k < PC_N_STAGES; ++k) {
         HIP_OK(hipEventCreate(&e0[k]));
         HIP_OK(hipEventCreate(&e1[k]));
@@ -750,10 +759,6 @@ int pc_profile_steps(pc_sim *s, int n_steps, double *stage_ms) {
             HIP_OK(hipEventElapsedTime(&ms, e0[k], e1[k]));
             acc[k] += ms;
         }
-    }
-    for (int k = 0; k < PC_N_STAGES; ++k) {
-        (void)hipEventDestroy(e0[k]);
-        (void)hipEventDestroy(e1[k]);
     }
     for (int k = 0; k < PC_N_STAGES; ++k) stage_ms[k] = acc[k] / n_steps;
     HIP_OK(hipGetLastError());

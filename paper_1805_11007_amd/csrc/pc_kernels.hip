@@ -9,6 +9,8 @@
 // a uint32 stable id.  A step is: bin -> scan -> scatter (cell-sorted copy)
 // [-> stable order by id] -> update (pairs + drift + noise + boundary +
 // deposit, writing back into the unsorted buffer in sorted order) -> PDE.
+#include <algorithm>
+
 #include "pc_device.h"
 
 namespace pc {
@@ -589,31 +591,36 @@ k_chem_inst(StepParams p, PdeParams q, const InstInfo *__restrict__ inst,
 // KDE: the source array holds (sigma, upsilon) float pairs, rewritten by
 // every step's density gather, so nothing is cleared.  stepc (non-null on
 // the last substep of a step): the step counter, advanced by node 0.
+// One work-group per grid row along x: the instance and the (y, z) of the
+// row are wave-uniform, so no thread divides by the grid size.
 template <int DIM, bool KDE>
 __global__ void __launch_bounds__(256)
 k_pde(PdeParams q, const float *__restrict__ cin, float *__restrict__ cout,
       unsigned long long *__restrict__ Ssrc, unsigned long long *__restrict__ Supt, int last,
       uint32_t *__restrict__ flags, uint32_t *__restrict__ stepc) {
-    const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (stepc && l == 0) *stepc += 1u;
-    if (l >= q.n_nodes_total) return;
+    const uint32_t row = blockIdx.x;
+    if (stepc && row == 0 && threadIdx.x == 0) *stepc += 1u;
     const int n = q.grid_n;
-    const int64_t G = q.nodes_per_inst;
-    const int64_t k = l / G;
-    const int loc = (int)(l - k * G);
-    const int ic[3] = {loc % n, (loc / n) % n, DIM == 3 ? loc / (n * n) : 0};
+    const uint32_t rows_per_inst = DIM == 3 ? (uint32_t)n * (uint32_t)n : (uint32_t)n;
+    const uint32_t k = row / rows_per_inst;
+    const uint32_t rr = row - k * rows_per_inst;
+    const int iy = (int)(rr % (uint32_t)n), iz = DIM == 3 ? (int)(rr / (uint32_t)n) : 0;
+    const float *cb = cin + (int64_t)k * q.nodes_per_inst;
     uint32_t flag = 0;
-    if (KDE) {
-        const float2 su = reinterpret_cast<const float2 *>(Ssrc)[l];
-        cout[l] = pde_node_dens<DIM>(q, cin + k * G, ic, su.x, su.y, flag);
-        if (flag) atomicOr(flags, flag);
-        return;
-    }
-    const unsigned long long sS = Ssrc[l], sU = q.has_uptake ? Supt[l] : 0ull;
-    cout[l] = pde_node<DIM>(q, cin + k * G, ic, sS, sU, flag);
-    if (last) {
-        if (sS) Ssrc[l] = 0ull;
-        if (sU) Supt[l] = 0ull;
+    for (int ix = threadIdx.x; ix < n; ix += blockDim.x) {
+        const int64_t l = (int64_t)row * n + ix;
+        const int ic[3] = {ix, iy, iz};
+        if (KDE) {
+            const float2 su = reinterpret_cast<const float2 *>(Ssrc)[l];
+            cout[l] = pde_node_dens<DIM>(q, cb, ic, su.x, su.y, flag);
+            continue;
+        }
+        const unsigned long long sS = Ssrc[l], sU = q.has_uptake ? Supt[l] : 0ull;
+        cout[l] = pde_node<DIM>(q, cb, ic, sS, sU, flag);
+        if (last) {
+            if (sS) Ssrc[l] = 0ull;
+            if (sU) Supt[l] = 0ull;
+        }
     }
     if (flag) atomicOr(flags, flag);
 }
@@ -965,9 +972,14 @@ void launch_chem_inst(const StepParams &p, const PdeParams &q, const Buffers &b,
 #undef PC_CHEM
 }
 
+// k_pde launch shape: one work-group per x-row of the grid, its width
+// rounded up to whole waves (at most 256 threads; longer rows loop)
+static dim3 pde_grid(const PdeParams &q) { return dim3((uint32_t)(q.n_nodes_total / q.grid_n)); }
+static dim3 pde_block(const PdeParams &q) { return dim3(std::min(256, (q.grid_n + 63) / 64 * 64)); }
+
 void launch_pde(const PdeParams &q, const Buffers &b, int cin, int cout, int last,
                 hipStream_t s) {
-    const dim3 g(grid_for(q.n_nodes_total, 256)), t(256);
+    const dim3 g = pde_grid(q), t = pde_block(q);
     if (q.kde) {
         if (q.dim == 2)
             hipLaunchKernelGGL((k_pde<2, true>), g, t, 0, s, q, b.c[cin], b.c[cout], b.S_src,
@@ -989,7 +1001,7 @@ void launch_pde(const PdeParams &q, const Buffers &b, int cin, int cout, int las
 
 void launch_pde_ptr(const PdeParams &q, const float *cin, float *cout, unsigned long long *Ssrc,
                     unsigned long long *Supt, int last, uint32_t *flags, hipStream_t s) {
-    const dim3 g(grid_for(q.n_nodes_total, 256)), t(256);
+    const dim3 g = pde_grid(q), t = pde_block(q);
     if (q.dim == 2)
         hipLaunchKernelGGL((k_pde<2, false>), g, t, 0, s, q, cin, cout, Ssrc, Supt, last, flags,
                            nullptr);
