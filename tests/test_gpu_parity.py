@@ -93,6 +93,40 @@ def test_one_step_full_size(name):
     assert field_err(c, c1) <= 1e-5
 
 
+def test_ensemble_256_full_size_sampled_instances():
+    """The 256-instance batch at full size (1.41M agents) in the launch
+    configuration the benchmark's autotuner picks for it (bins at the contact
+    distance, 128-thread work-groups, deposit and PDE of each instance in one
+    work-group): neighbour sets at X^0 and one step, checked on the
+    smallest, the largest and two other instances, each run alone by the
+    oracle."""
+    w = W.workload(W.ENSEMBLE_256)
+    inp = W.make_inputs(w)
+    cut = max(s.diameter for s in w.species)
+    sim = make_sim(w, inp, bin_size=cut * 1.0002, block=128, deposit_mode=3)
+    assert sim.info["deposit_path"] == 3 and sim.info["stencil"] == 3
+    cnt, hsh = sim.debug_neighbours()
+    cnt = cnt.cpu().numpy().astype(np.uint32)
+    hsh = hsh.cpu().numpy().view(np.uint64)
+    sim.step(1)
+    sim.sync()
+    x = sim.positions().cpu().numpy()
+    c = sim.field().cpu().numpy()
+    sizes = np.array([ins.n_agents for ins in w.instances])
+    off = np.concatenate([[0], np.cumsum(sizes)])
+    G = w.grid_n ** w.dim
+    diam = [s.diameter for s in w.species]
+    for k in sorted({int(np.argmin(sizes)), int(np.argmax(sizes)), 0, 137}):
+        a, b = off[k], off[k + 1]
+        x0, s0 = inp["x0"][a:b], inp["species0"][a:b]
+        oc, oh = oracle.neighbours_f32(w.dim, w.periodic, w.L, x0, s0,
+                                       np.arange(b - a, dtype=np.uint32), diam)
+        assert np.array_equal(cnt[a:b], oc) and np.array_equal(hsh[a:b], oh), k
+        X1, c1, _ = oracle.run(oracle.params(w, k), x0, s0, inp["c0"][k * G:(k + 1) * G], 0, 1)
+        assert pos_err(x[a:b], X1, w.L, w.periodic) <= 1e-5, k
+        assert field_err(c[k * G:(k + 1) * G], c1) <= 1e-5, k
+
+
 def test_one_step_later_counter_3d_blobs():
     """Per-step parity at a later step counter and evolved state: the oracle
     evolves the state for 5 steps, both sides take step 5 -> 6 from it."""
