@@ -18,6 +18,7 @@ Function map (all arrays are numpy, float64 unless stated):
 * :func:`pde`               n_sub forward-Euler updates of the chemical
 * :func:`pde_density`       the same updates from densities (kernel density deposit)
 * :func:`deposit_kde`       Gaussian kernel density of source / uptake at the nodes
+  (:func:`deposit_kde_at` at chosen nodes only)
 * :func:`react`             type switching of one step (eq. Chemo_reactions)
 * :func:`hs_correct`        hard-sphere overlap correction
 * :func:`step` / :func:`run` whole time steps of one instance
@@ -110,6 +111,7 @@ def lib():
             "orc_pde": ([P, vp, vp, vp], None),
             "orc_pde_density": ([P, vp, vp, vp], None),
             "orc_deposit_kde": ([P, i64, vp, vp, vp, vp], None),
+            "orc_deposit_kde_at": ([P, i64, vp, vp, i64, vp, vp, vp], None),
             "orc_hs_correct": ([P, i64, vp, vp], None),
             "orc_react": ([P, i64, vp, vp, vp, vp, C.c_uint32, vp], None),
             "orc_step": ([P, i64, vp, vp, vp, vp, vp], None),
@@ -287,6 +289,19 @@ def deposit_kde(p: Params, X: np.ndarray, sp: np.ndarray):
     sig = np.empty(n_nodes(p), np.float64)
     ups = np.empty(n_nodes(p), np.float64)
     lib().orc_deposit_kde(C.byref(p), len(X), _ptr(X), _ptr(sp), _ptr(sig), _ptr(ups))
+    return sig, ups
+
+
+def deposit_kde_at(p: Params, X: np.ndarray, sp: np.ndarray, nodes: np.ndarray):
+    """The kernel density of source and uptake at the given flat node indices
+    only (same definition as :func:`deposit_kde`): (sigma, upsilon)."""
+    X = _c(X, np.float64)
+    sp = _c(sp, np.uint8)
+    nodes = _c(nodes, np.int64)
+    sig = np.empty(len(nodes), np.float64)
+    ups = np.empty(len(nodes), np.float64)
+    lib().orc_deposit_kde_at(C.byref(p), len(X), _ptr(X), _ptr(sp), len(nodes), _ptr(nodes),
+                             _ptr(sig), _ptr(ups))
     return sig, ups
 
 

@@ -555,34 +555,44 @@ void orc_deposit(const orc_params *p, int64_t n, const double *X, const uint8_t 
  * rho_s and upsilon = sum_s uptake_s rho_s are densities (no control
  * volume).  Readings: the 2D kernel of the paper taken to dim dimensions;
  * a per-species bandwidth; the truncation radius is a parameter. */
+static void orc_kde_node(const orc_params *p, int64_t n, const double *X, const uint8_t *sp,
+                         int64_t l, double *sigma, double *ups) {
+    const double h = orc_h(p);
+    const double PI = 3.14159265358979323846;
+    int ci[3];
+    orc_unflat(p, l, ci);
+    double s_acc = 0.0, u_acc = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        const int s = sp[i];
+        const double eps = p->diam[s];
+        double r2 = 0.0;
+        for (int a = 0; a < p->dim; ++a) {
+            double dx = ci[a] * h - X[i * p->dim + a];
+            if (p->periodic) dx = orc_min_image(dx, p->L);
+            r2 += dx * dx;
+        }
+        const double R = p->kde_radius * eps;
+        if (!(r2 < R * R)) continue;
+        const double K = pow(2.0 * PI * eps * eps, -0.5 * p->dim) * exp(-r2 / (2.0 * eps * eps));
+        s_acc += p->source[s] * K;
+        u_acc += p->uptake[s] * K;
+    }
+    *sigma = s_acc;
+    *ups = u_acc;
+}
+
 void orc_deposit_kde(const orc_params *p, int64_t n, const double *X, const uint8_t *sp,
                      double *sigma, double *ups) {
     const int64_t G = orc_nodes(p);
-    const double h = orc_h(p);
-    const double PI = 3.14159265358979323846;
 #pragma omp parallel for
-    for (int64_t l = 0; l < G; ++l) {
-        int ci[3];
-        orc_unflat(p, l, ci);
-        double s_acc = 0.0, u_acc = 0.0;
-        for (int64_t i = 0; i < n; ++i) {
-            const int s = sp[i];
-            const double eps = p->diam[s];
-            double r2 = 0.0;
-            for (int a = 0; a < p->dim; ++a) {
-                double dx = ci[a] * h - X[i * p->dim + a];
-                if (p->periodic) dx = orc_min_image(dx, p->L);
-                r2 += dx * dx;
-            }
-            const double R = p->kde_radius * eps;
-            if (!(r2 < R * R)) continue;
-            const double K = pow(2.0 * PI * eps * eps, -0.5 * p->dim) * exp(-r2 / (2.0 * eps * eps));
-            s_acc += p->source[s] * K;
-            u_acc += p->uptake[s] * K;
-        }
-        sigma[l] = s_acc;
-        ups[l] = u_acc;
-    }
+    for (int64_t l = 0; l < G; ++l) orc_kde_node(p, n, X, sp, l, &sigma[l], &ups[l]);
+}
+
+/* The same densities at m given nodes only (sampled checks of large grids). */
+void orc_deposit_kde_at(const orc_params *p, int64_t n, const double *X, const uint8_t *sp,
+                        int64_t m, const int64_t *nodes, double *sigma, double *ups) {
+#pragma omp parallel for
+    for (int64_t k = 0; k < m; ++k) orc_kde_node(p, n, X, sp, nodes[k], &sigma[k], &ups[k]);
 }
 
 /* Control volume of node l in units of h^dim: 1, or 1/2 per wall axis. */

@@ -65,6 +65,58 @@ def test_one_step_matches_oracle(name, n, g, kappa):
     assert _within(c.cpu().numpy().astype(np.float64), clo, chi_, 1e-5 * scale)
 
 
+def test_one_step_full_size_walls_100k():
+    """The full 100k walls workload with the kernel density deposit as the
+    benchmark runs it (radius 3 bandwidths, default launch)."""
+    w = _kde(W.workload(W.WALLS_100K), 3.0)
+    inp = W.make_inputs(w)
+    sim = make_sim(w, inp)
+    sim.step(1)
+    x, c, _ = sim.get_state()
+    (Xlo, clo), (Xhi, chi_) = _bracket(w, inp, 1)
+    assert pos_err(x.cpu().numpy(), Xlo, w.L, w.periodic) <= 1e-5
+    scale = max(np.abs(clo).max(), 1e-30)
+    assert _within(c.cpu().numpy().astype(np.float64), clo, chi_, 1e-5 * scale)
+
+
+def test_one_step_full_size_3d_sampled_nodes():
+    """The full 1M-agent 3D workload with the kernel density deposit as the
+    benchmark runs it.  The oracle's density is a sum over every agent at
+    every node (2e12 terms here), so it is taken at 400 nodes: 300 at the
+    cells of random agents and 100 anywhere, from the device's own new
+    positions (in the blob cores a 1e-7 position difference would move the
+    density by more than the bar).  With one PDE substep a node's new value
+    needs only its own density and the old field, so the oracle's PDE with
+    the densities of the other nodes zeroed is exact at those nodes.
+    Positions: the oracle's step with the particle-in-cell deposit (the
+    update does not depend on the deposit kernel)."""
+    w = _kde(W.workload(W.BLOBS_1M), 3.0)
+    inp = W.make_inputs(w)
+    p = oracle.params(w)
+    assert p.n_sub == 1
+    sim = make_sim(w, inp)
+    sim.step(1)
+    x, c, _ = sim.get_state()
+    x, c = x.cpu().numpy(), c.cpu().numpy()
+    Xo, _ = oracle.run_workload(dataclasses.replace(w, deposit_kernel=0), inp, 1)
+    assert pos_err(x, Xo, w.L, w.periodic) <= 1e-5
+    rng = np.random.default_rng(11)
+    n = w.grid_n
+    cells = np.floor(Xo[rng.integers(0, w.n_total, 300)] * n).astype(np.int64) % n
+    nodes = np.unique(np.concatenate([cells[:, 0] + n * cells[:, 1] + n * n * cells[:, 2],
+                                      rng.integers(0, w.n_nodes, 100)]))
+    refs = []
+    for kappa in (3.0 * (1 - 1e-5), 3.0 * (1 + 1e-5)):
+        pk = oracle.params(dataclasses.replace(w, kde_radius=kappa))
+        sig, ups = oracle.deposit_kde_at(pk, x.astype(np.float64), inp["species0"], nodes)
+        sf, uf = np.zeros(w.n_nodes), np.zeros(w.n_nodes)
+        sf[nodes], uf[nodes] = sig, ups
+        refs.append(oracle.pde_density(pk, inp["c0"], sf, uf)[nodes])
+        assert (sig > 0).sum() >= 250
+    scale = max(np.abs(refs[0]).max(), np.abs(inp["c0"]).max())
+    assert _within(c[nodes].astype(np.float64), refs[0], refs[1], 1e-5 * scale)
+
+
 @pytest.mark.parametrize("name,n,g,steps", [(W.PERIODIC_1K, 2000, 37, 10),
                                             (W.WALLS_100K, 8000, 65, 6)])
 def test_trajectory_matches_oracle(name, n, g, steps):

@@ -16,7 +16,8 @@ import pytest
 
 import oracle
 import workloads as W
-from gpu_helpers import field_err, make_sim, oracle_forces, pos_err
+from gpu_helpers import (field_err, field_from_positions, field_ok, make_sim, oracle_forces,
+                         pos_err)
 
 pytestmark = pytest.mark.gpu
 
@@ -69,6 +70,28 @@ def test_one_step(name, n, g, kw):
     Xo, co = oracle.run_workload(w, inp, 1)
     assert pos_err(x.cpu().numpy(), Xo, w.L, w.periodic) <= 1e-5
     assert field_err(c.cpu().numpy(), co) <= 1e-5
+
+
+@pytest.mark.parametrize("name", [W.WALLS_100K, W.BLOBS_1M])
+@pytest.mark.parametrize("kw", [dict(potential=1, pot_range=3.0, k=1.0), dict(tamed=True),
+                                dict(potential=2)], ids=["exponential", "tamed", "hard_spheres"])
+def test_one_step_full_size(name, kw):
+    """The full 100k walls and 1M 3D workloads with each variant as the
+    benchmark runs it (default launch).  Positions against the oracle's
+    step; the field against the oracle's deposit and PDE at the device's own
+    new positions (on a 512^2 grid one agent's deposit weighs enough for a
+    position difference within the bar to show in the field), within 1e-5
+    max|c| plus the float32 rounding bound of the deposit weights."""
+    w = dataclasses.replace(W.workload(name), **kw)
+    inp = W.make_inputs(w)
+    sim = make_sim(w, inp)
+    sim.step(1)
+    x, c, _ = sim.get_state()
+    x = x.cpu().numpy()
+    Xo, _ = oracle.run_workload(w, inp, 1)
+    assert pos_err(x, Xo, w.L, w.periodic) <= 1e-5
+    c_ref = field_from_positions(w, inp["c0"], x, inp["species0"])
+    assert field_ok(c.cpu().numpy(), c_ref, w, x, inp["species0"])
 
 
 @pytest.mark.parametrize("name,n,g,kw,steps", [

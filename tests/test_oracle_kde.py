@@ -14,6 +14,7 @@ bandwidth eps = the species' diameter, truncated at kde_radius * eps.
 * the peak at an agent on a node is (2 pi eps^2)^(-d/2) source;
 * a whole step with D = chi = 0 uses the kernel density at X^{n+1}.
 """
+import dataclasses
 import math
 
 import numpy as np
@@ -120,3 +121,17 @@ def test_step_uses_kernel_density_at_new_positions(oracle_lib):
     p.deposit_kernel = 0
     _, c2, _ = oracle.run(p, X0, np.zeros(1, np.uint8), c0, 0, 1)
     assert np.abs(c2 - c1).max() > 1e-4
+
+
+def test_density_at_chosen_nodes_equals_the_full_grid(oracle_lib):
+    """deposit_kde_at evaluates the same definition at chosen nodes: equal,
+    bit for bit, to the full evaluation at every node of a small 3D case."""
+    w = dataclasses.replace(W.scaled(W.workload(W.BLOBS_1M), n_agents=3000, grid_n=16),
+                            deposit_kernel=1, kde_radius=3.0)
+    inp = W.make_inputs(w)
+    p = oracle.params(w)
+    sig, ups = oracle.deposit_kde(p, inp["x0"], inp["species0"])
+    nodes = np.random.default_rng(3).permutation(w.n_nodes)
+    s2, u2 = oracle.deposit_kde_at(p, inp["x0"], inp["species0"], nodes)
+    assert (sig > 0).sum() > 50
+    assert np.array_equal(sig[nodes], s2) and np.array_equal(ups[nodes], u2)
