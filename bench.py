@@ -410,8 +410,8 @@ def main() -> int:
                     help="run only this extra leg and print its JSON line")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(run with --gpus 1)", file=sys.stderr)
+        print("bench.py measures one GPU only: the library steps a batch on one device and "
+              "has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
         return 2
 
     import numpy as np
