@@ -133,6 +133,39 @@ def test_ensemble_256_full_size_sampled_instances():
         assert field_err(c[k * G:(k + 1) * G], c1) <= 1e-5, k
 
 
+@pytest.mark.parametrize("n0", [50, 199])
+def test_one_step_3d_blobs_from_clustered_gpu_state(n0):
+    """The full 1M-agent 3D run in the benchmark's launch, stepped on the
+    device to step n0 (the blobs have collapsed: ~345 neighbours per agent
+    at step 75, dense bins on the wave-uniform path).  From the device's
+    float32 state at n0: neighbour sets bit-exact, and one more step within
+    the per-step bars of the oracle's step from that state with the same
+    counter."""
+    w = W.workload(W.BLOBS_1M)
+    inp = W.make_inputs(w)
+    sim = make_sim(w, inp)
+    sim.use_graph(True)
+    sim.step(n0)
+    sim.sync()
+    x, c, st = sim.get_state()
+    assert st == n0
+    x, c = x.cpu().numpy(), c.cpu().numpy()
+    cnt, hsh = sim.debug_neighbours()
+    sn = dict(inp, x0=x, c0=c)
+    ocnt, ohsh = oracle_neighbours(w, sn)
+    assert ocnt.mean() > 50
+    assert np.array_equal(cnt.cpu().numpy().astype(np.uint32), ocnt)
+    assert np.array_equal(hsh.cpu().numpy().view(np.uint64), ohsh)
+    sim.step(1)
+    sim.sync()
+    x1 = sim.positions().cpu().numpy()
+    c1 = sim.field().cpu().numpy()
+    Xo, co = oracle_steps(w, sn, 1, step0=n0)
+    assert pos_err(x1, Xo, w.L, w.periodic) <= 1e-5
+    assert field_ok(c1, co, w, x1, inp["species0"])
+    assert field_ok(c1, field_from_positions(w, c, x1, inp["species0"]), w, x1, inp["species0"])
+
+
 def test_one_step_later_counter_3d_blobs():
     """Per-step parity at a later step counter and evolved state: the oracle
     evolves the state for 5 steps, both sides take step 5 -> 6 from it."""
