@@ -103,9 +103,9 @@ def test_ensemble_256_full_size_sampled_instances():
     """The 256-instance batch at full size (1.41M agents) in the launch
     configuration the benchmark's autotuner picks for it (bins at the contact
     distance, 128-thread work-groups, deposit and PDE of each instance in one
-    work-group): neighbour sets at X^0 and one step, checked on the
-    smallest, the largest and two other instances, each run alone by the
-    oracle."""
+    work-group): neighbour sets at X^0 and one step, then one step from the
+    device's state at step 250, checked on the smallest, the largest and two
+    other instances, each run alone by the oracle."""
     w = W.workload(W.ENSEMBLE_256)
     inp = W.make_inputs(w)
     cut = max(s.diameter for s in w.species)
@@ -129,6 +129,24 @@ def test_ensemble_256_full_size_sampled_instances():
                                        np.arange(b - a, dtype=np.uint32), diam)
         assert np.array_equal(cnt[a:b], oc) and np.array_equal(hsh[a:b], oh), k
         X1, c1, _ = oracle.run(oracle.params(w, k), x0, s0, inp["c0"][k * G:(k + 1) * G], 0, 1)
+        assert pos_err(x[a:b], X1, w.L, w.periodic) <= 1e-5, k
+        assert field_err(c[k * G:(k + 1) * G], c1) <= 1e-5, k
+    # half-way through the benchmark's 500 steps (graph replay), one more
+    # step from the device's own state
+    sim.use_graph(True)
+    sim.step(249)
+    sim.sync()
+    xs, cs, st = sim.get_state()
+    assert st == 250
+    xs, cs = xs.cpu().numpy(), cs.cpu().numpy()
+    sim.step(1)
+    sim.sync()
+    x = sim.positions().cpu().numpy()
+    c = sim.field().cpu().numpy()
+    for k in sorted({int(np.argmin(sizes)), int(np.argmax(sizes)), 0, 137}):
+        a, b = off[k], off[k + 1]
+        X1, c1, _ = oracle.run(oracle.params(w, k), xs[a:b], inp["species0"][a:b],
+                               cs[k * G:(k + 1) * G], 250, 1)
         assert pos_err(x[a:b], X1, w.L, w.periodic) <= 1e-5, k
         assert field_err(c[k * G:(k + 1) * G], c1) <= 1e-5, k
 
