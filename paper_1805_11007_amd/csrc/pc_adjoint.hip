@@ -156,10 +156,45 @@ k_adj_pde(PdeParams q, const float *__restrict__ mu_in, float *__restrict__ mu_o
     }
 }
 
-// Parameter derivative accumulation: sum over the wave when all its lanes
-// belong to one instance, else per lane.
+// Parameter derivative accumulation: sum over the work-group (256 threads)
+// when all its agents belong to one instance, so that each sum takes one
+// device atomic per work-group (the three sums are single addresses, where
+// atomics queue); else over the wave when its lanes share an instance, else
+// per lane.  Every thread of the work-group calls it (idle ones with zeros);
+// thread 0 always holds an agent.
 __device__ __forceinline__ void add_dtheta(double *__restrict__ dth, uint32_t inst, bool valid,
                                            double v0, double v1, double v2) {
+    __shared__ double part[4][3];
+    __shared__ uint32_t inst0;
+    if (threadIdx.x == 0) inst0 = inst;
+    __syncthreads();
+    const uint32_t bfirst = inst0;
+    if (__syncthreads_and(!valid || inst == bfirst)) {
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) {
+            v0 += __shfl_xor(v0, d, 64);
+            v1 += __shfl_xor(v1, d, 64);
+            v2 += __shfl_xor(v2, d, 64);
+        }
+        if ((threadIdx.x & 63) == 0) {
+            part[threadIdx.x >> 6][0] = v0;
+            part[threadIdx.x >> 6][1] = v1;
+            part[threadIdx.x >> 6][2] = v2;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+            for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+                s0 += part[w][0];
+                s1 += part[w][1];
+                s2 += part[w][2];
+            }
+            unsafeAtomicAdd(dth + 3 * bfirst + 0, s0);
+            unsafeAtomicAdd(dth + 3 * bfirst + 1, s1);
+            unsafeAtomicAdd(dth + 3 * bfirst + 2, s2);
+        }
+        return;
+    }
     const uint32_t first = __shfl(inst, 0, 64);
     const bool uniform = __all(!valid || inst == first);
     if (uniform) {
