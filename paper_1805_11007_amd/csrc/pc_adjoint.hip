@@ -293,8 +293,9 @@ k_adj_agent(StepParams p, AdjArgs A, const InstInfo *__restrict__ inst,
             const float y = pc[a] + p.dt * (fv.F[a] + chi * Ig[a]) + amp * xi[a];
             const bool refl = !p.periodic && (y < 0.0f || y > p.L);
             ly[a] = refl ? -lam[a] : lam[a];
-            A.lamY[row * DIM + a] = ly[a];
         }
+        // stored in the cell-sorted order, where the pair walk reads it
+        A.lamY[i] = make_float4(ly[0], ly[1], ly[2], 0.0f);
         // identity and drift terms of dL/dX^n
 #pragma unroll
         for (int b = 0; b < DIM; ++b) {
@@ -335,17 +336,14 @@ struct AdjPairVisitor {
     float k;
     float li[3];
     float acc[3];
-    const float *lamY;
-    const uint32_t *Is;
-    size_t base;
-    int dim;
+    const float4 *lamY;  // cell-sorted, indexed like the candidates
     __device__ __forceinline__ void operator()(uint32_t j, float dx, float dy, float dz, float r2,
                                                float c2, float dd, int) {
         if (r2 < c2 && r2 > 0.0f) {
-            const size_t rj = (base + Is[j]) * dim;
-            const float v0 = li[0] - lamY[rj + 0];
-            const float v1 = li[1] - lamY[rj + 1];
-            const float v2 = dim == 3 ? li[2] - lamY[rj + 2] : 0.0f;
+            const float4 lj = lamY[j];
+            const float v0 = li[0] - lj.x;
+            const float v1 = li[1] - lj.y;
+            const float v2 = li[2] - lj.z;
             const float rinv = rsqrtf(r2);
             const float r = r2 * rinv;
             const float ux = dx * rinv, uy = dy * rinv, uz = dz * rinv;
@@ -362,7 +360,7 @@ template <int DIM, int NS, int STENCIL>
 __global__ void __launch_bounds__(256)
 k_adj_pair(StepParams p, const InstInfo *__restrict__ inst, const float4 *__restrict__ Ps,
            const uint32_t *__restrict__ Is, const uint32_t *__restrict__ start,
-           const float *__restrict__ lamY, float *__restrict__ lamX_out) {
+           const float4 *__restrict__ lamY, float *__restrict__ lamX_out) {
     __shared__ SpTab tab;
     if (NS == 0) {
         load_tab(p, tab);
@@ -377,13 +375,11 @@ k_adj_pair(StepParams p, const InstInfo *__restrict__ inst, const float4 *__rest
     AdjPairVisitor v;
     v.k = p.k;
     v.lamY = lamY;
-    v.Is = Is;
-    v.base = ii.agent_base;
-    v.dim = DIM;
-    for (int a = 0; a < 3; ++a) {
-        v.li[a] = a < DIM ? lamY[row * DIM + a] : 0.0f;
-        v.acc[a] = 0.0f;
-    }
+    const float4 l4 = lamY[i];
+    v.li[0] = l4.x;
+    v.li[1] = l4.y;
+    v.li[2] = l4.z;
+    v.acc[0] = v.acc[1] = v.acc[2] = 0.0f;
     pair_loop<DIM, NS, STENCIL>(p, tab, Ps, start, ii.bin_base, pi, si, v);
 #pragma unroll
     for (int a = 0; a < DIM; ++a) lamX_out[row * DIM + a] += p.dt * v.acc[a];
@@ -590,7 +586,7 @@ static void adj_agent(const StepParams &p, const AdjArgs &A, const Buffers &b, i
 }
 
 template <int DIM, int NS, int ST>
-static void adj_pair(const StepParams &p, const Buffers &b, int src, const float *lamY,
+static void adj_pair(const StepParams &p, const Buffers &b, int src, const float4 *lamY,
                      float *lamX_out, hipStream_t s) {
     hipLaunchKernelGGL((k_adj_pair<DIM, NS, ST>), dim3(gridn(p.n_total, 256)), dim3(256), 0, s, p,
                        b.inst, b.P[src], b.I[src], b.start, lamY, lamX_out);
@@ -627,7 +623,7 @@ void launch_adj_agent(const StepParams &p, const AdjArgs &A, const Buffers &b, i
     PC_ADJ_DISPATCH(adj_agent, p, A, b, src, c, s);
 }
 
-void launch_adj_pair(const StepParams &p, const Buffers &b, int src, const float *lamY,
+void launch_adj_pair(const StepParams &p, const Buffers &b, int src, const float4 *lamY,
                      float *lamX_out, hipStream_t s) {
     PC_ADJ_DISPATCH(adj_pair, p, b, src, lamY, lamX_out, s);
 }

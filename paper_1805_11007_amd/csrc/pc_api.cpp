@@ -223,7 +223,7 @@ Layout layout(const Derived &d, int seg_steps) {
         L.seg_c = take(cur, 4 * (size_t)seg_steps * G);
         L.lamX[0] = take(cur, 4 * XD);
         L.lamX[1] = take(cur, 4 * XD);
-        L.lamY = take(cur, 4 * XD);
+        L.lamY = take(cur, 16 * N);
         L.lamC[0] = take(cur, 4 * G);
         L.lamC[1] = take(cur, 4 * G);
         L.aSrc = take(cur, 4 * G);
@@ -386,7 +386,7 @@ static void carve(pc_sim *s, char *ws) {
         b.seg_c = (float *)(ws + L.seg_c);
         b.lamX[0] = (float *)(ws + L.lamX[0]);
         b.lamX[1] = (float *)(ws + L.lamX[1]);
-        b.lamY = (float *)(ws + L.lamY);
+        b.lamY = (float4 *)(ws + L.lamY);
         b.lamC[0] = (float *)(ws + L.lamC[0]);
         b.lamC[1] = (float *)(ws + L.lamC[1]);
         b.aSrc = (float *)(ws + L.aSrc);

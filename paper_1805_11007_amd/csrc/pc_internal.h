@@ -104,7 +104,7 @@ struct Buffers {
     float *seg_x;          // (seg_steps + 1) x n_total x dim, id order
     float *seg_c;          // seg_steps x nodes_total
     float *lamX[2];        // n_total x dim
-    float *lamY;           // n_total x dim
+    float4 *lamY;          // n_total, cell-sorted order of the step
     float *lamC[2];        // nodes_total
     float *aSrc, *aUpt;    // dL/dS at nodes
     float *lamG;           // dim x nodes_total
@@ -116,7 +116,7 @@ struct AdjArgs {
     const float *xnext;    // X^{n+1}, id order, n_total x dim
     const float *lamX_in;  // dL/dX^{n+1}
     const float *aSrc, *aUpt;  // dL/dS at nodes
-    float *lamY;           // dL/dy (pre-boundary), id order
+    float4 *lamY;          // dL/dy (pre-boundary), cell-sorted order (the pair walk's)
     float *lamX_out;       // dL/dX^n (drift and identity terms; pair term added later)
     float *lamG;           // dL/d(node gradient), dim x nodes_total
     double *dth;           // 3 per instance: d/d scale of chi, k, D
@@ -172,7 +172,7 @@ void launch_adj_pde(const PdeParams &q, const float *mu_in, float *mu_out, const
                     hipStream_t s);
 void launch_adj_agent(const StepParams &p, const AdjArgs &A, const Buffers &b, int src,
                       const float *c, hipStream_t s);
-void launch_adj_pair(const StepParams &p, const Buffers &b, int src, const float *lamY,
+void launch_adj_pair(const StepParams &p, const Buffers &b, int src, const float4 *lamY,
                      float *lamX_out, hipStream_t s);
 void launch_adj_grad(const PdeParams &q, float inv_2h, const float *mu0, const float *lamG,
                      float *lamC_out, hipStream_t s);
