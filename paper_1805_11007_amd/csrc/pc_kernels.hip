@@ -186,16 +186,33 @@ __global__ void __launch_bounds__(1024) k_scan_tiles(uint32_t *__restrict__ tile
     }
 }
 
+// Bin starts of one tile from its counts and the tile's prefix.  A tile
+// holding no agent (its prefix equals the next one; the last tile ends at
+// n_agents) has only zero counts: its starts are all the prefix, written
+// without reading or clearing the counts.
 __global__ void __launch_bounds__(256) k_scan_apply(uint32_t *__restrict__ count, int64_t n,
                                                     const uint32_t *__restrict__ tile_sum,
-                                                    uint32_t *__restrict__ start) {
+                                                    uint32_t *__restrict__ start, int T,
+                                                    uint32_t n_agents) {
     __shared__ uint32_t lds[4];
     const int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x * 8;
+    const uint32_t pre = tile_sum[blockIdx.x];
+    const uint32_t nxt = (int)blockIdx.x + 1 < T ? tile_sum[blockIdx.x + 1] : n_agents;
+    if (pre == nxt) {
+        if (base + 8 <= n) {
+            uint4 *st4 = reinterpret_cast<uint4 *>(start + base);
+            st4[0] = st4[1] = make_uint4(pre, pre, pre, pre);
+        } else {
+            for (int k = 0; k < 8; ++k)
+                if (base + k < n) start[base + k] = pre;
+        }
+        return;
+    }
     uint32_t v[8];
     load8(count, base, n, v);
     const uint32_t s = ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]));
     uint32_t tot;
-    uint32_t run = block_exscan256(s, lds, tot) + tile_sum[blockIdx.x];
+    uint32_t run = block_exscan256(s, lds, tot) + pre;
     uint32_t o[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
@@ -786,7 +803,8 @@ void launch_scan(const StepParams &p, const Buffers &b, int64_t n_bins_total, hi
     if (!p.tile_totals)
         hipLaunchKernelGGL(k_tile_sums, dim3(T), dim3(256), 0, s, b.count, n, b.tile_cnt);
     hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, s, b.tile_cnt, b.tile_sum, T);
-    hipLaunchKernelGGL(k_scan_apply, dim3(T), dim3(256), 0, s, b.count, n, b.tile_sum, b.start);
+    hipLaunchKernelGGL(k_scan_apply, dim3(T), dim3(256), 0, s, b.count, n, b.tile_sum, b.start, T,
+                       (uint32_t)p.n_total);
 }
 
 void launch_scatter(const StepParams &p, const Buffers &b, int src, int dst, int block,
