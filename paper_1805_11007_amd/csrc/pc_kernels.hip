@@ -962,7 +962,10 @@ template <int DIM, int NS, bool UPT>
 static void chem(const StepParams &p, const PdeParams &q, const Buffers &b, int src, int cur,
                  int n_sub, hipStream_t s) {
     const size_t lds = 8 * (size_t)q.nodes_per_inst * (UPT ? 2 : 1);
-    hipLaunchKernelGGL((k_chem_inst<DIM, NS, UPT>), dim3(p.n_inst), dim3(1024), lds, s, p, q,
+    // small grids (the 52^2 grids of the Fig. 1 ensemble) run faster with
+    // 512 threads, larger ones (128^2) with 1024
+    const int threads = q.nodes_per_inst <= 4096 ? 512 : 1024;
+    hipLaunchKernelGGL((k_chem_inst<DIM, NS, UPT>), dim3(p.n_inst), dim3(threads), lds, s, p, q,
                        b.inst, b.P[src], b.c[0], b.c[1], cur, n_sub, b.flags, b.step);
 }
 
