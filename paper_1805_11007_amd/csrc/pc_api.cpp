@@ -46,6 +46,10 @@ struct Derived {
 // A species switches when react_to >= 0 and one of its rates is > 0.
 // Agents per chemical node below which the deposit skips LDS aggregation.
 constexpr double kDepositSparse = 0.2;
+// Agents below which it skips it too: the aggregating deposit runs 1024
+// agents per work-group and needs about one work-group per compute unit
+// (measured: direct atomics are faster on 100k, 50k and 1k agents).
+constexpr int64_t kDepositAggMinAgents = 256 * 1024;
 // Instances from which a batch whose per-instance deposit sums fit in LDS
 // runs deposit + PDE as one work-group per instance.
 constexpr int kFusedMinInstances = 64;
@@ -335,11 +339,15 @@ static void fill_params(pc_sim *s) {
     p.potential = d.potential;
     p.tamed = d.tamed;
     p.has_react = d.has_react;
-    // LDS aggregation pays where a work-group's agents share nodes; with
-    // fewer agents than kDepositSparse per node most corners are distinct
+    // LDS aggregation pays where a work-group's agents share nodes and the
+    // work-groups fill the chip; with fewer agents than kDepositSparse per
+    // node most corners are distinct
     p.deposit_agg = c.deposit_mode == 1 ? 1
                     : c.deposit_mode == 2 ? 0
-                    : ((double)d.n_total >= kDepositSparse * (double)d.nodes_total ? 1 : 0);
+                    : (d.n_total >= kDepositAggMinAgents &&
+                               (double)d.n_total >= kDepositSparse * (double)d.nodes_total
+                           ? 1
+                           : 0);
     PdeParams &q = s->pp;
     memset(&q, 0, sizeof(q));
     q.dim = d.dim;
