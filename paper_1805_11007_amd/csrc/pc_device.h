@@ -282,7 +282,7 @@ struct DebugVisitor {
 // Along x, neighbouring bins are adjacent in memory, so each (y, z) row of
 // the stencil is one contiguous agent range (two at the seam).
 // widest run of x bins a wave may span on the wave-uniform pair path
-constexpr int kSpan = 3;
+constexpr int kSpan = 5;
 
 template <int DIM, int NS, int STENCIL, class V>
 __device__ __forceinline__ void pair_loop(const StepParams &p, const SpTab &tab,
