@@ -43,12 +43,12 @@ FLOP_PER_PAIR, FLOP_PER_AGENT = 18.0, 140.0
 # rocprofv3 FETCH_SIZE and WRITE_SIZE runs (each scaled by the same counter's
 # reading for a plain device copy); valid only for the kernel sources they
 # were taken with, identified by a hash of those files.
-UPDATE_TRAFFIC_BYTES = 106.0e6
+UPDATE_TRAFFIC_BYTES = 106.1e6
 # SQ_INSTS_VALU of the same kernel over the chip's issue capacity in its
 # GRBM_GUI_ACTIVE cycles (one wave64 VALU instruction per SIMD per 4 cycles)
-UPDATE_VALU_ISSUE = 0.59
+UPDATE_VALU_ISSUE = 0.60
 UPDATE_TRAFFIC_SOURCES = ("pc_internal.h", "pc_device.h", "pc_kernels.hip")
-UPDATE_TRAFFIC_SHA = "9d5ac479c5e451e8"
+UPDATE_TRAFFIC_SHA = "eec133921cf7a0a3"
 
 
 def update_counters_valid(workload: str) -> bool:
