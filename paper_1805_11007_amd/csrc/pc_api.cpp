@@ -212,7 +212,7 @@ Layout layout(const Derived &d, int seg_steps) {
     L.count = take(cur, 4 * ((size_t)d.bins_total + 1));
     L.start = take(cur, 4 * ((size_t)d.bins_total + 1));
     L.tile_sum = take(cur, 4 * (((size_t)d.bins_total + 1 + kScanTile - 1) / kScanTile));
-    L.tile_cnt = take(cur, 4 * (((size_t)d.bins_total + 1 + kScanTile - 1) / kScanTile));
+    L.tile_cnt = take(cur, 4 * kTileReps * (((size_t)d.bins_total + kScanTile) / kScanTile));
     L.c[0] = take(cur, 4 * (size_t)d.nodes_total);
     L.c[1] = take(cur, 4 * (size_t)d.nodes_total);
     L.S_src = take(cur, 8 * (size_t)d.nodes_total);
@@ -296,9 +296,14 @@ static void fill_params(pc_sim *s) {
     p.dt = (float)c.dt;
     p.k = (float)c.k_rep;
     // Tile totals gathered by the histogram spare the scan a pass over every
-    // bin count, which pays where bins far outnumber agents; with fewer bins
-    // per agent the waves would queue on few tile counters.
-    p.tile_totals = d.bins_total + 1 >= 8 * d.n_total ? 1 : 0;
+    // bin count.  With many tiles each has one counter, used where bins far
+    // outnumber agents (else waves would queue on few counters); a grid of
+    // few tiles has kTileReps counters per tile, one picked by each wave.
+    {
+        const int64_t T = (d.bins_total + kScanTile) / kScanTile;
+        p.tile_reps = T <= kTileRepsMaxTiles ? kTileReps : 1;
+        p.tile_totals = (T <= kTileRepsMaxTiles || d.bins_total + 1 >= 8 * d.n_total) ? 1 : 0;
+    }
     // the factor k (d / r - 1) reaches this only for r < 1e-10 d; it keeps
     // the factor finite at r = 0, where it multiplies dx = 0
     p.fcap = (float)std::min(1e10 * c.k_rep * d.contact_max, 1e38);
@@ -408,7 +413,8 @@ static void carve(pc_sim *s, char *ws) {
 // Clear a histogram that no scan consumed: the bin counts and the tile totals.
 static void zero_counts(pc_sim *s, hipStream_t st) {
     launch_zero_u32(s->b.count, s->d.bins_total + 1, st);
-    launch_zero_u32(s->b.tile_cnt, (s->d.bins_total + kScanTile) / kScanTile, st);
+    launch_zero_u32(s->b.tile_cnt, (int64_t)kTileReps * ((s->d.bins_total + kScanTile) / kScanTile),
+                    st);
 }
 
 // Cell-sort the current positions (scan of the counts, scatter, optional
@@ -566,7 +572,8 @@ static int common_create(const pc_config *cfg, const pc_species_t *species, int 
     CK(hipMemcpyAsync(s->b.inst, s->inst_host.data(), sizeof(InstInfo) * n_inst,
                       hipMemcpyHostToDevice, st));
     CK(hipMemsetAsync(s->b.count, 0, 4 * ((size_t)d.bins_total + 1), st));
-    CK(hipMemsetAsync(s->b.tile_cnt, 0, 4 * (((size_t)d.bins_total + kScanTile) / kScanTile), st));
+    CK(hipMemsetAsync(s->b.tile_cnt, 0,
+                      4 * kTileReps * (((size_t)d.bins_total + kScanTile) / kScanTile), st));
     CK(hipMemsetAsync(s->b.S_src, 0, 8 * (size_t)d.nodes_total, st));
     if (d.has_uptake) CK(hipMemsetAsync(s->b.S_upt, 0, 8 * (size_t)d.nodes_total, st));
     CK(hipMemsetAsync(s->b.step, 0, 4, st));

@@ -11,6 +11,8 @@ constexpr int kMaxSpecies = 8;
 constexpr int kScanTile = 2048;   // bins per scan tile (256 threads x 8)
 constexpr int kScanTileLog2 = 11;
 static_assert(kScanTile == 1 << kScanTileLog2, "scan tile is a power of two");
+constexpr int kTileReps = 16;      // replicated tile counters for grids of few tiles
+constexpr int kTileRepsMaxTiles = 1024;
 constexpr int kFixShift = 32;     // deposit fixed point: value * 2^32 in uint64
 
 // Per-instance table (device), 32 bytes.
@@ -41,6 +43,7 @@ struct StepParams {
     float h, inv_h, inv_2h, inv_h2;
     float dt, k;
     int32_t tile_totals;   // 1: the histogram also totals each scan tile
+    int32_t tile_reps;     // counters per tile total (1 or kTileReps), picked by wave
     float fcap;            // upper clamp of the harmonic force factor, 1e10 k max d
     float cell_top;        // largest lower-corner index as float (n-1 periodic, n-2 walls)
     float cut2[kMaxSpecies * kMaxSpecies];  // float32 squared contact distances
@@ -93,7 +96,8 @@ struct Buffers {
     uint32_t *count;       // bins_total + 1
     uint32_t *start;       // bins_total + 1
     uint32_t *tile_sum;    // ceil((bins_total + 1) / kScanTile): exclusive tile prefixes
-    uint32_t *tile_cnt;    // same size: agents per scan tile, added with the bin counts
+    uint32_t *tile_cnt;    // kTileReps x that: agents per scan tile (tile_reps counters
+                           // each), added with the bin counts
     float *c[2];           // chemical, two buffers for substeps
     unsigned long long *S_src, *S_upt;  // fixed-point deposits
     InstInfo *inst;

@@ -54,15 +54,18 @@ __global__ void k_init_agents(StepParams p, const InstInfo *__restrict__ inst,
 // order, so a wave rarely spans more than two tiles).
 __device__ __forceinline__ uint32_t count_bin(uint32_t *__restrict__ count,
                                               uint32_t *__restrict__ tile_cnt, uint32_t b,
-                                              int32_t totals) {
+                                              int32_t totals, int32_t reps) {
     const uint32_t r = atomicAdd(count + b, 1u);
     if (!totals) return r;
+    // this wave's counter of the tile (reps is 1 or a power of two)
+    const uint32_t rep = ((blockIdx.x * blockDim.x + threadIdx.x) >> 6) & (uint32_t)(reps - 1);
     const uint32_t t = b >> kScanTileLog2;
     while (true) {
         const uint32_t lead = __builtin_amdgcn_readfirstlane(t);
         const unsigned long long m = __ballot(t == lead);
         if (t == lead) {
-            if (__lane_id() == __builtin_ctzll(m)) atomicAdd(tile_cnt + lead, (uint32_t)__popcll(m));
+            if (__lane_id() == __builtin_ctzll(m))
+                atomicAdd(tile_cnt + (size_t)lead * reps + rep, (uint32_t)__popcll(m));
             break;
         }
     }
@@ -80,7 +83,7 @@ __global__ void k_bin(StepParams p, const InstInfo *__restrict__ inst,
     const float4 x = P[i];
     const uint32_t b = inst[inst_of(x.w)].bin_base + agent_bin<DIM>(p, x);
     bin[i] = b;
-    rank[i] = count_bin(count, tile_cnt, b, p.tile_totals);
+    rank[i] = count_bin(count, tile_cnt, b, p.tile_totals, p.tile_reps);
 }
 
 // Block-wide exclusive scan of one value per thread (blockDim = 256).
@@ -131,19 +134,39 @@ __global__ void __launch_bounds__(256) k_tile_sums(const uint32_t *__restrict__ 
 }
 
 // Exclusive scan of the T tile totals (gathered by the histogram or by
-// k_tile_sums) into tile_sum by one work-group of 1024 threads: passes of 8192 totals, 8
-// consecutive totals per thread (two 16-byte loads and stores), carrying
-// the running total between passes.  The totals are cleared for the next
+// k_tile_sums) into tile_sum by one work-group of 1024 threads: passes of
+// 8192 totals, 8 consecutive totals per thread (two 16-byte loads and
+// stores), carrying the running total between passes.  With reps counters
+// per tile (kTileReps, grids of at most kTileRepsMaxTiles tiles) a tile's
+// total is the sum of its counters.  The counters are cleared for the next
 // histogram.
 __global__ void __launch_bounds__(1024) k_scan_tiles(uint32_t *__restrict__ tile_cnt,
-                                                     uint32_t *__restrict__ tile_sum, int T) {
+                                                     uint32_t *__restrict__ tile_sum, int T,
+                                                     int reps) {
     __shared__ uint32_t lds[16];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     uint32_t carry = 0;
     for (int64_t off = 0; off < T; off += 8192) {
         const int64_t b0 = off + threadIdx.x * 8;
         uint32_t v[8];
-        load8(tile_cnt, b0, T, v);
+        if (reps == 1) {
+            load8(tile_cnt, b0, T, v);
+        } else {
+            // kTileReps counters per tile, four 16-byte loads, then cleared
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                v[k] = 0u;
+                if (b0 + k < T) {
+                    uint4 *q = reinterpret_cast<uint4 *>(tile_cnt + (b0 + k) * kTileReps);
+#pragma unroll
+                    for (int r = 0; r < kTileReps / 4; ++r) {
+                        const uint4 u = q[r];
+                        v[k] += (u.x + u.y) + (u.z + u.w);
+                        q[r] = make_uint4(0u, 0u, 0u, 0u);
+                    }
+                }
+            }
+        }
         const uint32_t s = ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]));
         uint32_t x = s;
 #pragma unroll
@@ -171,14 +194,16 @@ __global__ void __launch_bounds__(1024) k_scan_tiles(uint32_t *__restrict__ tile
             uint4 *p4 = reinterpret_cast<uint4 *>(tile_sum + b0);
             p4[0] = make_uint4(o[0], o[1], o[2], o[3]);
             p4[1] = make_uint4(o[4], o[5], o[6], o[7]);
-            uint4 *z4 = reinterpret_cast<uint4 *>(tile_cnt + b0);
-            z4[0] = make_uint4(0u, 0u, 0u, 0u);
-            z4[1] = make_uint4(0u, 0u, 0u, 0u);
+            if (reps == 1) {
+                uint4 *z4 = reinterpret_cast<uint4 *>(tile_cnt + b0);
+                z4[0] = make_uint4(0u, 0u, 0u, 0u);
+                z4[1] = make_uint4(0u, 0u, 0u, 0u);
+            }
         } else {
             for (int k = 0; k < 8; ++k)
                 if (b0 + k < T) {
                     tile_sum[b0 + k] = o[k];
-                    tile_cnt[b0 + k] = 0u;
+                    if (reps == 1) tile_cnt[b0 + k] = 0u;
                 }
         }
         carry += total;
@@ -356,7 +381,7 @@ k_update(StepParams p, const InstInfo *__restrict__ inst, const float4 *__restri
     Iout[i] = id;
     const uint32_t b = ii.bin_base + agent_bin<DIM>(p, xn);
     bin[i] = b;
-    rank[i] = count_bin(count, tile_cnt, b, p.tile_totals);
+    rank[i] = count_bin(count, tile_cnt, b, p.tile_totals, p.tile_reps);
     if (flag) atomicOr(flags, flag);
 }
 
@@ -763,7 +788,7 @@ k_overlap(StepParams p, const InstInfo *__restrict__ inst, const float4 *__restr
     Iout[i] = Is[i];
     const uint32_t b = ii.bin_base + agent_bin<DIM>(p, xn);
     bin[i] = b;
-    rank[i] = count_bin(count, tile_cnt, b, p.tile_totals);
+    rank[i] = count_bin(count, tile_cnt, b, p.tile_totals, p.tile_reps);
     if (flag) atomicOr(flags, flag);
 }
 
@@ -802,7 +827,8 @@ void launch_scan(const StepParams &p, const Buffers &b, int64_t n_bins_total, hi
     const int T = (int)((n + kScanTile - 1) / kScanTile);
     if (!p.tile_totals)
         hipLaunchKernelGGL(k_tile_sums, dim3(T), dim3(256), 0, s, b.count, n, b.tile_cnt);
-    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, s, b.tile_cnt, b.tile_sum, T);
+    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, s, b.tile_cnt, b.tile_sum, T,
+                       p.tile_totals ? p.tile_reps : 1);
     hipLaunchKernelGGL(k_scan_apply, dim3(T), dim3(256), 0, s, b.count, n, b.tile_sum, b.start, T,
                        (uint32_t)p.n_total);
 }
