@@ -50,8 +50,9 @@ __global__ void k_init_agents(StepParams p, const InstInfo *__restrict__ inst,
 // Histogram of one agent's bin b: its rank within the bin and, when the
 // scan takes its tile totals from the histogram (totals != 0), the agent
 // added to the total of b's scan tile.  The tile totals are summed over the
-// wave first, one device atomic per distinct tile (agents come in cell
-// order, so a wave rarely spans more than two tiles).
+// wave first, one device atomic per distinct tile: in the update and the
+// overlap pass agents come in cell order and a wave rarely spans more than
+// two tiles; after a state load (k_bin, id order) it may span many.
 __device__ __forceinline__ uint32_t count_bin(uint32_t *__restrict__ count,
                                               uint32_t *__restrict__ tile_cnt, uint32_t b,
                                               int32_t totals, int32_t reps) {
