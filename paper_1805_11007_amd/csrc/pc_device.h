@@ -230,8 +230,10 @@ struct ExpVisitor {
     __device__ __forceinline__ void operator()(uint32_t, float dx, float dy, float dz, float r2,
                                                float c2, float dd, int) {
         if (r2 < c2 && r2 > 0.0f) {
+            // k / d and 1 / d are loop-invariant for one species (hoisted)
+            const float kd = k / dd, id = 1.0f / dd;
             const float rinv = rsqrtf(r2);
-            const float f = (k / dd) * expf(-(r2 * rinv) / dd) * rinv;
+            const float f = kd * expf(-(r2 * rinv) * id) * rinv;
             F[0] = fmaf(-f, dx, F[0]);
             F[1] = fmaf(-f, dy, F[1]);
             F[2] = fmaf(-f, dz, F[2]);

@@ -859,7 +859,17 @@ static void upd(const StepParams &p, const Buffers &b, int src, int dst, int cbu
                        b.I[dst], b.bin, b.rank, b.count, b.tile_cnt, b.step, b.flags);
 }
 
-// the other potentials use the generic (LDS) species table
+// the exponential potential with the species specialisations of the
+// harmonic one
+template <int DIM, int NS, int ST>
+static void upd_exp(const StepParams &p, const Buffers &b, int src, int dst, int cbuf, int block,
+                    hipStream_t s) {
+    hipLaunchKernelGGL((k_update<DIM, NS, ST, 1>), dim3(grid_for(p.n_total, block)), dim3(block),
+                       0, s, p, b.inst, b.P[src], b.I[src], b.start, b.c[cbuf], b.P[dst],
+                       b.I[dst], b.bin, b.rank, b.count, b.tile_cnt, b.step, b.flags);
+}
+
+// hard spheres (and a harmonic k = 0) use the generic (LDS) species table
 template <int DIM, int ST, int POT>
 static void upd_pot(const StepParams &p, const Buffers &b, int src, int dst, int cbuf, int block,
                     hipStream_t s) {
@@ -920,11 +930,11 @@ void launch_update(const StepParams &p, const Buffers &b, int src, int dst, int 
         PC_DISPATCH(upd, p, b, src, dst, cbuf, block, s);
         return;
     }
-#define PC_POT(D, S)                                                        \
-    do {                                                                    \
-        if (p.potential == 1) upd_pot<D, S, 1>(p, b, src, dst, cbuf, block, s); \
-        else upd_pot<D, S, 2>(p, b, src, dst, cbuf, block, s);              \
-    } while (0)
+    if (p.potential == 1) {
+        PC_DISPATCH(upd_exp, p, b, src, dst, cbuf, block, s);
+        return;
+    }
+#define PC_POT(D, S) upd_pot<D, S, 2>(p, b, src, dst, cbuf, block, s)
     if (p.dim == 2) {
         if (p.stencil == 3) PC_POT(2, 3);
         else PC_POT(2, 2);
