@@ -230,10 +230,12 @@ struct ExpVisitor {
     __device__ __forceinline__ void operator()(uint32_t, float dx, float dy, float dz, float r2,
                                                float c2, float dd, int) {
         if (r2 < c2 && r2 > 0.0f) {
-            // k / d and 1 / d are loop-invariant for one species (hoisted)
-            const float kd = k / dd, id = 1.0f / dd;
-            const float rinv = rsqrtf(r2);
-            const float f = kd * expf(-(r2 * rinv) * id) * rinv;
+            // k / d and log2(e) / d are loop-invariant for one species
+            // (hoisted); r / d <= the cut range, so the hardware exp2 and rsq
+            // (1 ulp) stay in their normal range
+            const float kd = k / dd, l2d = 1.44269504088896341f / dd;
+            const float rinv = __builtin_amdgcn_rsqf(r2);
+            const float f = kd * __builtin_amdgcn_exp2f(-(r2 * rinv) * l2d) * rinv;
             F[0] = fmaf(-f, dx, F[0]);
             F[1] = fmaf(-f, dy, F[1]);
             F[2] = fmaf(-f, dz, F[2]);
