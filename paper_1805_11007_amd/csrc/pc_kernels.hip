@@ -760,7 +760,7 @@ k_debug_pairs(StepParams p, const InstInfo *__restrict__ inst, const float4 *__r
 // 2 (d - r) D_i / (D_i + D_j); all pushes come from the same positions.
 // Then the boundary closure, and the bin / rank of the corrected position
 // (the counting sort of the next step), as the update kernel does.
-template <int DIM, int STENCIL>
+template <int DIM, int NS, int STENCIL>
 __global__ void __launch_bounds__(1024)
 k_overlap(StepParams p, const InstInfo *__restrict__ inst, const float4 *__restrict__ Ps,
           const uint32_t *__restrict__ Is, const uint32_t *__restrict__ start,
@@ -777,7 +777,7 @@ k_overlap(StepParams p, const InstInfo *__restrict__ inst, const float4 *__restr
     const int si = species_of(pi.w);
     const InstInfo ii = inst[inst_of(pi.w)];
     OverlapVisitor ov{tab.share + si * p.n_species, {0.f, 0.f, 0.f}};
-    pair_loop<DIM, 0, STENCIL>(p, tab, Ps, start, ii.bin_base, pi, si, ov);
+    pair_loop<DIM, NS, STENCIL>(p, tab, Ps, start, ii.bin_base, pi, si, ov);
     uint32_t flag = 0;
     float4 xn;
     xn.x = boundary(p, pi.x + ov.C[0], flag);
@@ -869,6 +869,16 @@ static void upd_exp(const StepParams &p, const Buffers &b, int src, int dst, int
                        b.I[dst], b.bin, b.rank, b.count, b.tile_cnt, b.step, b.flags);
 }
 
+// the hard-sphere overlap pass with the species specialisations of the pair
+// loop (its share table stays in LDS: it is read only for overlapping pairs)
+template <int DIM, int NS, int ST>
+static void ovl(const StepParams &p, const Buffers &b, int src, int dst, int block,
+                hipStream_t s) {
+    hipLaunchKernelGGL((k_overlap<DIM, NS, ST>), dim3(grid_for(p.n_total, block)), dim3(block),
+                       0, s, p, b.inst, b.P[src], b.I[src], b.start, b.P[dst], b.I[dst], b.bin,
+                       b.rank, b.count, b.tile_cnt, b.flags);
+}
+
 // hard spheres (and a harmonic k = 0) use the generic (LDS) species table
 template <int DIM, int ST, int POT>
 static void upd_pot(const StepParams &p, const Buffers &b, int src, int dst, int cbuf, int block,
@@ -947,18 +957,7 @@ void launch_update(const StepParams &p, const Buffers &b, int src, int dst, int 
 
 void launch_overlap(const StepParams &p, const Buffers &b, int src, int dst, int block,
                     hipStream_t s) {
-    const dim3 g(grid_for(p.n_total, block)), t(block);
-#define PC_OV(D, S)                                                                          \
-    hipLaunchKernelGGL((k_overlap<D, S>), g, t, 0, s, p, b.inst, b.P[src], b.I[src], b.start, \
-                       b.P[dst], b.I[dst], b.bin, b.rank, b.count, b.tile_cnt, b.flags)
-    if (p.dim == 2) {
-        if (p.stencil == 3) PC_OV(2, 3);
-        else PC_OV(2, 2);
-    } else {
-        if (p.stencil == 3) PC_OV(3, 3);
-        else PC_OV(3, 2);
-    }
-#undef PC_OV
+    PC_DISPATCH(ovl, p, b, src, dst, block, s);
 }
 
 void launch_debug_pairs(const StepParams &p, const Buffers &b, int src, uint32_t *count,
