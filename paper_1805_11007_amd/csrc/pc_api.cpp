@@ -333,7 +333,7 @@ static void fill_params(pc_sim *s) {
         const double e = sa.diameter, R = d.kde_radius * e;
         p.kde_R2[a] = (float)(R * R);
         p.kde_norm[a] = (float)pow(2.0 * M_PI * e * e, -0.5 * d.dim);
-        p.kde_inv2e2[a] = (float)(1.0 / (2.0 * e * e));
+        p.kde_l2e[a] = (float)(1.4426950408889634 / (2.0 * e * e));
         p.src_f[a] = (float)sa.source;
         p.upt_f[a] = (float)sa.uptake;
     }

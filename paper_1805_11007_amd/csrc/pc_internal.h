@@ -61,7 +61,7 @@ struct StepParams {
     float kde_R;                            // largest truncation radius
     float kde_R2[kMaxSpecies];              // (kde_radius eps_s)^2
     float kde_norm[kMaxSpecies];            // (2 pi eps_s^2)^(-dim/2)
-    float kde_inv2e2[kMaxSpecies];          // 1 / (2 eps_s^2)
+    float kde_l2e[kMaxSpecies];             // log2(e) / (2 eps_s^2)
     float src_f[kMaxSpecies], upt_f[kMaxSpecies];
     // pair interaction: 0 harmonic, 1 exponential, 2 hard spheres (no force;
     // overlaps corrected after the update); tamed Euler pair drift
