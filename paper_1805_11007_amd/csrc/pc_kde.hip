@@ -9,20 +9,27 @@
 // fixed order.  A wave takes a run of nodes along x: its lanes share one
 // (y, z) node row, so they walk the same bin rows with the same culling
 // (compact 4 x 4 x 4 node tiles, whose lanes differ in y and z, ran 2.2x
-// slower on the 1M-agent 3D workload).
+// slower on the 1M-agent 3D workload).  In 3D the bin rows of a node are
+// dealt round robin to the S waves of a work-group (threadIdx.y), whose
+// partial sums are added in LDS in the fixed order 0 .. S-1: a node inside
+// a dense cluster then no longer holds one wave for its whole ball.
 #include <hip/hip_runtime.h>
 
 #include "pc_device.h"
 
 namespace pc {
 
-template <int DIM>
-__global__ void __launch_bounds__(256)
+constexpr int kKdeSplit = 4;  // waves sharing one 3D node run's bin rows
+constexpr int kKdeAhead = 4;  // agent loads issued ahead in the gather
+
+template <int DIM, int S>
+__global__ void __launch_bounds__(S > 1 ? 64 * S : 256)
 k_kde(StepParams p, const InstInfo *__restrict__ inst, const float4 *__restrict__ Ps,
       const uint32_t *__restrict__ start, float2 *__restrict__ dens) {
     __shared__ float tR2[kMaxSpecies], tnorm[kMaxSpecies], tinv[kMaxSpecies];
     __shared__ float tsrc[kMaxSpecies], tupt[kMaxSpecies];
-    if (threadIdx.x < (unsigned)p.n_species) {
+    __shared__ float2 part[S > 1 ? 64 * S : 1];
+    if (threadIdx.y == 0 && threadIdx.x < (unsigned)p.n_species) {
         const int s = threadIdx.x;
         tR2[s] = p.kde_R2[s];
         tnorm[s] = p.kde_norm[s];
@@ -33,10 +40,11 @@ k_kde(StepParams p, const InstInfo *__restrict__ inst, const float4 *__restrict_
     __syncthreads();
     const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int G = p.nodes_per_inst;
-    if (l >= (int64_t)G * p.n_inst) return;
+    const bool valid = l < (int64_t)G * p.n_inst;
+    if (S == 1 && !valid) return;
     const int n = p.grid_n, nb = p.nb;
-    const int k = (int)(l / G);
-    const int loc = (int)(l - (int64_t)k * G);
+    const int k = valid ? (int)(l / G) : 0;
+    const int loc = valid ? (int)(l - (int64_t)k * G) : 0;
     const int ic[3] = {loc % n, (loc / n) % n, DIM == 3 ? loc / (n * n) : 0};
     const float pc[3] = {ic[0] * p.h, ic[1] * p.h, DIM == 3 ? ic[2] * p.h : 0.0f};
     const uint32_t bb = inst[k].bin_base;
@@ -68,10 +76,33 @@ k_kde(StepParams p, const InstInfo *__restrict__ inst, const float4 *__restrict_
     };
     const float R2 = p.kde_R * p.kde_R;
     float sig = 0.0f, ups = 0.0f;
-    for (int cz = 0; cz < cnt[2]; ++cz) {
+    // one node-agent term, summed in the agents' sorted order
+    auto eval = [&](const float4 &q) {
+        float dx = pc[0] - q.x, dy = pc[1] - q.y, dz = DIM == 3 ? pc[2] - q.z : 0.0f;
+        if (p.periodic) {
+            dx = dx > p.halfL ? dx - p.L : (dx < -p.halfL ? dx + p.L : dx);
+            dy = dy > p.halfL ? dy - p.L : (dy < -p.halfL ? dy + p.L : dy);
+            if (DIM == 3) dz = dz > p.halfL ? dz - p.L : (dz < -p.halfL ? dz + p.L : dz);
+        }
+        float r2 = dx * dx + dy * dy;
+        if (DIM == 3) r2 += dz * dz;
+        const int s = species_of(q.w);
+        if (r2 < tR2[s]) {
+            // tinv holds log2(e) / (2 eps^2): r2 * tinv <= 6.5 at the
+            // truncation radius 3 eps, in the hardware exp2's normal range
+            // (1 ulp)
+            const float w = tnorm[s] * __builtin_amdgcn_exp2f(-r2 * tinv[s]);
+            sig = fmaf(tsrc[s], w, sig);
+            ups = fmaf(tupt[s], w, ups);
+        }
+    };
+    // bin rows (cz outer, cy inner); wave threadIdx.y takes every S-th
+    const int nrows = valid ? cnt[1] * cnt[2] : 0;
+    for (int rr = (int)threadIdx.y; rr < nrows; rr += S) {
+        const int cz = DIM == 3 ? rr / cnt[1] : 0, cy = rr - cz * cnt[1];
         const int bz = DIM == 3 ? (lo[2] + cz) % nb : 0;
         const float dz = DIM == 3 && p.periodic ? fmaxf(slab_d(2, cz), 0.0f) : 0.0f;
-        for (int cy = 0; cy < cnt[1]; ++cy) {
+        {
             const int by = (lo[1] + cy) % nb;
             const uint32_t row = bb + (uint32_t)(nb * (by + nb * bz));
             // rows beyond the ball, and x bins beyond its chord, are skipped
@@ -99,27 +130,28 @@ k_kde(StepParams p, const InstInfo *__restrict__ inst, const float4 *__restrict_
                 const int a0 = r == 0 ? x0 : 0;
                 const int a1 = r == 0 ? min(x1, nb) : x1 - nb;
                 const uint32_t j0 = start[row + a0], j1 = start[row + a1];
-                for (uint32_t j = j0; j < j1; ++j) {
-                    const float4 q = Ps[j];
-                    float dx = pc[0] - q.x, dy = pc[1] - q.y, dz = DIM == 3 ? pc[2] - q.z : 0.0f;
-                    if (p.periodic) {
-                        dx = dx > p.halfL ? dx - p.L : (dx < -p.halfL ? dx + p.L : dx);
-                        dy = dy > p.halfL ? dy - p.L : (dy < -p.halfL ? dy + p.L : dy);
-                        if (DIM == 3) dz = dz > p.halfL ? dz - p.L : (dz < -p.halfL ? dz + p.L : dz);
-                    }
-                    float r2 = dx * dx + dy * dy;
-                    if (DIM == 3) r2 += dz * dz;
-                    const int s = species_of(q.w);
-                    if (r2 < tR2[s]) {
-                        // tinv holds log2(e) / (2 eps^2): r2 * tinv <= 6.5 at
-                        // the truncation radius 3 eps, in the hardware exp2's
-                        // normal range (1 ulp)
-                        const float w = tnorm[s] * __builtin_amdgcn_exp2f(-r2 * tinv[s]);
-                        sig = fmaf(tsrc[s], w, sig);
-                        ups = fmaf(tupt[s], w, ups);
-                    }
+                uint32_t j = j0;
+                // kKdeAhead loads in flight before the first is used (a
+                // lane inside a dense cluster walks thousands of agents)
+                for (; j + kKdeAhead <= j1; j += kKdeAhead) {
+                    float4 q[kKdeAhead];
+#pragma unroll
+                    for (int u = 0; u < kKdeAhead; ++u) q[u] = Ps[j + u];
+#pragma unroll
+                    for (int u = 0; u < kKdeAhead; ++u) eval(q[u]);
                 }
+                for (; j < j1; ++j) eval(Ps[j]);
             }
+        }
+    }
+    if (S > 1) {
+        part[threadIdx.y * 64 + threadIdx.x] = make_float2(sig, ups);
+        __syncthreads();
+        if (threadIdx.y != 0 || !valid) return;
+        for (int w = 1; w < S; ++w) {
+            const float2 q = part[w * 64 + threadIdx.x];
+            sig += q.x;
+            ups += q.y;
         }
     }
     dens[l] = make_float2(sig, ups);
@@ -127,12 +159,16 @@ k_kde(StepParams p, const InstInfo *__restrict__ inst, const float4 *__restrict_
 
 void launch_kde(const StepParams &p, const Buffers &b, int src, hipStream_t s) {
     const int64_t total = (int64_t)p.nodes_per_inst * p.n_inst;
-    const dim3 g((unsigned)((total + 255) / 256)), t(256);
     float2 *dens = reinterpret_cast<float2 *>(b.S_src);
-    if (p.dim == 2)
-        hipLaunchKernelGGL(k_kde<2>, g, t, 0, s, p, b.inst, b.P[src], b.start, dens);
-    else
-        hipLaunchKernelGGL(k_kde<3>, g, t, 0, s, p, b.inst, b.P[src], b.start, dens);
+    if (p.dim == 2) {
+        const dim3 g((unsigned)((total + 255) / 256)), t(256);
+        hipLaunchKernelGGL((k_kde<2, 1>), g, t, 0, s, p, b.inst, b.P[src], b.start, dens);
+    } else {
+        // 64 nodes per work-group, their bin rows split over kKdeSplit waves
+        const dim3 g((unsigned)((total + 63) / 64)), t(64, kKdeSplit);
+        hipLaunchKernelGGL((k_kde<3, kKdeSplit>), g, t, 0, s, p, b.inst, b.P[src], b.start,
+                           dens);
+    }
 }
 
 }  // namespace pc
