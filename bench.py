@@ -46,9 +46,9 @@ FLOP_PER_PAIR, FLOP_PER_AGENT = 18.0, 140.0
 UPDATE_TRAFFIC_BYTES = 106.1e6
 # SQ_INSTS_VALU of the same kernel over the chip's issue capacity in its
 # GRBM_GUI_ACTIVE cycles (one wave64 VALU instruction per SIMD per 4 cycles)
-UPDATE_VALU_ISSUE = 0.61
+UPDATE_VALU_ISSUE = 0.60
 UPDATE_TRAFFIC_SOURCES = ("pc_internal.h", "pc_device.h", "pc_kernels.hip")
-UPDATE_TRAFFIC_SHA = "2690e1e9f27763fd"
+UPDATE_TRAFFIC_SHA = "87878b9cb5f534dd"
 
 
 def update_counters_valid(workload: str) -> bool:
