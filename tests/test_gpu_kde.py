@@ -48,7 +48,9 @@ def _within(c, lo, hi, tol):
 CASES = [(W.PERIODIC_1K, 3001, 37, 3.0), (W.WALLS_100K, 20011, 129, 3.0),
          (W.BLOBS_1M, 8000, 32, 3.0), (W.ADJOINT_50K, 6000, 48, 3.0),
          (W.ENSEMBLE_256, None, 24, 3.0), (W.PERIODIC_1K, 3001, 37, 1.5),
-         (W.WALLS_100K, 5000, 65, 6.0)]
+         (W.WALLS_100K, 5000, 65, 6.0),
+         # 33^3 nodes: the last work-group of the 3D gather is ragged
+         (W.BLOBS_1M, 6007, 33, 3.0)]
 
 
 @pytest.mark.parametrize("name,n,g,kappa", CASES)
@@ -117,8 +119,24 @@ def test_one_step_full_size_3d_sampled_nodes():
     assert _within(c[nodes].astype(np.float64), refs[0], refs[1], 1e-5 * scale)
 
 
+def test_one_step_3d_batched_instances():
+    """Three 3D instances in one batch (17^3 nodes each, ragged in total):
+    every node's gather stays inside its own instance's cell list."""
+    w = _kde(W.scaled(W.workload(W.BLOBS_1M), n_agents=[1500, 2003, 700], grid_n=17))
+    inp = W.make_inputs(w)
+    sim = make_sim(w, inp)
+    sim.step(1)
+    x, c, _ = sim.get_state()
+    (Xlo, clo), (Xhi, chi_) = _bracket(w, inp, 1)
+    assert pos_err(x.cpu().numpy(), Xlo, w.L, w.periodic) <= 1e-5
+    scale = max(np.abs(clo).max(), 1e-30)
+    assert _within(c.cpu().numpy().astype(np.float64), clo, chi_, 1e-5 * scale)
+    assert np.abs(clo).max() > 0
+
+
 @pytest.mark.parametrize("name,n,g,steps", [(W.PERIODIC_1K, 2000, 37, 10),
-                                            (W.WALLS_100K, 8000, 65, 6)])
+                                            (W.WALLS_100K, 8000, 65, 6),
+                                            (W.BLOBS_1M, 4000, 33, 4)])
 def test_trajectory_matches_oracle(name, n, g, steps):
     w = _case(name, n, g)
     inp = W.make_inputs(w)
@@ -132,8 +150,10 @@ def test_trajectory_matches_oracle(name, n, g, steps):
     assert _within(c.cpu().numpy().astype(np.float64), clo, chi_, 1e-5 * steps * scale)
 
 
-def test_graph_equals_eager_and_deterministic_repeats():
-    w = _case(W.WALLS_100K, 6000, 65)
+@pytest.mark.parametrize("name,n,g", [(W.WALLS_100K, 6000, 65), (W.BLOBS_1M, 6007, 33)])
+def test_graph_equals_eager_and_deterministic_repeats(name, n, g):
+    """3D: the split row walk sums its partials in a fixed order."""
+    w = _case(name, n, g)
     inp = W.make_inputs(w)
     runs = []
     for graph in (False, True, True):
