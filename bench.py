@@ -264,7 +264,8 @@ def kde_leg(steps: int = 100, sample_nodes: int = 4000) -> dict:
     3 bandwidths) against the particle-in-cell deposit on the 100k-agent walls
     workload and the 1M-agent 3D workload, graph replay.  The gather's work
     is counted as kernel evaluations (node-agent pairs inside the radius),
-    estimated on the initial state from a random sample of nodes."""
+    estimated from a random sample of nodes on the states at the start,
+    middle and end of the profiled steps."""
     import dataclasses
     import numpy as np
     import torch
@@ -285,22 +286,39 @@ def kde_leg(steps: int = 100, sample_nodes: int = 4000) -> dict:
             r[name + "_ms_per_step"] = _timed(lambda: sim.step(steps)) / steps
             sim.sync()
             sim.set_state(x0, c0, 0)
-            prof = sim.profile_steps(min(steps, 50))
+            if dk == 1:
+                # the gather's work grows as the blobs collapse: keep the
+                # states at the start, middle and end of the profiled steps
+                half = min(steps, 50) // 2
+                states, ps = [inp["x0"]], []
+                for _ in range(2):
+                    ps.append(sim.profile_steps(half))
+                    states.append(sim.get_state()[0].cpu().numpy())
+                prof = {k: (ps[0][k] + ps[1][k]) / 2 for k in ps[0]}
+            else:
+                prof = sim.profile_steps(min(steps, 50))
             r[name + "_deposit_ms"] = prof["deposit"]
             r[name + "_pde_ms"] = prof["pde"]
             sim.close()
-        # kernel evaluations per step: node-agent pairs within 3 diameters
+        # kernel evaluations per step: node-agent pairs within 3 diameters,
+        # on a node sample of each kept state, averaged over the profiled
+        # steps (trapezoid rule)
         rng = np.random.default_rng(0)
         xs = W.node_coords(w)
         G = w.grid_n ** w.dim
         idx = rng.integers(0, G, sample_nodes)
         coords = np.stack([xs[(idx // w.grid_n ** a) % w.grid_n] for a in range(w.dim)], 1)
-        X = inp["x0"].astype(np.float64)
-        tree = cKDTree(X, boxsize=w.L if w.periodic else None)
         R = 3.0 * max(s.diameter for s in w.species)
-        cnt = np.array([len(v) for v in tree.query_ball_point(coords, R)])
-        evals = float(cnt.mean()) * G
+        at = []
+        for X in states:
+            X = X.astype(np.float64)
+            if w.periodic:
+                X = np.mod(X, w.L)
+            tree = cKDTree(X, boxsize=w.L if w.periodic else None)
+            at.append(float(tree.query_ball_point(coords, R, return_length=True).mean()) * G)
+        evals = (at[0] + 2.0 * at[1] + at[2]) / 4.0
         r["kernel_evals_per_step"] = evals
+        r["kernel_evals_per_step_at_0_mid_end"] = at
         r["kde_evals_per_s"] = evals / (r["kde_deposit_ms"] * 1e-3)
         r["agents"] = w.n_total
         r["nodes"] = G
