@@ -16,6 +16,7 @@
 #include <hip/hip_runtime.h>
 
 #include "pc_device.h"
+#include "pc_kde.h"
 
 namespace pc {
 
@@ -169,6 +170,123 @@ void launch_kde(const StepParams &p, const Buffers &b, int src, hipStream_t s) {
         hipLaunchKernelGGL((k_kde<3, kKdeSplit>), g, t, 0, s, p, b.inst, b.P[src], b.start,
                            dens);
     }
+}
+
+// Agent-side deposit, one thread per cell-sorted agent (a work-group's
+// agents are neighbours, so they share most nodes).  The nodes within the
+// species' radius R_s of X_i have integer coordinates in
+// [(X - R_s) / h, (X + R_s) / h] per axis (clamped to the grid with walls,
+// wrapped on the torus, where R_s < L / 2 keeps them distinct).  Every
+// agent walks the same box of nodes, so the wave stays convergent.  The
+// terms source_s K and uptake_s K are summed per node in an LDS table
+// (open addressing, 16 probes, then straight to the device), which is
+// flushed with one device float atomic per distinct node.
+constexpr int kKdeSlots = 4096;
+constexpr uint32_t kKdeEmpty = 0xFFFFFFFFu;
+
+template <int DIM>
+__global__ void __launch_bounds__(1024)
+k_kde_scatter(StepParams p, const InstInfo *__restrict__ inst, const float4 *__restrict__ Ps,
+              float2 *__restrict__ dens) {
+    __shared__ float tR2[kMaxSpecies], tnorm[kMaxSpecies], tinv[kMaxSpecies];
+    __shared__ float tsrc[kMaxSpecies], tupt[kMaxSpecies];
+    __shared__ uint32_t keys[kKdeSlots];
+    __shared__ float vs[kKdeSlots], vu[kKdeSlots];
+    if (threadIdx.x < (unsigned)p.n_species) {
+        const int s = threadIdx.x;
+        tR2[s] = p.kde_R2[s];
+        tnorm[s] = p.kde_norm[s];
+        tinv[s] = p.kde_l2e[s];
+        tsrc[s] = p.src_f[s];
+        tupt[s] = p.upt_f[s];
+    }
+    for (int q = threadIdx.x; q < kKdeSlots; q += blockDim.x) {
+        keys[q] = kKdeEmpty;
+        vs[q] = 0.0f;
+        vu[q] = 0.0f;
+    }
+    __syncthreads();
+    auto emit = [&](uint32_t key, float a, float b) {
+        uint32_t h = (key * 2654435761u) >> 20;  // 12 bits: kKdeSlots = 4096
+        for (int probe = 0; probe < 16; ++probe) {
+            uint32_t old =
+                __hip_atomic_load(&keys[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (old == kKdeEmpty) old = atomicCAS(&keys[h], kKdeEmpty, key);
+            if (old == kKdeEmpty || old == key) {
+                if (a != 0.0f) unsafeAtomicAdd(&vs[h], a);
+                if (b != 0.0f) unsafeAtomicAdd(&vu[h], b);
+                return;
+            }
+            h = (h + 1) & (kKdeSlots - 1);
+        }
+        if (a != 0.0f) unsafeAtomicAdd(&dens[key].x, a);
+        if (b != 0.0f) unsafeAtomicAdd(&dens[key].y, b);
+    };
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < p.n_total) {
+        const float4 q = Ps[i];
+        const int s = species_of(q.w);
+        const float src = tsrc[s], upt = tupt[s];
+        const float xq[3] = {q.x, q.y, q.z};
+        // a non-finite position is flagged by the update; it deposits nothing
+        const bool live = (src != 0.0f || upt != 0.0f) && isfinite(xq[0]) && isfinite(xq[1]) &&
+                          isfinite(xq[2]);
+        const int n = p.grid_n;
+        const float R2 = tR2[s], R = sqrtf(R2);
+        int lo[3] = {0, 0, 0}, hi[3] = {0, 0, -1};
+        if (live) {
+            hi[2] = 0;
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) {
+                // on the torus the box stays within [-n, 2n), where one wrap
+                // maps it into the grid; n nodes at most per axis
+                lo[a] = max((int)ceilf((xq[a] - R) * p.inv_h), p.periodic ? -n : 0);
+                hi[a] = min((int)floorf((xq[a] + R) * p.inv_h), p.periodic ? 2 * n - 1 : n - 1);
+                if (hi[a] - lo[a] >= n) hi[a] = lo[a] + n - 1;
+            }
+        }
+        const uint32_t base = inst[inst_of(q.w)].node_base;
+        const float norm = tnorm[s], l2e = tinv[s];
+        auto wrap = [&](int c) { return c < 0 ? c + n : (c >= n ? c - n : c); };
+        for (int iz = lo[2]; iz <= hi[2]; ++iz) {
+            const float dz = DIM == 3 ? (float)iz * p.h - xq[2] : 0.0f;
+            const int wz = DIM == 3 ? (p.periodic ? wrap(iz) : iz) : 0;
+            for (int iy = lo[1]; iy <= hi[1]; ++iy) {
+                const float dy = (float)iy * p.h - xq[1];
+                const int wy = p.periodic ? wrap(iy) : iy;
+                const float r2yz = dy * dy + dz * dz;
+                if (r2yz >= R2) continue;
+                const uint32_t rowo = base + (uint32_t)((wz * n + wy) * n);
+                for (int ix = lo[0]; ix <= hi[0]; ++ix) {
+                    const float dx = (float)ix * p.h - xq[0];
+                    const float r2 = dx * dx + r2yz;
+                    if (r2 < R2) {
+                        const float w = norm * __builtin_amdgcn_exp2f(-r2 * l2e);
+                        emit(rowo + (uint32_t)(p.periodic ? wrap(ix) : ix), src * w, upt * w);
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < kKdeSlots; q += blockDim.x) {
+        const uint32_t k = keys[q];
+        if (k == kKdeEmpty) continue;
+        if (vs[q] != 0.0f) unsafeAtomicAdd(&dens[k].x, vs[q]);
+        if (vu[q] != 0.0f) unsafeAtomicAdd(&dens[k].y, vu[q]);
+    }
+}
+
+void launch_kde_scatter(const StepParams &p, const Buffers &b, int src, hipStream_t s) {
+    const int64_t total = (int64_t)p.nodes_per_inst * p.n_inst;
+    float2 *dens = reinterpret_cast<float2 *>(b.S_src);
+    launch_zero_u32(reinterpret_cast<uint32_t *>(b.S_src), 2 * total, s);
+    if (p.n_total == 0) return;
+    const dim3 g((unsigned)((p.n_total + 1023) / 1024)), t(1024);
+    if (p.dim == 2)
+        hipLaunchKernelGGL(k_kde_scatter<2>, g, t, 0, s, p, b.inst, b.P[src], dens);
+    else
+        hipLaunchKernelGGL(k_kde_scatter<3>, g, t, 0, s, p, b.inst, b.P[src], dens);
 }
 
 }  // namespace pc

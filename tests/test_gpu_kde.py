@@ -1,11 +1,13 @@
-"""Gaussian kernel density deposit on the GPU (per-node gather over the cell
-list of X^{n+1}) against the FP64 oracle, through the C ABI.
+"""Gaussian kernel density deposit on the GPU against the FP64 oracle,
+through the C ABI: the agent-side scatter (LDS table, then float atomics;
+the default in 3D) and the per-node gather over the cell list of X^{n+1}
+(fixed order; 2D, and deterministic mode).
 
 Bars: positions as the plain step (1e-5 L per step).  The field after a
 step lies within 1e-5 max|c| of the oracle's field bracketed by truncation
 radii kde_radius (1 -/+ 1e-5): a node-agent pair at the truncation radius
-may be decided either way in float32.  Graph replay equals eager replay
-bit for bit; deterministic mode repeats bit for bit.
+may be decided either way in float32.  In deterministic mode graph replay
+equals eager replay bit for bit and runs repeat bit for bit.
 """
 import dataclasses
 
@@ -53,11 +55,15 @@ CASES = [(W.PERIODIC_1K, 3001, 37, 3.0), (W.WALLS_100K, 20011, 129, 3.0),
          (W.BLOBS_1M, 6007, 33, 3.0)]
 
 
+@pytest.mark.parametrize("det", [False, True], ids=["scatter", "gather"])
 @pytest.mark.parametrize("name,n,g,kappa", CASES)
-def test_one_step_matches_oracle(name, n, g, kappa):
+def test_one_step_matches_oracle(name, n, g, kappa, det):
+    """Both forms of the deposit in 3D: the agent-side scatter (float
+    atomics) and, where results must repeat bit for bit, the fixed-order
+    gather (the 2D cases run the gather either way)."""
     w = _case(name, n, g, kappa)
     inp = W.make_inputs(w)
-    sim = make_sim(w, inp)
+    sim = make_sim(w, inp, deterministic=det)
     assert sim.info["deposit_path"] == 4
     sim.step(1)
     x, c, _ = sim.get_state()
