@@ -105,8 +105,11 @@ typedef struct {
                                K(x) = (2 pi e^2)^(-dim/2) exp(-|x|^2 / (2 e^2)), e =
                                the agent's diameter, over |p - X_i| < kde_radius e
                                (minimum image on the torus; no image across walls).
-                               Gathered per node over the cell list of X^{n+1};
-                               deposit_mode is then ignored (3 is rejected)           */
+                               In 2D, and in deterministic mode, gathered per node
+                               over the cell list of X^{n+1} in a fixed order; in 3D
+                               otherwise scattered from the agents by float atomics
+                               (last bits vary run to run).  deposit_mode is then
+                               ignored (3 is rejected)                                */
     int32_t reserved;
     double kde_radius;      /* truncation radius in bandwidths (0: 3); kde_radius times
                                the largest diameter must be < L/2                       */
