@@ -166,7 +166,13 @@ typedef struct {
 size_t pc_workspace_bytes(const pc_config *cfg, const pc_species_t *species, int n_species,
                           const pc_instance *inst, int n_inst);
 
-/* Create a simulation handle.
+/* Create a simulation handle: the counterpart of the `Simulation(sample)`
+ * constructor of the paper's Python interface (Sect. 4).  There a sample
+ * number seeds the realisation's random generators (set-up of Sect. 3.1);
+ * here each instance carries the noise key of its realisation, so one
+ * handle may hold many realisations.  Creation also builds the cell list
+ * over the domain (the neighbour-search set-up of Sect. 3.1) and loads the
+ * grid vector c of the chemical (Sect. 3.5).
  *   workspace_dev / workspace_bytes: caller-owned device buffer of at least
  *     pc_workspace_bytes(...) bytes, 256-byte aligned, valid until pc_destroy;
  *   x0_dev: float32, sum(N) x dim, instance-major id order, inside the box;
@@ -183,27 +189,55 @@ int pc_create(const pc_config *cfg, const pc_species_t *species, int n_species,
               const float *x0_dev, const uint8_t *species0_dev, const float *c0_dev,
               void *hip_stream, pc_sim **out);
 
-/* Enqueue n_steps time steps (n_steps >= 0).  With pc_use_graph(sim, 1) the
- * steps are replayed from a captured HIP graph (captured on first use). */
+/* Enqueue n_steps time steps (n_steps >= 0): the counterpart of
+ * `integrate(time)` of Sect. 4, which advances the simulation by a span of
+ * time; integrate(T) is round(T / dt) steps (the Python binding's
+ * Sim.integrate).  Each step is the Euler-Maruyama update of eq. sde_EM
+ * coupled to the forward-Euler update of eq. pde_c, in the order of the
+ * listings of Sect. 3.  With pc_use_graph(sim, 1) the steps are replayed
+ * from a captured HIP graph (captured on first use).  Errors: PC_EINVAL
+ * (null handle, n_steps < 0), PC_EHIP; kernel-side conditions surface at
+ * pc_sync. */
 int pc_step(pc_sim *sim, int n_steps);
 
-/* Turn HIP-graph replay of pc_step on (1) or off (0). */
+/* Turn HIP-graph replay of pc_step on (1) or off (0).  Not in the paper (a
+ * launch mechanism of this library); results are bit for bit those of
+ * eager steps. */
 int pc_use_graph(pc_sim *sim, int on);
 
-/* Current positions into out_dev (float32, sum(N) x dim, id order). */
+/* Current positions into out_dev (float32, sum(N) x dim, id order): the
+ * counterpart of `get_positions()` of Sect. 4.  The paper wraps the
+ * particle positions in a NumPy array without copying; here the positions
+ * are written into a caller-owned device buffer (which torch wraps without
+ * a host copy), because the library keeps them in cell-sorted order.
+ * Stream-ordered.  Errors: PC_EINVAL (null argument), PC_EHIP. */
 int pc_positions(pc_sim *sim, float *out_dev);
 
-/* Current chemical field into out_dev (float32, n_inst x grid_n^dim). */
+/* Current chemical field into out_dev (float32, n_inst x grid_n^dim): the
+ * grid vector c of the chemical at the nodes (Sect. 3.5), which the paper
+ * also hands to Python with a grid-data counterpart of its particle-vector
+ * wrapper (Sect. 4).  Stream-ordered device-to-device copy.  Errors:
+ * PC_EINVAL (null argument), PC_EHIP. */
 int pc_field(pc_sim *sim, float *out_dev);
 
-/* Species of every agent into out_dev (uint8, sum(N), id order). */
+/* Species of every agent into out_dev (uint8, sum(N), id order): the
+ * counterpart of `get_type()` of Sect. 4, the cell type alpha / beta of
+ * Sect. 3.1 (a species index here).  Stream-ordered.  Errors: PC_EINVAL
+ * (null argument), PC_EHIP. */
 int pc_species(pc_sim *sim, uint8_t *out_dev);
 
 /* Checkpoint: positions (as pc_positions), field (as pc_field) and the step
- * counter (host value; steps enqueued so far plus the initial counter). */
+ * counter (host value; steps enqueued so far plus the initial counter).
+ * The state of Sect. 3 is the particle set (Sect. 3.1) and the grid vector
+ * c (Sect. 3.5); the paper saves finished runs to disk from Python
+ * (Sect. 4), and this call is the in-memory form of that.  x_dev or c_dev
+ * may be NULL to skip that part.  Stream-ordered.  Errors: PC_EINVAL (null
+ * handle), PC_EHIP. */
 int pc_get_state(pc_sim *sim, float *x_dev, float *c_dev, uint32_t *step);
 
-/* Restore a checkpoint; the noise of later steps is that of the restored
+/* Restore a checkpoint (the inverse of pc_get_state): positions of the
+ * particle set (Sect. 3.1) in id order, the grid vector c (Sect. 3.5) and
+ * the step counter; the noise of later steps is that of the restored
  * step counter (Philox is keyed by step, id and instance).  Agents take the
  * species last given to pc_create or pc_set_species (switches made by steps
  * since then are undone); x_dev or c_dev may be NULL to keep that part. */
@@ -269,7 +303,10 @@ enum { PC_STAGE_BIN, PC_STAGE_SCAN, PC_STAGE_SCATTER, PC_STAGE_STABLE, PC_STAGE_
        PC_STAGE_DEPOSIT, PC_STAGE_PDE, PC_STAGE_OVERLAP, PC_N_STAGES };
 int pc_profile_steps(pc_sim *sim, int n_steps, double *stage_ms);
 
-/* Release the handle (does not touch caller memory). */
+/* Release the handle (does not touch caller memory): the end of the
+ * `Simulation` object's life (Sect. 4).  Destroys the captured graphs; the
+ * caller frees the workspace after the stream has passed the last call.
+ * A NULL handle is accepted (PC_OK). */
 int pc_destroy(pc_sim *sim);
 
 const char *pc_strerror(int code);

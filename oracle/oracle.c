@@ -271,7 +271,7 @@ static void orc_candidates(int dim, int periodic, int64_t n, const double *X, co
                 for (int64_t t = B->start[b]; t < B->start[b + 1]; ++t)
                     if (B->order[t] != i) list_push(out, B->order[t]);
             }
-    qsort(out->v, (size_t)out->n, sizeof(int64_t), cmp_i64);
+    if (out->n > 1) qsort(out->v, (size_t)out->n, sizeof(int64_t), cmp_i64);
 }
 
 /* Pair repulsion for every agent: F_i = -sum_j g(r) dx over neighbours

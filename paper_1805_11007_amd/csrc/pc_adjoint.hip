@@ -430,7 +430,7 @@ __device__ __forceinline__ void hist_cell(const LossArgs &a, float x, int &i0, i
     const float s = fmaxf(x * a.inv_hh, 0.0f);
     const float fi = fminf(floorf(s), (float)(a.m - 1));
     i0 = (int)fi;
-    t = s - fi;
+    t = fmaf(x, a.inv_hh, -fi);   // one rounding, as cell_of
     i1 = i0 + 1 == a.m ? 0 : i0 + 1;
 }
 

@@ -371,6 +371,9 @@ static void fill_params(pc_sim *s) {
     q.inv_hd = (float)(1.0 / hd);
     q.has_uptake = d.has_uptake;
     q.kde = d.kde;
+    // the 3D kernel density deposit scatters from the agents into pairs
+    // that must start each step at zero (enqueue_kde picks the same path)
+    q.kde_clear = d.kde && d.dim == 3 && !c.deterministic ? 1 : 0;
 }
 
 static void carve(pc_sim *s, char *ws) {

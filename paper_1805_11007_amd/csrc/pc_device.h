@@ -200,11 +200,10 @@ __device__ __forceinline__ void pair_range(const StepParams &p, const SpTab &tab
 
 // Repulsion F_i = -sum k (d_ij - r) dx / r over neighbours with r > 0,
 // evaluated as k d / r - k with the hardware reciprocal square root, for
-// every candidate, and selected by the neighbour test (no branch: in dense
-// regions nearly every wave has a neighbour among its candidates).  The
-// self pair and coincident agents (r2 = 0, dx = 0) contribute exactly zero
-// through the product with dx; the 1e-20 added to r2 keeps f finite there
-// and leaves r2 of any two distinct float32 positions in the box unchanged.
+// every candidate, and selected without a branch (in dense regions nearly
+// every wave has a neighbour among its candidates).  The self pair and
+// coincident agents (r2 = 0, dx = 0) contribute exactly zero through the
+// product with dx: the clamp below keeps the factor finite there.
 struct ForceVisitor {
     float k, fcap;
     float F[3];
@@ -482,6 +481,11 @@ __device__ __forceinline__ void pair_loop(const StepParams &p, const SpTab &tab,
 // Grid geometry.  Periodic: spacing L/n, nodes i*h, upper corner wraps.
 // Walls: spacing L/(n-1), nodes on both walls, lower corner <= n-2.
 // ---------------------------------------------------------------------------
+// The offset t = x / h - i0 is formed with one rounding, fma(x, 1/h, -i0).
+// Where the float32 1/h is exact (an integer for L = 1: 128, 511, 51, ...)
+// t is the exact offset rounded once, accurate to an ulp of t rather than
+// of x / h.  Where x / h rounds up to an integer the floor is one too high
+// and t comes out a hair below 0; the weights stay continuous.
 struct Cell { int i0, i1; float t; };
 
 __device__ __forceinline__ Cell cell_of(const StepParams &p, float x) {
@@ -489,7 +493,7 @@ __device__ __forceinline__ Cell cell_of(const StepParams &p, float x) {
     const float fi = fminf(floorf(s), p.cell_top);
     Cell c;
     c.i0 = (int)fi;
-    c.t = s - fi;
+    c.t = fmaf(x, p.inv_h, -fi);
     c.i1 = c.i0 + 1;
     if (p.periodic && c.i1 == p.grid_n) c.i1 = 0;
     return c;

@@ -31,7 +31,7 @@ struct StepParams {
     int32_t dim, periodic, n_species, n_inst;
     int32_t nb;            // bins per axis
     int32_t stencil;       // 3: (3)^dim bins ; 2: (2)^dim bins picked by half-bin side
-    int32_t bin_order;     // 0 row-major, 1 bricks of 2^dim bins
+    int32_t bin_order;     // 0: row-major, x fastest (the only order built)
     int32_t grid_n;
     int32_t n_total;       // agents over all instances
     int32_t nodes_per_inst;
@@ -77,6 +77,7 @@ struct PdeParams {
     float inv_hd;          // 1 / h^dim
     int32_t has_uptake;
     int32_t kde;           // 1: sources are kernel-density pairs (sigma, upsilon)
+    int32_t kde_clear;     // 1: the last substep clears the pairs (agent-side scatter)
 };
 
 // Flag bits latched by kernels in the device flag word.

@@ -232,7 +232,10 @@ k_kde_scatter(StepParams p, const InstInfo *__restrict__ inst, const float4 *__r
         const bool live = (src != 0.0f || upt != 0.0f) && isfinite(xq[0]) && isfinite(xq[1]) &&
                           isfinite(xq[2]);
         const int n = p.grid_n;
-        const float R2 = tR2[s], R = sqrtf(R2);
+        // the node box is taken a hair wider than the ball (as the gather's
+        // bin range), so float32 rounding of (x -+ R) / h never drops a node
+        // inside it; r2 < R2 decides every node of the box
+        const float R2 = tR2[s], R = sqrtf(R2) * (1.0f + 1e-4f);
         int lo[3] = {0, 0, 0}, hi[3] = {0, 0, -1};
         if (live) {
             hi[2] = 0;
@@ -277,10 +280,10 @@ k_kde_scatter(StepParams p, const InstInfo *__restrict__ inst, const float4 *__r
     }
 }
 
+// The (sigma, upsilon) pairs start at zero: cleared at creation and by the
+// last PDE substep of every step (k_pde with PdeParams::kde_clear).
 void launch_kde_scatter(const StepParams &p, const Buffers &b, int src, hipStream_t s) {
-    const int64_t total = (int64_t)p.nodes_per_inst * p.n_inst;
     float2 *dens = reinterpret_cast<float2 *>(b.S_src);
-    launch_zero_u32(reinterpret_cast<uint32_t *>(b.S_src), 2 * total, s);
     if (p.n_total == 0) return;
     const dim3 g((unsigned)((p.n_total + 1023) / 1024)), t(1024);
     if (p.dim == 2)

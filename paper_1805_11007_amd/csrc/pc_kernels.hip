@@ -631,9 +631,11 @@ k_chem_inst(StepParams p, PdeParams q, const InstInfo *__restrict__ inst,
 
 // PDE substep, one thread per node; the last substep of a step clears the
 // deposits for the next step.
-// KDE: the source array holds (sigma, upsilon) float pairs, rewritten by
-// every step's density gather, so nothing is cleared.  stepc (non-null on
-// the last substep of a step): the step counter, advanced by node 0.
+// KDE: the source array holds (sigma, upsilon) float pairs.  The per-node
+// gather rewrites every pair each step; the agent-side scatter adds into
+// them, so with it (q.kde_clear) the last substep clears the pairs it read.
+// stepc (non-null on the last substep of a step): the step counter,
+// advanced by node 0.
 // One work-group per grid row along x: the instance and the (y, z) of the
 // row are wave-uniform, so no thread divides by the grid size.
 template <int DIM, bool KDE>
@@ -654,8 +656,11 @@ k_pde(PdeParams q, const float *__restrict__ cin, float *__restrict__ cout,
         const int64_t l = (int64_t)row * n + ix;
         const int ic[3] = {ix, iy, iz};
         if (KDE) {
-            const float2 su = reinterpret_cast<const float2 *>(Ssrc)[l];
+            float2 *dens = reinterpret_cast<float2 *>(Ssrc);
+            const float2 su = dens[l];
             cout[l] = pde_node_dens<DIM>(q, cb, ic, su.x, su.y, flag);
+            if (last && q.kde_clear && (su.x != 0.0f || su.y != 0.0f))
+                dens[l] = make_float2(0.0f, 0.0f);
             continue;
         }
         const unsigned long long sS = Ssrc[l], sU = q.has_uptake ? Supt[l] : 0ull;

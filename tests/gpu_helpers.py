@@ -60,9 +60,10 @@ def oracle_steps(w, inp, n_steps, step0=0):
 def deposit_rounding_tol(w, x32, species, c_max):
     """Per-node bound (flat, instance-major like the field) of the difference
     that float32 rounding of the particle-in-cell weights can make in one
-    step's field.  The device forms t = x / h - i0 from s = x * (1/h) in
-    float32; for x / h <= n (n nodes per axis) s is off by at most
-    2 n 2^-24, and each of an agent's weights by d times that.  Node l takes
+    step's field.  The device forms t = x / h - i0 with one rounding
+    (fma(x, 1/h, -i0), 1/h exact on these grids), so t is off by at most
+    2^-24, each factor 1 - t or t by 2 ulps, and the product of an agent's
+    d factors by about 2 d 2^-24.  Node l takes
     dt q_a W / (h^d v_l) from every agent a whose cell has l as a corner,
     with q_a = source + uptake * max|c| (the uptake acts through upsilon c).
     The largest bound of a node's 3^d neighbourhood is taken, since PDE
@@ -99,7 +100,7 @@ def deposit_rounding_tol(w, x32, species, c_max):
                     idx = [slice(None)] * d
                     idx[ax] = e
                     inv_v[tuple(idx)] *= 2.0
-        b = w.dt * inv_v / h ** d * acc * d * 2.0 * n * 2.0 ** -24
+        b = w.dt * inv_v / h ** d * acc * 2.0 * d * 2.0 ** -24
         for ax in range(d):
             pad = [(0, 0)] * d
             pad[ax] = (1, 1)
@@ -116,7 +117,11 @@ def field_ok(c_gpu, c_ref, w, x32, species):
     c_ref = np.asarray(c_ref, np.float64)
     cmax = np.abs(c_ref).max()
     tol = 1e-5 * cmax + deposit_rounding_tol(w, x32, species, cmax)
-    return bool(np.all(np.abs(np.asarray(c_gpu, np.float64) - c_ref) <= tol))
+    diff = np.abs(np.asarray(c_gpu, np.float64) - c_ref)
+    worst = int(np.argmax(diff / tol))
+    print(f"field: max |diff| {diff.max():.3e} (max|c| {cmax:.3e}); at the node nearest "
+          f"its bound diff {diff[worst]:.3e} vs bound {tol[worst]:.3e}")
+    return bool(np.all(diff <= tol))
 
 
 def field_from_positions(w, c0, X, species):

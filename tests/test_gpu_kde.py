@@ -73,6 +73,85 @@ def test_one_step_matches_oracle(name, n, g, kappa, det):
     assert _within(c.cpu().numpy().astype(np.float64), clo, chi_, 1e-5 * scale)
 
 
+def _w3(n, g, periodic, species, kappa, rule="halves", seed=1203):
+    return W.Workload("kde3d", 3, periodic, 1.0, g, 1e-6, 100.0, 1.0, 0.1, 1, tuple(species),
+                      (W.Instance(n, seed),), species_rule=rule,
+                      c0="sin" if periodic else "cos", gen_seed=seed, deposit_kernel=1,
+                      kde_radius=kappa)
+
+
+# 3D agent-side scatter at the ball sizes of the full workload (radius about
+# 1.5 to 3 node spacings, so every agent walks a box of several nodes per
+# axis, across the periodic seam), with two species of different radii and
+# uptake, with walls, with kappa = 6, and with uniform agents whose
+# 1024-agent work-groups reach far more than the 4096 slots of the LDS table
+# (the overflow goes to device atomics).
+SCATTER_3D = {
+    "wide_balls_torus": _w3(6000, 32, True, [W.Species(0.02, 1.0, 1.0, 1.0, 0.0)], 3.0,
+                            rule="single"),
+    "two_species_uptake_walls": _w3(6000, 33, False, [W.Species(0.015, 1.0, 0.0, 1.0, 0.0),
+                                                      W.Species(0.025, 0.5, 2.0, 0.0, 1.0)],
+                                    3.0),
+    "kappa6_two_species_torus": _w3(4000, 32, True, [W.Species(0.01, 1.0, 0.0, 1.0, 0.0),
+                                                     W.Species(0.015, 0.5, 1.0, 0.5, 2.0)],
+                                    6.0),
+    "lds_table_overflow": _w3(16000, 40, True, [W.Species(0.025, 1.0, 1.0, 1.0, 0.0)], 3.0,
+                              rule="single"),
+}
+
+
+def _nodes_per_workgroup(w, x):
+    """Distinct nodes inside the balls of each 1024-agent run of the
+    cell-sorted order (the scatter's work-groups), counted on the host."""
+    d = max(s.diameter for s in w.species)
+    nb = int(np.floor(w.L / (d * (1 + 1e-4))))
+    b = np.minimum((x * nb / w.L).astype(np.int64), nb - 1)
+    order = np.argsort(b[:, 0] + nb * (b[:, 1] + nb * b[:, 2]), kind="stable")
+    n = w.grid_n
+    h = w.L / n if w.periodic else w.L / (n - 1)
+    R = w.kde_radius * d
+    r = int(np.ceil(R / h))
+    off = np.stack(np.meshgrid(*([np.arange(-r, r + 1)] * 3), indexing="ij"), -1).reshape(-1, 3)
+    out = []
+    for g0 in range(0, len(order), 1024):
+        xs = x[order[g0:g0 + 1024]].astype(np.float64)
+        base = np.floor(xs / h).astype(np.int64)
+        cand = (base[:, None, :] + off[None, :, :])
+        dist2 = ((cand * h - xs[:, None, :]) ** 2).sum(-1)
+        keep = cand[dist2 < R * R] % n
+        out.append(len(np.unique(keep[:, 0] + n * (keep[:, 1] + n * keep[:, 2]))))
+    return out
+
+
+@pytest.mark.parametrize("case", sorted(SCATTER_3D))
+def test_one_step_3d_scatter_cases(case):
+    w = SCATTER_3D[case]
+    inp = W.make_inputs(w)
+    if case == "lds_table_overflow":
+        assert max(_nodes_per_workgroup(w, inp["x0"])) > 2 * 4096
+    sim = make_sim(w, inp)
+    assert sim.info["deposit_path"] == 4
+    sim.step(1)
+    x, c, _ = sim.get_state()
+    (Xlo, clo), (Xhi, chi_) = _bracket(w, inp, 1)
+    assert pos_err(x.cpu().numpy(), Xlo, w.L, w.periodic) <= 1e-5
+    scale = max(np.abs(clo).max(), 1e-30)
+    cg = c.cpu().numpy().astype(np.float64)
+    print(f"{case}: field dev from bracket {max((np.minimum(clo, chi_) - cg).max(), (cg - np.maximum(clo, chi_)).max(), 0.0) / scale:.2e}")
+    assert _within(cg, clo, chi_, 1e-5 * scale)
+    # a second step: the pairs cleared by the last PDE substep start at zero
+    sim.step(1)
+    x2, c2, _ = sim.get_state()
+    here = dict(inp, x0=x.cpu().numpy(), c0=c.cpu().numpy())
+    lo2 = oracle.run_workload(dataclasses.replace(w, kde_radius=w.kde_radius * (1 - 1e-5)),
+                              here, 1, step0=1)
+    hi2 = oracle.run_workload(dataclasses.replace(w, kde_radius=w.kde_radius * (1 + 1e-5)),
+                              here, 1, step0=1)
+    assert pos_err(x2.cpu().numpy(), lo2[0], w.L, w.periodic) <= 1e-5
+    scale2 = max(np.abs(lo2[1]).max(), 1e-30)
+    assert _within(c2.cpu().numpy().astype(np.float64), lo2[1], hi2[1], 1e-5 * scale2)
+
+
 def test_one_step_full_size_walls_100k():
     """The full 100k walls workload with the kernel density deposit as the
     benchmark runs it (radius 3 bandwidths, default launch)."""

@@ -10,7 +10,7 @@ import pytest
 
 import oracle
 import workloads as W
-from gpu_helpers import (field_err, field_from_positions, field_ok, make_sim, oracle_forces,
+from gpu_helpers import (field_err, field_from_positions, make_sim, oracle_forces,
                          oracle_neighbours, oracle_steps, pos_err)
 
 pytestmark = pytest.mark.gpu
@@ -81,10 +81,9 @@ def test_one_step(name, n, g, det):
 
 @pytest.mark.parametrize("name", FULL)
 def test_one_step_full_size(name):
-    """Full size: positions against the oracle's step; the field within
-    1e-5 max|c| of the oracle's step, and within 1e-5 max|c| plus the
-    float32 rounding bound of the deposit weights of the oracle's deposit
-    and PDE at the device's own new positions."""
+    """Full size: positions and field against the oracle's step (1e-5 L,
+    1e-5 max|c|); the field also against the oracle's deposit and PDE at the
+    device's own new positions, at the same bar."""
     w = W.workload(name)
     inp = W.make_inputs(w)
     sim = make_sim(w, inp)
@@ -93,10 +92,12 @@ def test_one_step_full_size(name):
     x = sim.positions().cpu().numpy()
     c = sim.field().cpu().numpy()
     X1, c1 = oracle_steps(w, inp, 1)
-    assert pos_err(x, X1, w.L, w.periodic) <= 1e-5
-    assert field_ok(c, c1, w, x, inp["species0"])
-    c_ref = field_from_positions(w, inp["c0"], x, inp["species0"])
-    assert field_ok(c, c_ref, w, x, inp["species0"])
+    ex, ec = pos_err(x, X1, w.L, w.periodic), field_err(c, c1)
+    ecp = field_err(c, field_from_positions(w, inp["c0"], x, inp["species0"]))
+    print(f"{name}: position err {ex:.2e} field err {ec:.2e} (at device positions {ecp:.2e})")
+    assert ex <= 1e-5
+    assert ec <= 1e-5
+    assert ecp <= 1e-5
 
 
 def test_ensemble_256_full_size_sampled_instances():
@@ -179,9 +180,12 @@ def test_one_step_3d_blobs_from_clustered_gpu_state(n0):
     x1 = sim.positions().cpu().numpy()
     c1 = sim.field().cpu().numpy()
     Xo, co = oracle_steps(w, sn, 1, step0=n0)
-    assert pos_err(x1, Xo, w.L, w.periodic) <= 1e-5
-    assert field_ok(c1, co, w, x1, inp["species0"])
-    assert field_ok(c1, field_from_positions(w, c, x1, inp["species0"]), w, x1, inp["species0"])
+    ex, ec = pos_err(x1, Xo, w.L, w.periodic), field_err(c1, co)
+    ecp = field_err(c1, field_from_positions(w, c, x1, inp["species0"]))
+    print(f"step {n0}: position err {ex:.2e} field err {ec:.2e} (at device positions {ecp:.2e})")
+    assert ex <= 1e-5
+    assert ec <= 1e-5
+    assert ecp <= 1e-5
 
 
 def test_one_step_later_counter_3d_blobs():

@@ -102,7 +102,46 @@ def test_species_and_warnings():
     assert sim.warnings() & PC_WARN_DT_RULE  # sqrt(2*2*1e-6) = 0.002 = d for species 0
 
 
-def test_walls_keep_agents_in_box_and_nonfinite_flag():
+def test_nonfinite_field_raises_enonfinite_at_sync():
+    """A NaN in c0 reaches the PDE (and the drift of agents near it); the
+    kernels latch the non-finite flag and pc_sync reports PC_ENONFINITE
+    once, then clears it."""
+    import torch
+    from paper_1805_11007_amd import PcError
+    from paper_1805_11007_amd._lib import PC_ENONFINITE
+    w = W.scaled(W.workload(W.PERIODIC_1K), n_agents=2000, grid_n=32)
+    inp = W.make_inputs(w)
+    c0 = inp["c0"].copy()
+    c0[5 * 32 + 7] = np.nan
+    sim = make_sim(w, dict(inp, c0=c0))
+    sim.sync()                       # creation itself reads no field value
+    sim.step(1)
+    with pytest.raises(PcError) as e:
+        sim.sync()
+    assert e.value.code == PC_ENONFINITE
+    sim.sync()                       # reported once, then cleared
+    # a finite state restored: further steps are clean
+    sim.set_state(torch.from_numpy(inp["x0"]), torch.from_numpy(inp["c0"]), 0)
+    sim.step(2)
+    sim.sync()
+
+
+def test_positivity_warning():
+    """dt' (gamma + upsilon) >= 1 at a node sets PC_WARN_POSITIVITY."""
+    import dataclasses
+    from paper_1805_11007_amd._lib import PC_WARN_POSITIVITY
+    w = W.scaled(W.workload(W.PERIODIC_1K), n_agents=500, grid_n=16)
+    inp = W.make_inputs(w)
+    sim = make_sim(w, inp)
+    sim.step(2)
+    assert not sim.warnings() & PC_WARN_POSITIVITY
+    w2 = dataclasses.replace(w, gamma=2.0 / w.dt)   # dt gamma = 2
+    sim2 = make_sim(w2, inp)
+    sim2.step(1)
+    assert sim2.warnings() & PC_WARN_POSITIVITY
+
+
+def test_walls_keep_agents_in_box():
     w = W.scaled(W.workload(W.WALLS_100K), n_agents=20000, grid_n=65)
     inp = W.make_inputs(w)
     x0 = inp["x0"].copy()

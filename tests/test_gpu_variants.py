@@ -78,20 +78,32 @@ def test_one_step(name, n, g, kw):
 def test_one_step_full_size(name, kw):
     """The full 100k walls and 1M 3D workloads with each variant as the
     benchmark runs it (default launch).  Positions against the oracle's
-    step; the field against the oracle's deposit and PDE at the device's own
-    new positions (on a 512^2 grid one agent's deposit weighs enough for a
-    position difference within the bar to show in the field), within 1e-5
-    max|c| plus the float32 rounding bound of the deposit weights."""
+    step (1e-5 L).  Exponential and tamed: the field against the oracle's
+    step and against its deposit and PDE at the device's own new positions
+    (1e-5 max|c|).  Hard spheres: the correction maps a near-coincident
+    pair's distance r to 2d - r, so a rounding difference in r moves both
+    agents, and on the 512^2 grid one agent's deposit weighs enough for such
+    a move (inside the position bar) to show in the field; its field is
+    compared at the device's own positions, within 1e-5 max|c| plus the
+    float32 rounding bound of the deposit weights."""
     w = dataclasses.replace(W.workload(name), **kw)
     inp = W.make_inputs(w)
     sim = make_sim(w, inp)
     sim.step(1)
     x, c, _ = sim.get_state()
-    x = x.cpu().numpy()
-    Xo, _ = oracle.run_workload(w, inp, 1)
-    assert pos_err(x, Xo, w.L, w.periodic) <= 1e-5
+    x, c = x.cpu().numpy(), c.cpu().numpy()
+    Xo, co = oracle.run_workload(w, inp, 1)
+    ex = pos_err(x, Xo, w.L, w.periodic)
     c_ref = field_from_positions(w, inp["c0"], x, inp["species0"])
-    assert field_ok(c.cpu().numpy(), c_ref, w, x, inp["species0"])
+    ec, ecp = field_err(c, co), field_err(c, c_ref)
+    print(f"{name} {kw}: position err {ex:.2e} field err {ec:.2e} "
+          f"(at device positions {ecp:.2e})")
+    assert ex <= 1e-5
+    if kw.get("potential") == 2:
+        assert field_ok(c, c_ref, w, x, inp["species0"])
+    else:
+        assert ec <= 1e-5
+        assert ecp <= 1e-5
 
 
 @pytest.mark.parametrize("name,n,g,kw,steps", [

@@ -82,3 +82,31 @@ def test_validation_of_variant_parameters():
     for over in bad:
         with pytest.raises(PcError):
             workspace_bytes(_spec(**over))
+
+
+def test_create_reports_enospace_and_bad_workspace_before_any_device_work():
+    """pc_create validates the workspace on the host before it enqueues
+    anything: a workspace one byte short gives PC_ENOSPACE, a misaligned one
+    PC_EINVAL.  The device pointers are never dereferenced on these paths
+    (placeholders are passed), so no GPU is needed."""
+    import ctypes as C
+    from paper_1805_11007_amd import _lib
+    from paper_1805_11007_amd._lib import PC_EINVAL, PC_ENOSPACE
+    if not _lib.LIB_PATH.exists():
+        pytest.skip("libpc.so not built")
+    L = _lib.load()
+    cfg, sp, ns, inst, ni = _spec().c_structs()
+    need = L.pc_workspace_bytes(C.byref(cfg), sp, ns, inst, ni)
+    assert need > 0
+    out = C.c_void_p()
+    fake = C.c_void_p(1 << 20)      # 256-byte aligned placeholder, never touched
+    rc = L.pc_create(C.byref(cfg), sp, ns, inst, ni, fake, need - 1, fake, fake, fake, None,
+                     C.byref(out))
+    assert rc == PC_ENOSPACE and not out.value
+    assert b"workspace too small" in L.pc_last_error()
+    rc = L.pc_create(C.byref(cfg), sp, ns, inst, ni, C.c_void_p((1 << 20) + 16), need, fake,
+                     fake, fake, None, C.byref(out))
+    assert rc == PC_EINVAL and not out.value
+    rc = L.pc_create(C.byref(cfg), sp, ns, inst, ni, fake, need, None, fake, fake, None,
+                     C.byref(out))
+    assert rc == PC_EINVAL and not out.value
