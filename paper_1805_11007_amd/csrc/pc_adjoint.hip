@@ -290,7 +290,7 @@ k_adj_agent(StepParams p, AdjArgs A, const InstInfo *__restrict__ inst,
         float ly[3] = {0.f, 0.f, 0.f};
 #pragma unroll
         for (int a = 0; a < DIM; ++a) {
-            const float y = pc[a] + p.dt * (fv.F[a] + chi * Ig[a]) + amp * xi[a];
+            const float y = pc[a] + (p.dt * (fv.F[a] + chi * Ig[a]) + amp * xi[a]);
             const bool refl = !p.periodic && (y < 0.0f || y > p.L);
             ly[a] = refl ? -lam[a] : lam[a];
         }
@@ -427,10 +427,9 @@ k_adj_grad(PdeParams q, float inv_2h, const float *__restrict__ mu0,
 
 template <int DIM>
 __device__ __forceinline__ void hist_cell(const LossArgs &a, float x, int &i0, int &i1, float &t) {
-    const float s = fmaxf(x * a.inv_hh, 0.0f);
-    const float fi = fminf(floorf(s), (float)(a.m - 1));
+    float fi;
+    t = cell_offset(x, a.inv_hh, (float)(a.m - 1), fi);   // as cell_of
     i0 = (int)fi;
-    t = fmaf(x, a.inv_hh, -fi);   // one rounding, as cell_of
     i1 = i0 + 1 == a.m ? 0 : i0 + 1;
 }
 

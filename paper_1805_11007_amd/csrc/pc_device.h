@@ -484,16 +484,29 @@ __device__ __forceinline__ void pair_loop(const StepParams &p, const SpTab &tab,
 // The offset t = x / h - i0 is formed with one rounding, fma(x, 1/h, -i0).
 // Where the float32 1/h is exact (an integer for L = 1: 128, 511, 51, ...)
 // t is the exact offset rounded once, accurate to an ulp of t rather than
-// of x / h.  Where x / h rounds up to an integer the floor is one too high
-// and t comes out a hair below 0; the weights stay continuous.
+// of x / h.  Where x / h rounds up to an integer k from just below it, the
+// floor of the rounded quotient is one too high and t comes out a hair
+// below 0: the agent then belongs to cell k - 1 with t = 1 - (that hair).
+// The final clamp keeps every weight in [0, 1] (a weight below zero would
+// turn into a huge fixed-point deposit), also at a wall's last cell.
 struct Cell { int i0, i1; float t; };
 
+__device__ __forceinline__ float cell_offset(float x, float inv_h, float top, float &fi) {
+    const float s = fmaxf(x * inv_h, 0.0f);
+    fi = fminf(floorf(s), top);
+    float t = fmaf(x, inv_h, -fi);
+    if (t < 0.0f && fi > 0.0f) {
+        fi -= 1.0f;
+        t += 1.0f;
+    }
+    return __builtin_amdgcn_fmed3f(t, 0.0f, 1.0f);
+}
+
 __device__ __forceinline__ Cell cell_of(const StepParams &p, float x) {
-    const float s = fmaxf(x * p.inv_h, 0.0f);
-    const float fi = fminf(floorf(s), p.cell_top);
+    float fi;
     Cell c;
+    c.t = cell_offset(x, p.inv_h, p.cell_top, fi);
     c.i0 = (int)fi;
-    c.t = fmaf(x, p.inv_h, -fi);
     c.i1 = c.i0 + 1;
     if (p.periodic && c.i1 == p.grid_n) c.i1 = 0;
     return c;

@@ -358,9 +358,11 @@ k_update(StepParams p, const InstInfo *__restrict__ inst, const float4 *__restri
     const float amp = sel<NS>(p.amp, tab.amp, si);
     uint32_t flag = 0;
     float4 xn;
-    xn.x = boundary(p, pi.x + p.dt * (F[0] + drift[0]) + amp * xi[0], flag);
-    xn.y = boundary(p, pi.y + p.dt * (F[1] + drift[1]) + amp * xi[1], flag);
-    xn.z = DIM == 3 ? boundary(p, pi.z + p.dt * (F[2] + drift[2]) + amp * xi[2], flag) : 0.0f;
+    // the increment is summed first and added to the position once, so the
+    // new position carries a single rounding at its own scale
+    xn.x = boundary(p, pi.x + (p.dt * (F[0] + drift[0]) + amp * xi[0]), flag);
+    xn.y = boundary(p, pi.y + (p.dt * (F[1] + drift[1]) + amp * xi[1]), flag);
+    xn.z = DIM == 3 ? boundary(p, pi.z + (p.dt * (F[2] + drift[2]) + amp * xi[2]), flag) : 0.0f;
     xn.w = pi.w;
     if (p.has_react) {
         // type switch (eq. Chemo_reactions, fixed-step rule): one more Philox

@@ -222,3 +222,56 @@ def test_trajectory(name, steps):
     ec = field_err(sim.field().cpu().numpy(), cn)
     print(f"{name} {steps} steps: position err {ex:.3e} field err {ec:.3e}")
     assert ex <= 1e-5 * steps and ec <= 1e-5 * steps
+
+
+def _rounded_up_coords(n_cells, inv_h, L):
+    """float32 coordinates x just below a node plane k h whose float32
+    product x * (1/h) rounds up to the integer k (exactly below it in real
+    arithmetic): the cell is k - 1 with offset 1 - tiny."""
+    out = []
+    for k in range(1, n_cells):
+        x = np.float32(k * (L / n_cells))
+        for _ in range(4):
+            x = np.nextafter(x, np.float32(-1.0), dtype=np.float32)
+            if float(x) * float(inv_h) < k and np.float32(x) * np.float32(inv_h) == np.float32(k):
+                out.append(x)
+    return np.array(out, np.float32)
+
+
+@pytest.mark.parametrize("dim,periodic,grid_n,det",
+                         [(3, True, 48, False), (3, True, 48, True), (2, False, 51, False),
+                          (2, True, 37, False)])
+def test_deposit_where_quotient_rounds_to_a_node(dim, periodic, grid_n, det):
+    """Particle-in-cell deposit (Sect. 2.3) of agents sitting a float32 ulp
+    below node planes, where x / h rounds up to the node's index: each
+    weight must stay in [0, 1] (no fixed-point wrap of a negative weight).
+    The agents do not move (D = 0, chi = 0, k = 0), so the deposit is taken
+    at exactly these positions; a source and an uptake species."""
+    base = W.workload(W.WALLS_100K)
+    sp = (W.Species(0.002, 0.0, 0.0, 1.0, 0.0), W.Species(0.002, 0.0, 0.0, 0.0, 1.0))
+    n_cells = grid_n if periodic else grid_n - 1
+    L = 1.0
+    inv_h = np.float32(n_cells / L)
+    xs = _rounded_up_coords(n_cells, inv_h, L)
+    assert len(xs) >= 3
+    rng = np.random.default_rng(7)
+    n = 3 * len(xs) * dim
+    x0 = rng.uniform(0.0, L, size=(n, dim)).astype(np.float32)
+    for a in range(dim):  # every axis gets every adversarial coordinate
+        sl = slice(a * 3 * len(xs), (a + 1) * 3 * len(xs))
+        x0[sl, a] = np.tile(xs, 3)
+    x0 = np.ascontiguousarray(x0)
+    w = W.Workload("rounded_planes", dim, periodic, L, grid_n, 1e-4, 0.0, 1.0, 0.1, 1, sp,
+                   (W.Instance(n, 77),), species_rule="halves", c0="sin" if periodic else "cos")
+    inp = W.make_inputs(w)
+    inp["x0"] = x0
+    sim = make_sim(w, inp, deterministic=det)
+    sim.step(1)
+    sim.sync()
+    x = sim.positions().cpu().numpy()
+    c = sim.field().cpu().numpy()
+    assert np.array_equal(x, x0)
+    X1, c1 = oracle_steps(w, inp, 1)
+    ec = field_err(c, c1)
+    print(f"dim {dim} periodic {periodic} n {grid_n}: {len(xs)} coordinates, field err {ec:.2e}")
+    assert ec <= 1e-5
