@@ -4,7 +4,9 @@
 * the smoothed histogram keeps total mass 1 and maps a constant to itself;
 * the analytic position gradient matches central finite differences;
 * FD of the loss in theta is smooth enough to have a plateau (sanity of the
-  finite-difference reference used by the GPU adjoint tests).
+  finite-difference reference used by the GPU adjoint tests);
+* the float32 conditioning of the differentiation workload's segment
+  derivatives: well inside 1e-3 over one step, percents over 20.
 """
 import math
 
@@ -94,3 +96,41 @@ def test_theta_finite_differences_have_a_plateau(oracle_lib):
                         oracle.loss_at(w, inp, tm, target, 10, m, 2.0)) / (2 * h))
         scale = max(abs(fds[0]), 1e-12)
         assert abs(fds[0] - fds[1]) <= 2e-2 * scale + 1e-10
+
+
+def test_differentiation_segment_derivatives_float32_conditioning():
+    """Why the reverse-mode gate of a 20-step segment of the differentiation
+    workload carries the derivative's own float32 conditioning.  On the
+    oracle alone, the scale derivatives (chi, k, D) of three linear
+    functionals (displacements with random weights, the field with random
+    node weights, a smooth field moment) are compared along the FP64
+    trajectory and along trajectories perturbed by half a float32 ulp per
+    step: over one step they agree far inside the 1e-3 bar, over 20 steps
+    some differ by more than 1e-2."""
+    from adjoint_ref import segment_fd_ensemble
+    w = W.adjoint_2d()
+    inp = W.make_inputs(w)
+    rng = np.random.default_rng(4000)
+    wX = rng.standard_normal((w.n_total, 2))
+    wC = rng.standard_normal(w.n_nodes)
+    xs = W.node_coords(w)
+    gx, gy = np.meshgrid(xs, xs, indexing="xy")
+    wS = (np.sin(2 * np.pi * gx) * np.cos(2 * np.pi * gy)).reshape(-1)
+    x64 = inp["x0"].astype(np.float64)
+
+    def funcs(X, c):
+        d = X - x64
+        d -= np.rint(d)
+        return [float((wX * d).sum()), float((wC * c).sum()), float((wS * c).sum())]
+
+    theta = np.array([1.0, 100.0, 1.0])
+    worst = {}
+    for K in (1, 20):
+        fd0, mem = segment_fd_ensemble(w, inp["x0"], inp["species0"], inp["c0"], 0, K, theta,
+                                       funcs, M=2, seed=7)
+        sig = np.sqrt(((mem - fd0) ** 2).mean(0))
+        nz = np.abs(fd0) > 0
+        worst[K] = float((sig[nz] / np.abs(fd0[nz])).max())
+    print(f"float32 conditioning, worst of 9: 1 step {worst[1]:.1e}, 20 steps {worst[20]:.1e}")
+    assert worst[1] < 2e-4
+    assert worst[20] > 1e-2
