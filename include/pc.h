@@ -96,9 +96,19 @@ typedef struct {
                                LDS before the device atomics; 2: device atomics only;
                                3: deposit and PDE substeps of each instance in one
                                work-group, with the deposit sums in LDS (needs them to
-                               fit: 8 bytes x grid_n^dim x (2 with uptake, else 1)).
-                               The deposit is an integer sum, so every mode gives the
-                               same bits                                                */
+                               fit: 8 bytes x grid_n^dim x (2 with uptake, else 1));
+                               4: owner-computes slabs: the step sorts X^{n+1} before
+                               the deposit, and one work-group per slab of nodes
+                               (whole x rows, a few y rows and z layers) gathers the
+                               agents of its cells through that cell list into LDS and
+                               stores each node once, with no device atomics; with one
+                               PDE substep it also updates its nodes' field (the
+                               deposit never reaches HBM).  Rejected (PC_EINVAL) when
+                               bins are so much finer than the grid that a slab's bin
+                               layers exceed its run table.  Automatic mode picks 3
+                               for batches of >= 64 instances whose sums fit, else 4
+                               in 3D, else 1 or 2 by agents per node.  The deposit is
+                               an integer sum, so every mode gives the same bits        */
     int32_t deposit_kernel; /* 0: particle-in-cell (piecewise-linear weights);
                                1: Gaussian kernel density (Sect. 2.3): at node p,
                                sigma = sum_i source_i K(p - X_i), upsilon likewise,
@@ -109,7 +119,7 @@ typedef struct {
                                over the cell list of X^{n+1} in a fixed order; in 3D
                                otherwise scattered from the agents by float atomics
                                (last bits vary run to run).  deposit_mode is then
-                               ignored (3 is rejected)                                */
+                               ignored (3 and 4 are rejected)                          */
     int32_t reserved;
     double kde_radius;      /* truncation radius in bandwidths (0: 3); kde_radius times
                                the largest diameter must be < L/2                       */
@@ -286,7 +296,8 @@ typedef struct {
     int32_t block;
     double bin_side;
     size_t workspace_bytes;
-    int32_t deposit_path;   /* deposit_mode in effect (1, 2 or 3; never 0)  */
+    int32_t deposit_path;   /* deposit in effect: 1, 2, 3 or 4 as deposit_mode (slabs
+                               report 5), 4 for the kernel density; never 0          */
     int32_t reserved;
 } pc_info_t;
 int pc_info(pc_sim *sim, pc_info_t *info);

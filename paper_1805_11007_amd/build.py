@@ -16,7 +16,8 @@ PKG = Path(__file__).resolve().parent
 ROOT = PKG.parent
 CSRC = PKG / "csrc"
 LIB = PKG / "libpc.so"
-SOURCES = ["pc_kernels.hip", "pc_adjoint.hip", "pc_stats.hip", "pc_kde.hip", "pc_api.cpp"]
+SOURCES = ["pc_kernels.hip", "pc_deposit.hip", "pc_adjoint.hip", "pc_stats.hip", "pc_kde.hip",
+           "pc_api.cpp"]
 ARCH = "gfx950"
 
 

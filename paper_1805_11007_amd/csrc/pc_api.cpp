@@ -83,8 +83,8 @@ int derive(const pc_config *cfg, const pc_species_t *sp, int ns, const pc_instan
     if (ns < 1 || ns > PC_MAX_SPECIES) return fail(PC_EINVAL, "1..8 species supported");
     if (ni < 1 || ni >= (1 << 24)) return fail(PC_EINVAL, "instance count out of range");
     if (cfg->bin_order != 0) return fail(PC_ENOTSUP, "only row-major bin order is built");
-    if (cfg->deposit_mode < 0 || cfg->deposit_mode > 3)
-        return fail(PC_EINVAL, "deposit_mode must be 0, 1, 2 or 3");
+    if (cfg->deposit_mode < 0 || cfg->deposit_mode > 4)
+        return fail(PC_EINVAL, "deposit_mode must be 0 .. 4");
     if (cfg->block != 0 && cfg->block != 64 && cfg->block != 128 && cfg->block != 256 &&
         cfg->block != 512 && cfg->block != 1024)
         return fail(PC_EINVAL, "block must be 0, 64, 128, 256, 512 or 1024");
@@ -136,8 +136,8 @@ int derive(const pc_config *cfg, const pc_species_t *sp, int ns, const pc_instan
     if (!(cfg->kde_radius >= 0) || !std::isfinite(cfg->kde_radius))
         return fail(PC_EINVAL, "kde_radius must be finite and >= 0");
     if (d.kde) {
-        if (cfg->deposit_mode == 3)
-            return fail(PC_EINVAL, "deposit_mode 3 is a particle-in-cell path");
+        if (cfg->deposit_mode == 3 || cfg->deposit_mode == 4)
+            return fail(PC_EINVAL, "deposit_modes 3 and 4 are particle-in-cell paths");
         if (d.kde_radius * d.contact_max >= cfg->L / 2)
             return fail(PC_EINVAL, "kde_radius * diameter must be < L/2");
         if (d.potential == 2)
@@ -268,6 +268,8 @@ struct pc_sim {
     // sorted:  P[sorted_src] / start hold the cell-sorted current positions
     int binned, sorted, sorted_src;
     int chem_fused;           // deposit + PDE in one per-instance kernel (k_chem_inst)
+    int slab;                 // owner-computes deposit by node slabs (k_chem_slabs) from
+                              // the sorted X^{n+1}: the step sorts after the update
 };
 
 static void fill_params(pc_sim *s) {
@@ -471,6 +473,16 @@ static void enqueue_chem(pc_sim *s, hipStream_t st) {
     }
 }
 
+// Owner-computes deposit by node slabs from the sorted X^{n+1}; with one PDE
+// substep the same kernel updates the field (and advances the step counter),
+// otherwise it stores the deposits for the substeps.
+static void enqueue_slabs(pc_sim *s, hipStream_t st) {
+    const int fuse = s->d.n_sub == 1 ? 1 : 0;
+    launch_chem_slabs(s->sp, s->pp, s->b, s->sorted_src, s->cur_c, fuse, st);
+    if (fuse) s->cur_c = 1 - s->cur_c;
+    else enqueue_pde(s, st);
+}
+
 static void enqueue_step(pc_sim *s, hipStream_t st) {
     ensure_sorted(s, st);
     launch_update(s->sp, s->b, s->sorted_src, 0, s->cur_c, s->d.block, st);
@@ -494,6 +506,14 @@ static void enqueue_step(pc_sim *s, hipStream_t st) {
         enqueue_pde(s, st);
         return;
     }
+    if (s->slab) {
+        // the slab deposit gathers through the cell list of X^{n+1}
+        s->binned = 1;
+        s->sorted = 0;
+        ensure_sorted(s, st);
+        enqueue_slabs(s, st);
+        return;
+    }
     enqueue_chem(s, st);
     s->binned = 1;
     s->sorted = 0;
@@ -502,7 +522,7 @@ static void enqueue_step(pc_sim *s, hipStream_t st) {
 // The state a step leaves: binned (counts of X^{n+1} kept for the next
 // step's scan), or sorted already when the deposit gathers per node.
 static int is_steady(const pc_sim *s) {
-    return s->d.kde ? (s->sorted && !s->binned) : (s->binned && !s->sorted);
+    return (s->d.kde || s->slab) ? (s->sorted && !s->binned) : (s->binned && !s->sorted);
 }
 
 static int common_create(const pc_config *cfg, const pc_species_t *species, int n_species,
@@ -555,6 +575,16 @@ static int common_create(const pc_config *cfg, const pc_species_t *species, int 
         }
         s->chem_fused = !d.kde && (cfg->deposit_mode == 3 ||
                                    (cfg->deposit_mode == 0 && fits && d.ni >= kFusedMinInstances));
+        // the slab deposit: its LDS sums and run table must fit, and the
+        // bins per cell must leave a slab few enough runs
+        const size_t slab_lds = chem_slab_lds_bytes(s->sp);
+        const bool slab_ok = !d.kde && !s->chem_fused && slab_lds > 0 &&
+                             slab_lds + 8192 <= (size_t)max_lds;
+        if (cfg->deposit_mode == 4 && !slab_ok) {
+            delete s;
+            return fail(PC_EINVAL, "deposit_mode 4: the node slabs do not fit this grid");
+        }
+        s->slab = slab_ok && (cfg->deposit_mode == 4 || (cfg->deposit_mode == 0 && d.dim == 3));
     }
     carve(s, (char *)workspace_dev);
     s->inst_host.resize(n_inst);
@@ -731,7 +761,7 @@ int pc_profile_steps(pc_sim *s, int n_steps, double *stage_ms) {
     double acc[PC_N_STAGES] = {0};
     // with the per-node density gather a step starts sorted; the sort of
     // the initial state belongs to no step
-    if (s->d.kde) ensure_sorted(s, st);
+    if (s->d.kde || s->slab) ensure_sorted(s, st);
     for (int t = 0; t < n_steps; ++t) {
         bool ran[PC_N_STAGES] = {false};
 #define PC_STAGE(K, BODY)                              \
@@ -775,6 +805,18 @@ int pc_profile_steps(pc_sim *s, int n_steps, double *stage_ms) {
             if (rc) return rc;
             PC_STAGE(PC_STAGE_DEPOSIT, enqueue_kde(s, st));
             PC_STAGE(PC_STAGE_PDE, enqueue_pde(s, st));
+        } else if (s->slab) {
+            rc = sort_stages();
+            if (rc) return rc;
+            if (s->d.n_sub == 1) {
+                // deposit and PDE in one kernel: its time is reported under
+                // the deposit
+                PC_STAGE(PC_STAGE_DEPOSIT, enqueue_slabs(s, st));
+            } else {
+                PC_STAGE(PC_STAGE_DEPOSIT, launch_chem_slabs(s->sp, s->pp, s->b, s->sorted_src,
+                                                             s->cur_c, 0, st));
+                PC_STAGE(PC_STAGE_PDE, enqueue_pde(s, st));
+            }
         } else if (s->chem_fused) {
             // one kernel for both: its time is reported under the deposit
             PC_STAGE(PC_STAGE_DEPOSIT, enqueue_chem(s, st));
@@ -888,6 +930,12 @@ int pc_sync(pc_sim *s) {
         HIP_OK(hipMemcpy(s->b.flags, &zero, 4, hipMemcpyHostToDevice));
         return fail(PC_EINVAL, "a species index >= n_species was replaced by 0");
     }
+    if (s->flags_host & FLAG_INTERNAL) {
+        s->flags_host &= ~FLAG_INTERNAL;
+        uint32_t zero = 0;
+        HIP_OK(hipMemcpy(s->b.flags, &zero, 4, hipMemcpyHostToDevice));
+        return fail(PC_EHIP, "internal: a kernel's bound check failed (deposit slab runs)");
+    }
     return PC_OK;
 }
 
@@ -911,7 +959,7 @@ int pc_info(pc_sim *s, pc_info_t *info) {
     info->block = s->d.block;
     info->bin_side = s->d.bin_side;
     info->workspace_bytes = s->lay.total;
-    info->deposit_path = s->d.kde ? 4 : s->chem_fused ? 3 : (s->sp.deposit_agg ? 1 : 2);
+    info->deposit_path = s->d.kde ? 4 : s->slab ? 5 : s->chem_fused ? 3 : (s->sp.deposit_agg ? 1 : 2);
     info->reserved = 0;
     return PC_OK;
 }

@@ -84,6 +84,7 @@ struct PdeParams {
 enum : uint32_t {
     FLAG_NONFINITE = 1u << 0,
     FLAG_BAD_SPECIES = 1u << 1,
+    FLAG_INTERNAL = 1u << 2,        // a kernel's own bound check failed (a library bug)
     FLAG_WARN_POSITIVITY = 1u << 8,
     FLAG_WARN_CLAMPED = 1u << 9,
     FLAG_WARN_REACTION = 1u << 10,
@@ -156,6 +157,11 @@ void launch_kde(const StepParams &p, const Buffers &b, int src, hipStream_t s);
 void launch_overlap(const StepParams &p, const Buffers &b, int src, int dst, int block,
                     hipStream_t s);
 size_t chem_inst_lds_bytes(const PdeParams &q);
+// owner-computes deposit by slabs of nodes (pc_deposit.hip); with fuse_pde
+// also the single PDE substep of the step (and the step counter)
+size_t chem_slab_lds_bytes(const StepParams &p);
+void launch_chem_slabs(const StepParams &p, const PdeParams &q, const Buffers &b, int src,
+                       int cur, int fuse_pde, hipStream_t s);
 void launch_chem_inst(const StepParams &p, const PdeParams &q, const Buffers &b, int src, int cur,
                       int n_sub, hipStream_t s);
 int launch_species_hist(const StepParams &p, const Buffers &b, int src, int m, float s,

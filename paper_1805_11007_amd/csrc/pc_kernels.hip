@@ -388,55 +388,6 @@ k_update(StepParams p, const InstInfo *__restrict__ inst, const float4 *__restri
     if (flag) atomicOr(flags, flag);
 }
 
-// Forward-Euler update of node l with the centred Laplacian (periodic wrap
-// or mirror ghost nodes) and the source / uptake densities sigma, upsilon
-// at the node.  The particle-in-cell densities are the fixed-point deposits
-// divided by the node control volume (the wrapper below); the kernel
-// density estimate gives densities directly.
-template <int DIM>
-__device__ __forceinline__ float pde_node_dens(const PdeParams &q, const float *__restrict__ cb,
-                                               const int ic[3], float sigma, float ups,
-                                               uint32_t &flag) {
-    const int n = q.grid_n, nn = n * n;
-    auto nbr = [&](int i, int off) {
-        const int r = i + off;
-        if (q.periodic) return r < 0 ? r + n : (r >= n ? r - n : r);
-        return r < 0 ? 1 : (r >= n ? n - 2 : r);
-    };
-    const int ix = ic[0], iy = ic[1], iz = ic[2];
-    const float c0 = cb[iz * nn + iy * n + ix];
-    const int rowo = iz * nn + iy * n;
-    float lap = (cb[rowo + nbr(ix, 1)] + cb[rowo + nbr(ix, -1)]) +
-                (cb[iz * nn + nbr(iy, 1) * n + ix] + cb[iz * nn + nbr(iy, -1) * n + ix]);
-    float diag = 4.0f;
-    if (DIM == 3) {
-        lap += cb[nbr(iz, 1) * nn + iy * n + ix] + cb[nbr(iz, -1) * nn + iy * n + ix];
-        diag = 6.0f;
-    }
-    lap = (lap - diag * c0) * q.inv_h2;
-    const float cn = c0 + q.dts * (q.D_c * lap + sigma - ups * c0 - q.gamma * c0);
-    if (!isfinite(cn)) flag |= FLAG_NONFINITE;
-    if (q.dts * (q.gamma + ups) >= 1.0f) flag |= FLAG_WARN_POSITIVITY;
-    return cn;
-}
-
-template <int DIM>
-__device__ __forceinline__ float pde_node(const PdeParams &q, const float *__restrict__ cb,
-                                          const int ic[3], unsigned long long sS,
-                                          unsigned long long sU, uint32_t &flag) {
-    const int n = q.grid_n;
-    float inv_v = 1.0f;
-    if (!q.periodic) {
-        if (ic[0] == 0 || ic[0] == n - 1) inv_v *= 2.0f;
-        if (ic[1] == 0 || ic[1] == n - 1) inv_v *= 2.0f;
-        if (DIM == 3 && (ic[2] == 0 || ic[2] == n - 1)) inv_v *= 2.0f;
-    }
-    const float dens = q.fx_to_density * inv_v;
-    const float sigma = (float)sS * dens;
-    const float ups = q.has_uptake ? (float)sU * dens : 0.0f;
-    return pde_node_dens<DIM>(q, cb, ic, sigma, ups, flag);
-}
-
 // Piecewise-linear deposit (fixed point, 2^-32 units) of every agent at its
 // new position, one thread per agent.  The 2^dim corner contributions of a
 // work-group's agents (contiguous in cell-sorted order, hence spatially

@@ -250,6 +250,21 @@ def test_error_paths():
 
 
 def _dep_case(name, n, g):
+    import dataclasses
+    if name == "3d_walls":
+        return dataclasses.replace(W.scaled(W.workload(W.BLOBS_1M), n_agents=n, grid_n=g),
+                                   periodic=False, c0="cos")
+    if name == "3d_batch":
+        w = W.scaled(W.workload(W.BLOBS_1M), n_agents=[n, n // 3, 7], grid_n=g)
+        return dataclasses.replace(w, species=(W.Species(0.004, 1.0, 1.0, 1.0, 0.0),
+                                               W.Species(0.006, 0.5, 2.0, 0.3, 1.0)),
+                                   species_rule="halves")
+    if name == "3d_uniform_sparse":
+        # agents far sparser than bins: a 1024-agent work-group touches more
+        # node rows than the row-window table holds (the overflow path)
+        import dataclasses
+        return dataclasses.replace(W.scaled(W.workload(W.BLOBS_1M), n_agents=n, grid_n=g),
+                                   layout="uniform")
     if name == W.ENSEMBLE_256:
         return W.scaled(W.workload(W.ENSEMBLE_256),
                         n_agents=list(np.random.default_rng(7).integers(1, 600, 70)), grid_n=g)
@@ -259,13 +274,16 @@ def _dep_case(name, n, g):
 
 
 @pytest.mark.parametrize("name,n,g,modes", [
-    (W.BLOBS_1M, 40000, 32, (2,)), (W.WALLS_100K, 20011, 129, (2,)),
-    (W.PERIODIC_1K, 3001, 37, (2, 3)), (W.ENSEMBLE_256, None, 24, (2, 3)),
-    (W.ADJOINT_50K, 3000, 32, (2, 3)), (W.FIG1_2000, 70, None, (2, 3))])
+    (W.BLOBS_1M, 40000, 32, (2, 4)), (W.WALLS_100K, 20011, 129, (2, 4)),
+    ("3d_uniform_sparse", 60000, 64, (2, 4)), ("3d_walls", 30011, 33, (2, 4)),
+    ("3d_batch", 9001, 20, (2, 4)),
+    (W.PERIODIC_1K, 3001, 37, (2, 3, 4)), (W.ENSEMBLE_256, None, 24, (2, 3, 4)),
+    (W.ADJOINT_50K, 3000, 32, (2, 3, 4)), (W.FIG1_2000, 70, None, (2, 3, 4))])
 def test_deposit_modes_bitwise_equal(name, n, g, modes):
-    """The deposit is an integer sum: LDS-aggregated, direct-atomic and
-    per-instance fused (deposit + PDE substeps in one work-group) paths give
-    the same bits, step after step."""
+    """The deposit is an integer sum: LDS-aggregated, direct-atomic,
+    per-instance fused (deposit + PDE substeps in one work-group) and
+    owner-computes slab (gathered through the cell list of X^{n+1}, fused
+    with a single PDE substep) paths give the same bits, step after step."""
     w = _dep_case(name, n, g)
     inp = W.make_inputs(w)
     a = make_sim(w, inp, deterministic=True, deposit_mode=1)
@@ -274,11 +292,25 @@ def test_deposit_modes_bitwise_equal(name, n, g, modes):
     xa, ca = _state(a)
     for m in modes:
         b = make_sim(w, inp, deterministic=True, deposit_mode=m)
-        assert b.info["deposit_path"] == m
+        assert b.info["deposit_path"] == (5 if m == 4 else m)
         b.step(7)
         xb, cb = _state(b)
         assert np.array_equal(xa, xb) and np.array_equal(ca, cb), m
         b.close()
+
+
+def test_slab_path_default_in_3d_and_rejected_for_bins_far_finer_than_the_grid():
+    from paper_1805_11007_amd import PcError
+    w = W.scaled(W.workload(W.BLOBS_1M), n_agents=2000, grid_n=24)
+    assert make_sim(w, W.make_inputs(w)).info["deposit_path"] == 5
+    # 6^3 grid with bins of side 0.004 (249 per axis): ~42 bins per cell,
+    # more bin layers per slab than its run table holds
+    w = W.scaled(W.workload(W.BLOBS_1M), n_agents=2000, grid_n=6)
+    side = 0.004 * 1.0002
+    sim = make_sim(w, W.make_inputs(w), bin_size=side)
+    assert sim.info["bins_per_axis"] == 249 and sim.info["deposit_path"] != 5
+    with pytest.raises(PcError):
+        make_sim(w, W.make_inputs(w), bin_size=side, deposit_mode=4)
 
 
 def test_fused_path_chosen_for_many_small_instances_and_rejected_when_too_big():
