@@ -377,6 +377,23 @@ size_t pc_density_loss_work_bytes(pc_sim *sim, int hist_n);
 int pc_density_loss(pc_sim *sim, const float *target_dev, int hist_n, double sigma_bins,
                     void *work_dev, size_t work_bytes, double *loss_out, float *dLdX_dev);
 
+/* pc_density_loss without a caller buffer, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  The histogram, smoothing buffers
+ * and per-instance sums live in a file-scope static device array of 4 MiB
+ * (one per GPU, held until the process ends), so the call allocates nothing
+ * and takes only the inputs and outputs of pc_density_loss:
+ *   target_dev, hist_n, sigma_bins, loss_out, dLdX_dev: as pc_density_loss.
+ * Limit: pc_density_loss_work_bytes(sim, hist_n) <= 4 MiB, i.e. n_inst *
+ * hist_n^dim up to about 262,000 histogram nodes (PC_ENOSPACE beyond).  The
+ * array is cleared by kernels at the start of every call.  Every call on one
+ * GPU shares that GPU's array: calls that overlap on one GPU (from several
+ * host threads or streams) race, so the caller serialises them.  Errors as
+ * pc_density_loss, plus PC_EHIP if the array's device address cannot be
+ * found.  Synchronises the stream. */
+int pc_density_loss_noalloc(pc_sim *sim, const float *target_dev, int hist_n, double sigma_bins,
+                            double *loss_out, float *dLdX_dev);
+
 /* The smoothed histogram rho_s of the loss above (float32, n_inst x
  * hist_n^dim) into rho_out_dev, e.g. to build a target from a reference run.
  * Same arguments and errors as pc_density_loss. */

@@ -19,7 +19,7 @@ EXPORTS = (
     "pc_positions", "pc_field", "pc_species", "pc_get_state", "pc_set_state", "pc_set_species", "pc_ensemble_stats", "pc_sync",
     "pc_warnings", "pc_info", "pc_destroy", "pc_strerror", "pc_last_error",
     "pc_debug_neighbours", "pc_debug_forces", "pc_adjoint_segment", "pc_profile_steps",
-    "pc_density_loss_work_bytes", "pc_density_loss", "pc_density_hist",
+    "pc_density_loss_work_bytes", "pc_density_loss", "pc_density_loss_noalloc", "pc_density_hist",
 )
 STAGES = ("bin", "scan", "scatter", "stable", "update", "deposit", "pde", "overlap")
 
@@ -101,6 +101,7 @@ def load() -> C.CDLL:
         "pc_density_loss_work_bytes": ([vp, i32], C.c_size_t),
         "pc_density_loss": ([vp, vp, i32, C.c_double, vp, C.c_size_t, C.POINTER(C.c_double),
                              vp], i32),
+        "pc_density_loss_noalloc": ([vp, vp, i32, C.c_double, C.POINTER(C.c_double), vp], i32),
         "pc_density_hist": ([vp, i32, C.c_double, vp, C.c_size_t, vp], i32),
     }
     for name, (args, res) in sigs.items():

@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -1159,6 +1160,61 @@ int pc_density_loss(pc_sim *s, const float *target_dev, int hist_n, double sigma
                     void *work_dev, size_t work_bytes, double *loss_out, float *dLdX_dev) {
     if (!s || !target_dev || !work_dev || !loss_out) return fail(PC_EINVAL, "null argument");
     return density_common(s, target_dev, hist_n, sigma_bins, work_dev, work_bytes, loss_out,
+                          dLdX_dev, nullptr);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Static scratch of pc_density_loss_noalloc: the loss histogram, two
+// smoothing buffers and the per-instance sums in a file-scope device array,
+// so that the call needs no caller buffer and allocates nothing.  Each GPU
+// holds its own copy for the life of the process; its address is looked up
+// once per device (hipGetSymbolAddress, with that device current) and only
+// that address is ever handed to kernels.
+// ---------------------------------------------------------------------------
+constexpr size_t kLossScratchBytes = (size_t)4 << 20;
+static __device__ __align__(256) unsigned char scratch[kLossScratchBytes];
+
+namespace {
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxScratchDevices] = {};
+
+int loss_scratch(int device, void **out) {
+    if (device < 0 || device >= kMaxScratchDevices)
+        return fail(PC_EINVAL, "device index beyond the static scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        int prev = -1;
+        HIP_OK(hipGetDevice(&prev));
+        if (prev != device) HIP_OK(hipSetDevice(device));
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (prev != device) (void)hipSetDevice(prev);
+        if (e != hipSuccess || !ptr)
+            return fail(PC_EHIP, std::string("hipGetSymbolAddress(scratch) failed: ") +
+                                     hipGetErrorString(e));
+        g_scratch_ptr[device] = ptr;
+    }
+    *out = g_scratch_ptr[device];
+    return PC_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int pc_density_loss_noalloc(pc_sim *s, const float *target_dev, int hist_n, double sigma_bins,
+                            double *loss_out, float *dLdX_dev) {
+    if (!s || !target_dev || !loss_out) return fail(PC_EINVAL, "null argument");
+    const size_t need = pc_density_loss_work_bytes(s, hist_n);
+    if (need == 0) return fail(PC_EINVAL, "hist_n must be >= 2");
+    if (need > kLossScratchBytes)
+        return fail(PC_ENOSPACE, "n_inst * hist_n^dim exceeds the 4 MiB static loss scratch");
+    void *ws = nullptr;
+    const int rc = loss_scratch(s->device, &ws);
+    if (rc) return rc;
+    return density_common(s, target_dev, hist_n, sigma_bins, ws, kLossScratchBytes, loss_out,
                           dLdX_dev, nullptr);
 }
 

@@ -286,6 +286,26 @@ class Sim:
                                         _ptr(g) if grad else C.c_void_p(0)))
         return np.array(list(loss)), g
 
+    def density_loss_noalloc(self, target: torch.Tensor, hist_n: int = 64,
+                             sigma_bins: float = 2.0, dLdX: torch.Tensor | None = None):
+        """density_loss through pc_density_loss_noalloc: the library uses its
+        static scratch, so nothing is allocated for the call (target and the
+        optional dL/dX output must already be float32 device tensors)."""
+        import numpy as np
+        if (target.dtype != torch.float32 or target.device != self.device
+                or not target.is_contiguous()):
+            raise ValueError("target must be a contiguous float32 tensor on the handle's device")
+        if dLdX is not None and (dLdX.dtype != torch.float32 or dLdX.device != self.device
+                                 or not dLdX.is_contiguous()):
+            raise ValueError("dLdX must be a contiguous float32 tensor on the handle's device")
+        ni = len(self.spec.instances)
+        loss = (C.c_double * ni)()
+        LB.check(self.L.pc_density_loss_noalloc(self.h, _ptr(target), int(hist_n),
+                                                float(sigma_bins), loss,
+                                                _ptr(dLdX) if dLdX is not None
+                                                else C.c_void_p(0)))
+        return np.array(list(loss))
+
     def density_hist(self, hist_n: int = 64, sigma_bins: float = 2.0) -> torch.Tensor:
         """Smoothed position histogram of the loss (n_inst x hist_n^dim)."""
         nb = int(self.L.pc_density_loss_work_bytes(self.h, int(hist_n)))
