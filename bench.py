@@ -2,21 +2,27 @@
 """Benchmark of the hybrid chemotaxis step on one MI355X.
 
 Workload: the 3D periodic run with 1,000,000 agents in 8 Gaussian blobs on a
-128^3 chemical grid (dt = 1e-7), stepped from its initial state.  W warm-up
+128^3 chemical grid (dt = 1e-7), stepped from its initial state with the
+bin side and work-group size the autotuner picks for that run.  W warm-up
 steps run first on the same handle, the state is then restored to the
 initial condition and exactly K steps are timed (HIP-graph replay, inputs
 already resident in HBM).  One JSON line is printed with:
 
 * value: particle-steps/s of the whole timed region;
-* roofline: the dominant kernel's algorithmic bytes per launch divided by
-  its mean launch time (HIP events between the stages of each step, on the
-  library's stream), against the 8 TB/s HBM peak;
+* roofline: the dominant kernel of the timed steps against the 8 TB/s HBM
+  peak: its algorithmic bytes per launch over its mean launch time (HIP
+  events between the stages of each step, on the library's stream, over
+  the same K steps from the same state), with its rocprofv3 counter bytes;
+* step_hbm: the whole step against HBM: the algorithmic floor of a step
+  (positions in and out, ids, the field and its deposits) over the step
+  time, and the counter bytes of all the step's kernels over the same time;
 * cpu_baseline: the FP64 oracle timed on the host cores on a bounded sample
-  of the same workload.
+  of the same workload (all threads, and one thread).
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -28,7 +34,8 @@ sys.path.insert(0, str(ROOT))
 
 METRIC = ("particle-steps/s (3D, 1M cells) + % HBM roofline; fwd+bwd and ensemble vs plain")
 HBM_PEAK_GBS = 8000.0
-FP32_PEAK_TFLOPS = 157.3      # MI355X FP32 vector (counts packed dual-issue)
+FP32_PEAK_TFLOPS = 157.3      # MI355X FP32 vector, counting packed (dual-issue) FMA
+FP32_ATTAINABLE_TFLOPS = 78.6  # without packed FP32 instructions (this build disables them)
 
 # Algorithmic float operations of the particle update, by definition of what
 # it computes: per neighbour pair, the float32 distance (3 sub, 3 mul, 2 add),
@@ -39,38 +46,46 @@ FP32_PEAK_TFLOPS = 157.3      # MI355X FP32 vector (counts packed dual-issue)
 # (~10) -> 140.  Integer Philox work is not counted.
 FLOP_PER_PAIR, FLOP_PER_AGENT = 18.0, 140.0
 
-# HBM bytes per launch of the update kernel on the 1M-agent 3D workload, from
-# rocprofv3 FETCH_SIZE and WRITE_SIZE runs (each scaled by the same counter's
-# reading for a plain device copy); valid only for the kernel sources they
-# were taken with, identified by a hash of those files.
-UPDATE_TRAFFIC_BYTES = 106.1e6
-# SQ_INSTS_VALU of the same kernel over the chip's issue capacity in its
-# GRBM_GUI_ACTIVE cycles (one wave64 VALU instruction per SIMD per 4 cycles)
-UPDATE_VALU_ISSUE = 0.60
-UPDATE_TRAFFIC_SOURCES = ("pc_internal.h", "pc_device.h", "pc_kernels.hip")
-UPDATE_TRAFFIC_SHA = "87878b9cb5f534dd"
+# rocprofv3 FETCH_SIZE and WRITE_SIZE of the kernels of one step on the 1M-
+# agent 3D workload, over the window the default run times (the first 20
+# steps after 5 warm-up steps; each counter in its own run, FETCH_SIZE scaled
+# by 2.0 and WRITE_SIZE by 1.0 from a plain device copy).  Bytes per step
+# (summed over the step's kernels) and per launch of the update kernel.
+# Valid only for the kernel sources they were taken with (a hash of every
+# file under csrc/) and for that workload; reported as null otherwise.
+COUNTER_STEP_BYTES = None
+COUNTER_UPDATE_BYTES = None
+COUNTER_SOURCES_SHA = None
+COUNTER_WORKLOAD = "3d_periodic_1M_blobs"
 
 
-def update_counters_valid(workload: str) -> bool:
-    """True while the update kernel's sources and the workload are those the
-    counters were taken with."""
-    import hashlib
-    if workload != "3d_periodic_1M_blobs":
-        return False
+def sources_sha() -> str:
     h = hashlib.sha256()
-    csrc = Path(__file__).resolve().parent / "paper_1805_11007_amd" / "csrc"
-    try:
-        for f in UPDATE_TRAFFIC_SOURCES:
-            h.update((csrc / f).read_bytes())
-    except OSError:
-        return False
-    return h.hexdigest()[:16] == UPDATE_TRAFFIC_SHA
+    csrc = ROOT / "paper_1805_11007_amd" / "csrc"
+    for f in sorted(csrc.iterdir()):
+        if f.suffix in (".hip", ".h", ".cpp"):
+            h.update(f.name.encode())
+            h.update(f.read_bytes())
+    return h.hexdigest()[:16]
 
 
-def update_traffic(workload: str):
-    """Counter traffic of the update kernel, or None if the kernel sources
-    changed since the counters were taken or the workload differs."""
-    return UPDATE_TRAFFIC_BYTES if update_counters_valid(workload) else None
+def counters_valid(workload: str, bin_side_mult: float | None = None) -> bool:
+    """True while the kernel sources and the workload are those the counter
+    figures were taken with."""
+    return (COUNTER_SOURCES_SHA is not None and workload == COUNTER_WORKLOAD
+            and sources_sha() == COUNTER_SOURCES_SHA)
+
+
+def floor_bytes(w) -> float:
+    """What one step must move by definition of the method, whatever the
+    kernels (N agents, G nodes, d = dim, F deposited fields: 1 without
+    uptake, else 2): read positions (4d) and ids / species (4), write
+    positions (4d); read and write the field (8 per node), write each
+    deposited field once and read it once (8F per node)."""
+    N, d = w.n_total, w.dim
+    G = w.n_inst * w.grid_n ** d
+    F = 2 if any(s.uptake > 0 for s in w.species) else 1
+    return float(N * (8 * d + 4) + G * (8 + 8 * F))
 
 
 def algorithmic_bytes(stage: str, w, n_sub: int) -> float:
@@ -103,22 +118,47 @@ def algorithmic_bytes(stage: str, w, n_sub: int) -> float:
     return 0.0
 
 
-def cpu_baseline(w, inp, budget_s: float = 12.0, max_steps: int = 40):
+def cpu_model() -> str:
+    try:
+        for line in Path("/proc/cpuinfo").read_text().splitlines():
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(w, inp, budget_s: float = 10.0, max_steps: int = 40,
+                 one_thread_budget_s: float = 8.0):
+    """The FP64 cell-list oracle on the same workload from the same initial
+    state: as many steps as fit in budget_s on all host threads, then on one
+    thread for about one_thread_budget_s.  Rates in particle-steps/s."""
     import oracle
-    p = oracle.params(w, 0, mode=1)
-    X, sp, c = inp["x0"], inp["species0"], inp["c0"]
-    steps, t0 = 0, time.perf_counter()
-    st = 0
-    while steps < max_steps:
-        X, c, st = oracle.step(p, X, sp, c, st)
-        steps += 1
-        if time.perf_counter() - t0 > budget_s:
-            break
-    el = time.perf_counter() - t0
+
+    def timed(budget, cap):
+        p = oracle.params(w, 0, mode=1)
+        X, sp, c = inp["x0"], inp["species0"], inp["c0"]
+        steps, st, t0 = 0, 0, time.perf_counter()
+        while steps < cap:
+            X, c, st = oracle.step(p, X, sp, c, st)
+            steps += 1
+            if time.perf_counter() - t0 > budget:
+                break
+        return steps, time.perf_counter() - t0
+
+    n_all = oracle.num_threads()
+    steps, el = timed(budget_s, max_steps)
+    oracle.set_threads(1)
+    try:
+        steps1, el1 = timed(one_thread_budget_s, max_steps)
+    finally:
+        oracle.set_threads(n_all)
     return {"value": w.n_total * steps / el, "unit": "particle-steps/s",
-            "cores": oracle.num_threads(), "kind": "oracle",
+            "cores": n_all, "kind": "oracle", "cpu_model": cpu_model(),
             "sample": f"first {steps} steps of the same workload, FP64 cell-list oracle, "
-                      f"{el:.1f} s"}
+                      f"{el:.1f} s on {n_all} threads",
+            "one_thread": {"value": w.n_total * steps1 / el1, "unit": "particle-steps/s",
+                           "cores": 1, "sample": f"first {steps1} steps, {el1:.1f} s"}}
 
 
 def _timed(fn) -> float:
@@ -170,8 +210,12 @@ def ensemble_leg(steps: int = 500, plain_steps: int = 50) -> dict:
         s1.close()
         off += n
     plain = tot_ps / (tot_ms / 1e3)
+    fb = floor_bytes(w)
     return {"workload": w.name, "instances": w.n_inst, "agents_total": w.n_total,
             "batched_particle_steps_per_s": batched, "batched_steps": steps,
+            "batched_ms_per_step": ms / steps,
+            "floor_bytes_per_step": fb,
+            "floor_frac": fb / (ms / steps * 1e-3) / 1e9 / HBM_PEAK_GBS,
             "plain_particle_steps_per_s": plain, "plain_steps_per_instance": plain_steps,
             "speedup_vs_plain": batched / plain,
             "tuned": {"bin_size": spec.bin_size, "block": spec.block,
@@ -402,21 +446,56 @@ def adjoint_leg(steps: int = 200, K: int = 20) -> dict:
             "grad_theta": theta.grad.tolist()}
 
 
+def configs_leg() -> dict:
+    """The other single-instance workloads, forward only (HIP-graph replay of
+    their full step count from the initial state, 2 warm-up steps): step time,
+    particle-steps/s and the step's algorithmic floor against HBM."""
+    import torch
+    import workloads as W
+    from paper_1805_11007_amd import ModelSpec, Sim
+    out = {}
+    for name in (W.PERIODIC_1K, W.WALLS_100K, W.ADJOINT_50K):
+        w = W.workload(name)
+        inp = W.make_inputs(w)
+        x0, s0, c0 = (torch.from_numpy(inp[k]).cuda() for k in ("x0", "species0", "c0"))
+        sim = Sim(ModelSpec.from_workload(w), x0, s0, c0)
+        sim.use_graph(True)
+        sim.step(2)
+        sim.set_state(x0, c0, 0)
+        ms = _timed(lambda: sim.step(w.steps)) / w.steps
+        sim.sync()
+        sim.set_state(x0, c0, 0)
+        prof = sim.profile_steps(min(w.steps, 200))
+        sim.close()
+        fb = floor_bytes(w)
+        out[name] = {"agents": w.n_total, "nodes": w.n_inst * w.grid_n ** w.dim,
+                     "steps": w.steps, "ms_per_step": ms,
+                     "particle_steps_per_s": w.n_total / (ms * 1e-3),
+                     "floor_bytes_per_step": fb, "floor_GBs": fb / (ms * 1e-3) / 1e9,
+                     "floor_frac": fb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                     "stage_ms": {k: round(v, 5) for k, v in prof.items() if v > 0}}
+    return out
+
+
 LEGS = {"ensemble": lambda: ensemble_leg(), "fig1": lambda: fig1_leg(), "kde": lambda: kde_leg(),
         "variants": lambda: variants_leg(),
-        "switching": lambda: reaction_overhead_leg(), "fwd_bwd": lambda: adjoint_leg()}
+        "switching": lambda: reaction_overhead_leg(), "fwd_bwd": lambda: adjoint_leg(),
+        "configs": lambda: configs_leg()}
 
 
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="3d_periodic_1M_blobs",
                     help="workload name (the workloads module lists them)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the ensemble and forward+backward legs")
+                    help="skip the full-run, per-workload, ensemble, forward+backward and "
+                         "variant legs")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="use the library's default bin side and work-group size")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run three plain 256 MiB device copies (the reference "
                          "kernel for scaling FETCH_SIZE / WRITE_SIZE counters)")
@@ -450,15 +529,23 @@ def main() -> int:
 
     import workloads as W
     from paper_1805_11007_amd import ModelSpec, Sim
+    from paper_1805_11007_amd.autotune import tune
 
     w = W.workload(args.workload)
     inp = W.make_inputs(w)
-    spec = ModelSpec.from_workload(w, deterministic=args.deterministic,
-                                   bin_size=args.bin_size, block=args.block)
     torch.cuda.set_device(0)
     x0 = torch.from_numpy(inp["x0"]).cuda()
     s0 = torch.from_numpy(inp["species0"]).cuda()
     c0 = torch.from_numpy(inp["c0"]).cuda()
+    spec = ModelSpec.from_workload(w, deterministic=args.deterministic,
+                                   bin_size=args.bin_size, block=args.block)
+    tune_rep = None
+    if not args.no_tune and not args.bin_size and not args.block:
+        # bin side, work-group size and deposit mode for this run, timed from
+        # the states at the start, middle and end of the workload's full run
+        spec, tune_rep = tune(spec, x0, s0, c0, steps=10, horizon=w.steps)
+        print(f"[bench] autotuned: {json.dumps(tune_rep.get('best', tune_rep.get('cached')))}",
+              file=sys.stderr, flush=True)
     sim = Sim(spec, x0, s0, c0)
     if not args.no_graph:
         sim.use_graph(True)
@@ -481,16 +568,17 @@ def main() -> int:
     ms = e0.elapsed_time(e1)
     sim.sync()
     value = w.n_total * args.steps / (ms / 1e3)
+    ms_step = ms / args.steps
     print(f"[bench] timed {args.steps} steps: {ms:.3f} ms", file=sys.stderr, flush=True)
 
-    # per-stage HIP-event profile of the same run (restored initial state)
+    # per-stage HIP-event profile of the same steps from the same state
     sim.set_state(x0, c0, 0)
     prof = sim.profile_steps(args.steps)
     dom = max(prof, key=prof.get)
     n_sub = sim.info["pde_substeps"]
     print(f"[bench] stage ms/step: {json.dumps({k: round(v, 5) for k, v in prof.items()})}",
           file=sys.stderr, flush=True)
-    # neighbour counts along the same run (a third pass, sampled every 10 steps)
+    # mean true neighbours along the same steps (sampled every 10 steps)
     sim.set_state(x0, c0, 0)
     nbr = []
     for t in range(0, args.steps, 10):
@@ -498,26 +586,30 @@ def main() -> int:
         nbr.append(float(cnt.double().mean()))
         sim.step(min(10, args.steps - t))
     nbr_mean = float(np.mean(nbr))
+
+    valid = counters_valid(w.name) and not args.deterministic and not args.no_graph
+    alg = algorithmic_bytes(dom, w, n_sub)
+    achieved = alg / (prof[dom] * 1e-3) / 1e9
+    roof = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+            "traffic": (COUNTER_UPDATE_BYTES if valid and dom == "update" else None),
+            "algorithmic_bytes_per_launch": alg, "launch_ms": prof[dom]}
     if dom == "update":
         flops = w.n_total * (FLOP_PER_PAIR * nbr_mean + FLOP_PER_AGENT)
-        achieved = flops / (prof[dom] * 1e-3) / 1e12
-        roof = {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": FP32_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS,
-                "traffic": update_traffic(w.name),
-                "valu_issue_frac": UPDATE_VALU_ISSUE if update_counters_valid(w.name) else None,
-                "algorithmic_flop_per_launch": flops, "mean_neighbours": nbr_mean,
-                "launch_ms": prof[dom]}
-    else:
-        alg = algorithmic_bytes(dom, w, n_sub)
-        achieved = alg / (prof[dom] * 1e-3) / 1e9
-        roof = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                "algorithmic_bytes_per_launch": alg, "launch_ms": prof[dom]}
-    # the same kernel measured against HBM, for reference
-    alg_b = algorithmic_bytes(dom, w, n_sub)
-    hbm_view = {"kernel": dom, "algorithmic_bytes_per_launch": alg_b,
-                "achieved_GBs": alg_b / (prof[dom] * 1e-3) / 1e9,
-                "frac": alg_b / (prof[dom] * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        tf = flops / (prof[dom] * 1e-3) / 1e12
+        roof["alu_view"] = {"achieved_TFLOPs": tf, "peak_attainable": FP32_ATTAINABLE_TFLOPS,
+                            "frac": tf / FP32_ATTAINABLE_TFLOPS,
+                            "algorithmic_flop_per_launch": flops,
+                            "mean_neighbours": nbr_mean}
+    fb = floor_bytes(w)
+    step_hbm = {"floor_bytes": fb, "floor_GBs": fb / (ms_step * 1e-3) / 1e9,
+                "floor_frac": fb / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                "counter_bytes": COUNTER_STEP_BYTES if valid else None}
+    if step_hbm["counter_bytes"]:
+        cb = step_hbm["counter_bytes"]
+        step_hbm.update({"counter_GBs": cb / (ms_step * 1e-3) / 1e9,
+                         "counter_frac": cb / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                         "amplification": cb / fb})
 
     res = {
         "metric": METRIC,
@@ -526,7 +618,7 @@ def main() -> int:
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms / args.steps,
+        "ms_per_step": ms_step,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -536,31 +628,34 @@ def main() -> int:
                    "grid": f"{w.grid_n}^{w.dim}", "dt": w.dt, "timed_steps": args.steps,
                    "graph": not args.no_graph, "deterministic": args.deterministic,
                    "bins_per_axis": sim.info["bins_per_axis"], "stencil": sim.info["stencil"],
-                   "block": sim.info["block"]},
+                   "block": sim.info["block"], "deposit_path": sim.info["deposit_path"]},
         "roofline": roof,
-        "roofline_hbm_view": hbm_view,
+        "step_hbm": step_hbm,
         "stage_ms": prof,
+        "autotune": ({"choice": tune_rep.get("best", tune_rep.get("cached")),
+                      "states_at_steps": tune_rep.get("states_at_steps"),
+                      "trials": tune_rep.get("trials")} if tune_rep else None),
     }
+    if not args.no_extras:
+        # the workload's whole run (all its steps from the initial state)
+        sim.set_state(x0, c0, 0)
+        fms = _timed(lambda: sim.step(w.steps))
+        sim.set_state(x0, c0, 0)
+        fprof = sim.profile_steps(w.steps)
+        res["full_run"] = {"steps": w.steps, "ms_per_step": fms / w.steps,
+                           "particle_steps_per_s": w.n_total * w.steps / (fms / 1e3),
+                           "floor_frac": fb / (fms / w.steps * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                           "stage_ms": {k: round(v, 5) for k, v in fprof.items() if v > 0}}
+        print(f"[bench] full run: {json.dumps(res['full_run'])}", file=sys.stderr, flush=True)
     sim.close()
     if not args.no_extras:
-        print("[bench] ensemble leg", file=sys.stderr, flush=True)
-        res["ensemble"] = ensemble_leg()
-        print(f"[bench] ensemble: {json.dumps(res['ensemble'])}", file=sys.stderr, flush=True)
-        print("[bench] Fig. 1 ensemble leg", file=sys.stderr, flush=True)
-        res["fig1"] = fig1_leg()
-        print(f"[bench] fig1: {json.dumps(res['fig1'])}", file=sys.stderr, flush=True)
-        print("[bench] switching overhead leg", file=sys.stderr, flush=True)
-        res["switching"] = reaction_overhead_leg()
-        print(f"[bench] switching: {json.dumps(res['switching'])}", file=sys.stderr, flush=True)
-        print("[bench] kernel density leg", file=sys.stderr, flush=True)
-        res["kde"] = kde_leg()
-        print(f"[bench] kde: {json.dumps(res['kde'])}", file=sys.stderr, flush=True)
-        print("[bench] pair/update variants leg", file=sys.stderr, flush=True)
-        res["variants"] = variants_leg()
-        print(f"[bench] variants: {json.dumps(res['variants'])}", file=sys.stderr, flush=True)
-        print("[bench] forward+backward leg", file=sys.stderr, flush=True)
-        res["fwd_bwd"] = adjoint_leg()
-        print(f"[bench] fwd_bwd: {json.dumps(res['fwd_bwd'])}", file=sys.stderr, flush=True)
+        for name, title in (("configs", "other workloads"), ("ensemble", "ensemble"),
+                            ("fig1", "Fig. 1 ensemble"), ("switching", "switching overhead"),
+                            ("kde", "kernel density"), ("variants", "pair/update variants"),
+                            ("fwd_bwd", "forward+backward")):
+            print(f"[bench] {title} leg", file=sys.stderr, flush=True)
+            res[name] = LEGS[name]()
+            print(f"[bench] {name}: {json.dumps(res[name])}", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
         res["cpu_baseline"] = cpu_baseline(w, inp)

@@ -53,7 +53,8 @@ class ModelSpec:
     bin_size: float = 0.0
     deterministic: bool = False
     block: int = 0
-    deposit_mode: int = 0    # 0 auto, 1 LDS-aggregated, 2 direct atomics, 3 fused per instance
+    deposit_mode: int = 0    # 0 auto, 1 LDS-aggregated, 2 direct atomics, 3 fused per instance,
+                             # 4 owner-computes node slabs (3D)
     deposit_kernel: int = 0  # 0 particle-in-cell, 1 Gaussian kernel density (Sect. 2.3)
     kde_radius: float = 0.0  # kernel truncation in bandwidths (0: 3)
     potential: int = 0       # 0 harmonic, 1 exponential k exp(-r/d), 2 hard spheres

@@ -48,3 +48,29 @@ def test_every_candidate_is_parity_green(bin_mult, block):
     X1, c1 = oracle_steps(w, inp, 1)
     assert pos_err(sim.positions().cpu().numpy(), X1, 1.0, True) <= 1e-5
     assert field_err(sim.field().cpu().numpy(), c1) <= 1e-5
+
+
+def test_autotune_times_states_along_the_run(tmp_path, monkeypatch):
+    """With a horizon the candidates are timed from the states at the start,
+    middle and end of the run, cached under their own key, and the choice
+    still reproduces the oracle's step."""
+    from paper_1805_11007_amd import ModelSpec, Sim
+    from paper_1805_11007_amd import autotune as AT
+    monkeypatch.setenv("PC_AUTOTUNE_CACHE", str(tmp_path / "tune.json"))
+    w = W.scaled(W.workload(W.BLOBS_1M), n_agents=20000, grid_n=24)
+    inp = W.make_inputs(w)
+    x0, s0, c0 = (torch.from_numpy(inp[k]) for k in ("x0", "species0", "c0"))
+    spec, rep = AT.tune(ModelSpec.from_workload(w), x0, s0, c0, steps=3, horizon=30,
+                        bins=(1.0, 2.0), blocks=(64, 128))
+    assert rep["states_at_steps"] == [0, 15, 27]
+    assert any(t.get("deposit_mode") == 4 for t in rep["trials"])   # the slab path is tried
+    _, rep0 = AT.tune(ModelSpec.from_workload(w), x0, s0, c0, steps=3, bins=(1.0,),
+                      blocks=(128,))
+    assert "best" in rep0                     # a horizon-0 tuning is a separate entry
+    _, rep2 = AT.tune(ModelSpec.from_workload(w), x0, s0, c0, steps=3, horizon=30)
+    assert rep2["cached"]["block"] == spec.block
+    sim = Sim(spec, x0, s0, c0)
+    sim.step(1)
+    X1, c1 = oracle_steps(w, inp, 1)
+    assert pos_err(sim.positions().cpu().numpy(), X1, 1.0, True) <= 1e-5
+    assert field_err(sim.field().cpu().numpy(), c1) <= 1e-5
