@@ -120,7 +120,13 @@ typedef struct {
                                otherwise scattered from the agents by float atomics
                                (last bits vary run to run).  deposit_mode is then
                                ignored (3 and 4 are rejected)                          */
-    int32_t reserved;
+    int32_t slab_split;     /* deposit_mode 4 (slabs): a slab whose cells hold more than
+                               this many agents (0: 2048) is handed over: its agents are
+                               spread in chunks of 2048 over many work-groups, which
+                               add their node sums with device atomics, so that a blob
+                               collapsed into a few cells does not serialise on one
+                               work-group.  The sums are integers: the bits do not
+                               depend on it.  Must be >= 0                              */
     double kde_radius;      /* truncation radius in bandwidths (0: 3); kde_radius times
                                the largest diameter must be < L/2                       */
     int32_t potential;      /* pair interaction with contact distance d = mean diameter:

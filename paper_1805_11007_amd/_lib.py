@@ -30,7 +30,7 @@ class PcConfig(C.Structure):
                 ("D_c", C.c_double), ("gamma", C.c_double), ("pde_substeps", C.c_int32),
                 ("bin_size", C.c_double), ("deterministic", C.c_int32), ("block", C.c_int32),
                 ("bin_order", C.c_int32), ("deposit_mode", C.c_int32),
-                ("deposit_kernel", C.c_int32), ("reserved", C.c_int32),
+                ("deposit_kernel", C.c_int32), ("slab_split", C.c_int32),
                 ("kde_radius", C.c_double), ("potential", C.c_int32), ("tamed", C.c_int32),
                 ("pot_range", C.c_double)]
 

@@ -43,6 +43,8 @@ struct Derived {
     int n_sub, block, has_uptake, has_react, kde, potential, tamed;
     double kde_radius, pot_range, contact_max;
     uint32_t warn;
+    int slab_ok;           // the node slabs of the owner-computes deposit fit
+    SlabShape slab;
 };
 
 // A species switches when react_to >= 0 and one of its rates is > 0.
@@ -55,14 +57,18 @@ constexpr int64_t kDepositAggMinAgents = 256 * 1024;
 // Instances from which a batch whose per-instance deposit sums fit in LDS
 // runs deposit + PDE as one work-group per instance.
 constexpr int kFusedMinInstances = 64;
+// Agents above which a slab of the owner-computes deposit is handed to the
+// agent-parallel pass (2 per thread of its 1024-thread work-group; 1024 to
+// 4096 measured within 3% on the 1M 3D run).
+constexpr uint32_t kSlabSplitDefault = 2048;
 
 static bool reacts(const pc_species_t &s) {
     return s.react_to >= 0 && (s.react_rate > 0 || s.react_rate_c > 0);
 }
 
 struct Layout {
-    size_t P[3], I[3], bin, rank, count, start, tile_sum, tile_cnt, c[2], S_src, S_upt, inst, species_id,
-        step, flags, seg_x, seg_c, lamX[2], lamY, lamC[2], aSrc, aUpt, lamG, csub, dth;
+    size_t P[3], I[3], bin, rank, count, start, tile_sum, tile_cnt, c[2], S_src, S_upt, slab_cnt,
+        slab_tab, inst, species_id, step, flags, seg_x, seg_c, lamX[2], lamY, lamC[2], aSrc, aUpt, lamG, csub, dth;
     size_t total;
 };
 
@@ -86,6 +92,7 @@ int derive(const pc_config *cfg, const pc_species_t *sp, int ns, const pc_instan
     if (cfg->bin_order != 0) return fail(PC_ENOTSUP, "only row-major bin order is built");
     if (cfg->deposit_mode < 0 || cfg->deposit_mode > 4)
         return fail(PC_EINVAL, "deposit_mode must be 0 .. 4");
+    if (cfg->slab_split < 0) return fail(PC_EINVAL, "slab_split must be >= 0");
     if (cfg->block != 0 && cfg->block != 64 && cfg->block != 128 && cfg->block != 256 &&
         cfg->block != 512 && cfg->block != 1024)
         return fail(PC_EINVAL, "block must be 0, 64, 128, 256, 512 or 1024");
@@ -199,6 +206,7 @@ int derive(const pc_config *cfg, const pc_species_t *sp, int ns, const pc_instan
             const double dij = 0.5 * (sp[a].diameter + sp[b].diameter);
             if (sqrt(2.0 * (sp[a].D + sp[b].D) * cfg->dt) >= dij) d.warn |= PC_WARN_DT_RULE;
         }
+    d.slab_ok = chem_slab_shape(d.dim, cfg->grid_n, d.h / d.bin_side, d.ni, d.slab) ? 1 : 0;
     return PC_OK;
 }
 
@@ -219,6 +227,10 @@ Layout layout(const Derived &d, int seg_steps) {
     L.c[1] = take(cur, 4 * (size_t)d.nodes_total);
     L.S_src = take(cur, 8 * (size_t)d.nodes_total);
     L.S_upt = take(cur, d.has_uptake ? 8 * (size_t)d.nodes_total : 8);
+    if (d.slab_ok) {
+        L.slab_cnt = take(cur, 4 * (size_t)d.slab.nslabs);
+        L.slab_tab = take(cur, 4 * (size_t)d.slab.nslabs * chem_slab_table_words());
+    }
     L.inst = take(cur, sizeof(InstInfo) * (size_t)d.ni);
     L.species_id = take(cur, N);
     L.step = take(cur, 4);
@@ -271,6 +283,7 @@ struct pc_sim {
     int chem_fused;           // deposit + PDE in one per-instance kernel (k_chem_inst)
     int slab;                 // owner-computes deposit by node slabs (k_chem_slabs) from
                               // the sorted X^{n+1}: the step sorts after the update
+    uint32_t slab_split;      // agents above which a slab is handed to k_slab_assist
 };
 
 static void fill_params(pc_sim *s) {
@@ -293,6 +306,7 @@ static void fill_params(pc_sim *s) {
     p.L = (float)c.L;
     p.halfL = (float)(0.5 * c.L);
     p.inv_bin = (float)(d.nb / c.L);
+    p.bin_w = (float)c.L / (float)d.nb;
     p.h = (float)d.h;
     p.inv_h = (float)(1.0 / d.h);
     p.inv_2h = (float)(0.5 / d.h);
@@ -397,6 +411,10 @@ static void carve(pc_sim *s, char *ws) {
     b.c[1] = (float *)(ws + L.c[1]);
     b.S_src = (unsigned long long *)(ws + L.S_src);
     b.S_upt = (unsigned long long *)(ws + L.S_upt);
+    if (s->d.slab_ok) {
+        b.slab_cnt = (uint32_t *)(ws + L.slab_cnt);
+        b.slab_tab = (uint32_t *)(ws + L.slab_tab);
+    }
     b.inst = (InstInfo *)(ws + L.inst);
     b.species_id = (uint8_t *)(ws + L.species_id);
     b.step = (uint32_t *)(ws + L.step);
@@ -479,7 +497,8 @@ static void enqueue_chem(pc_sim *s, hipStream_t st) {
 // otherwise it stores the deposits for the substeps.
 static void enqueue_slabs(pc_sim *s, hipStream_t st) {
     const int fuse = s->d.n_sub == 1 ? 1 : 0;
-    launch_chem_slabs(s->sp, s->pp, s->b, s->sorted_src, s->cur_c, fuse, st);
+    launch_chem_slabs(s->sp, s->pp, s->b, s->d.slab, s->slab_split, s->sorted_src, s->cur_c,
+                      fuse, st);
     if (fuse) s->cur_c = 1 - s->cur_c;
     else enqueue_pde(s, st);
 }
@@ -578,14 +597,15 @@ static int common_create(const pc_config *cfg, const pc_species_t *species, int 
                                    (cfg->deposit_mode == 0 && fits && d.ni >= kFusedMinInstances));
         // the slab deposit: its LDS sums and run table must fit, and the
         // bins per cell must leave a slab few enough runs
-        const size_t slab_lds = chem_slab_lds_bytes(s->sp);
+        const size_t slab_lds = d.slab_ok ? d.slab.lds_bytes * (d.has_uptake ? 2 : 1) : 0;
         const bool slab_ok = !d.kde && !s->chem_fused && slab_lds > 0 &&
-                             slab_lds + 8192 <= (size_t)max_lds;
+                             slab_lds + 12288 <= (size_t)max_lds;
         if (cfg->deposit_mode == 4 && !slab_ok) {
             delete s;
             return fail(PC_EINVAL, "deposit_mode 4: the node slabs do not fit this grid");
         }
         s->slab = slab_ok && (cfg->deposit_mode == 4 || (cfg->deposit_mode == 0 && d.dim == 3));
+        s->slab_split = cfg->slab_split > 0 ? (uint32_t)cfg->slab_split : kSlabSplitDefault;
     }
     carve(s, (char *)workspace_dev);
     s->inst_host.resize(n_inst);
@@ -810,11 +830,12 @@ int pc_profile_steps(pc_sim *s, int n_steps, double *stage_ms) {
             rc = sort_stages();
             if (rc) return rc;
             if (s->d.n_sub == 1) {
-                // deposit and PDE in one kernel: its time is reported under
+                // deposit and PDE in one pass: its time is reported under
                 // the deposit
                 PC_STAGE(PC_STAGE_DEPOSIT, enqueue_slabs(s, st));
             } else {
-                PC_STAGE(PC_STAGE_DEPOSIT, launch_chem_slabs(s->sp, s->pp, s->b, s->sorted_src,
+                PC_STAGE(PC_STAGE_DEPOSIT, launch_chem_slabs(s->sp, s->pp, s->b, s->d.slab,
+                                                             s->slab_split, s->sorted_src,
                                                              s->cur_c, 0, st));
                 PC_STAGE(PC_STAGE_PDE, enqueue_pde(s, st));
             }

@@ -21,11 +21,26 @@
 // work-group, so every node receives the same integer as on every other
 // deposit path (fixed point, 2^-32 units, charge times the axis weights in
 // axis order), and the PDE node update is the same function as k_pde's.
+//
+// One work-group per slab serialises where chemotaxis has collapsed a blob
+// into a few cells: a slab can then hold 10^5 agents.  A slab with more
+// agents than a threshold is handed over: its work-group records its run
+// table and zeroes its nodes' deposits, k_slab_assist spreads its agents in
+// chunks over many work-groups (each sums a chunk's owned corners in LDS and
+// adds the nonzero node sums to HBM with device atomics), and k_slab_finish
+// applies the PDE to its nodes.  The sums are still integers, so the bits
+// do not depend on which slabs were handed over.
 #include "pc_device.h"
 
 namespace pc {
 
 constexpr int kSlabRuns = 256;   // contiguous agent runs per slab (LDS table)
+// per-slab run table handed to k_slab_assist: run count, run starts, prefixes
+constexpr int kSlabTableWords = 2 * kSlabRuns + 2;
+constexpr int kAssistChunk = 2048;   // agents of a heavy slab per assisting pass
+constexpr int kAssistThreads = 256;
+constexpr int kAssistBlocks = 1024;
+constexpr int kAssistSlabBlock = 4 * kAssistThreads;   // slab counts scanned per pass
 
 // Bins holding every agent whose cell lies in [c0, c1] along one axis, as
 // up to two disjoint inclusive intervals (c0 = -1 on the torus: cell n - 1
@@ -71,14 +86,101 @@ __device__ __forceinline__ void cells_of_nodes(const StepParams &p, int o0, int 
     }
 }
 
+// Owned nodes of slab s: instance k, y rows [y0, y1), z layers [z0, z1),
+// all x.
+struct SlabGeom {
+    int k, y0, y1, z0, z1, owned;
+};
+
+template <int DIM>
+__device__ __forceinline__ SlabGeom slab_geom(int s, int n, int By, int Bz, int nby, int nbz) {
+    SlabGeom g;
+    const int per_inst = nby * nbz;
+    g.k = s / per_inst;
+    const int bl = s - g.k * per_inst;
+    const int jy = bl % nby, jz = bl / nby;
+    g.y0 = jy * By;
+    g.y1 = min(g.y0 + By, n);
+    g.z0 = DIM == 3 ? jz * Bz : 0;
+    g.z1 = DIM == 3 ? min(g.z0 + Bz, n) : 1;
+    g.owned = n * (g.y1 - g.y0) * (g.z1 - g.z0);
+    return g;
+}
+
+// The corners of agent x that fall in the slab's owned nodes, added to the
+// LDS sums (source, then uptake at offset owned).
+template <int DIM, int NS, bool UPT>
+__device__ __forceinline__ void slab_agent(const StepParams &p, const SpTab &tab, const float4 x,
+                                           const SlabGeom &g, unsigned long long *sums) {
+    const int n = p.grid_n;
+    const int s = species_of(x.w);
+    const float qs = sel<NS>(p.src_fx, tab.src, s);
+    const float qu = UPT ? sel<NS>(p.upt_fx, tab.upt, s) : 0.0f;
+    if (qs == 0.0f && qu == 0.0f) return;
+    Cell cc[3];
+    cc[0] = cell_of(p, x.x);
+    cc[1] = cell_of(p, x.y);
+    cc[2] = Cell{0, 0, 0.0f};
+    if (DIM == 3) cc[2] = cell_of(p, x.z);
+    // owned corner offsets along y and z (-1: outside the slab)
+    const int ly0 = cc[1].i0 - g.y0, ly1 = cc[1].i1 - g.y0;
+    const int oy[2] = {(ly0 >= 0 && ly0 < g.y1 - g.y0) ? ly0 : -1,
+                       (ly1 >= 0 && ly1 < g.y1 - g.y0) ? ly1 : -1};
+    int oz[2] = {0, -1};
+    if (DIM == 3) {
+        const int lz0 = cc[2].i0 - g.z0, lz1 = cc[2].i1 - g.z0;
+        oz[0] = (lz0 >= 0 && lz0 < g.z1 - g.z0) ? lz0 : -1;
+        oz[1] = (lz1 >= 0 && lz1 < g.z1 - g.z0) ? lz1 : -1;
+    }
+    const int ox[2] = {cc[0].i0, cc[0].i1};
+    const int ny = g.y1 - g.y0;
+#pragma unroll
+    for (int m = 0; m < (1 << DIM); ++m) {
+        const int ux = m & 1, uy = (m >> 1) & 1, uz = (m >> 2) & 1;
+        // the charge times the axis weights in axis order, as every deposit
+        // path forms it
+        float ws = qs, wu = qu;
+        const float fx = ux ? cc[0].t : 1.0f - cc[0].t;
+        const float fy = uy ? cc[1].t : 1.0f - cc[1].t;
+        ws *= fx;
+        if (UPT) wu *= fx;
+        ws *= fy;
+        if (UPT) wu *= fy;
+        if (DIM == 3) {
+            const float fz = uz ? cc[2].t : 1.0f - cc[2].t;
+            ws *= fz;
+            if (UPT) wu *= fz;
+        }
+        if (oy[uy] < 0 || oz[uz] < 0) continue;
+        const int l = ox[ux] + n * (oy[uy] + ny * oz[uz]);
+        const unsigned long long vs = (unsigned long long)__float2ull_rn(ws);
+        if (vs) atomicAdd(&sums[l], vs);
+        if (UPT) {
+            const unsigned long long vu = (unsigned long long)__float2ull_rn(wu);
+            if (vu) atomicAdd(&sums[g.owned + l], vu);
+        }
+    }
+}
+
+template <int DIM>
+__device__ __forceinline__ int64_t slab_node(const SlabGeom &g, const InstInfo &ii, int n, int l,
+                                             int ic[3]) {
+    const int ny = g.y1 - g.y0;
+    ic[0] = l % n;
+    ic[1] = g.y0 + (l / n) % ny;
+    ic[2] = g.z0 + l / (n * ny);
+    return (int64_t)ii.node_base + ic[0] + (int64_t)n * (ic[1] + (int64_t)n * ic[2]);
+}
+
 template <int DIM, int NS, bool UPT>
 __global__ void __launch_bounds__(1024)
 k_chem_slabs(StepParams p, PdeParams q, const InstInfo *__restrict__ inst,
              const float4 *__restrict__ Ps, const uint32_t *__restrict__ start,
              const float *__restrict__ cin, float *__restrict__ cout,
              unsigned long long *__restrict__ Ssrc, unsigned long long *__restrict__ Supt,
-             int By, int Bz, int nby, int nbz, int fuse_pde, uint32_t *__restrict__ flags,
-             uint32_t *__restrict__ stepc) {
+             int By, int Bz, int nby, int nbz, int fuse_pde, uint32_t split,
+             uint32_t *__restrict__ slab_cnt, uint32_t *__restrict__ slab_tab,
+             uint32_t *__restrict__ flags, uint32_t *__restrict__ stepc) {
     extern __shared__ unsigned long long sums[];   // owned source sums, then uptake
     __shared__ uint32_t run_a[kSlabRuns];
     __shared__ uint32_t run_pre[kSlabRuns + 1];
@@ -89,14 +191,9 @@ k_chem_slabs(StepParams p, PdeParams q, const InstInfo *__restrict__ inst,
     if (fuse_pde && stepc && blockIdx.x == 0 && threadIdx.x == 0) *stepc += 1u;
     const int n = p.grid_n;
     const int nb = p.nb;
-    const int per_inst = nby * nbz;
-    const int k = blockIdx.x / per_inst;
-    const int bl = blockIdx.x - k * per_inst;
-    const int jy = bl % nby, jz = bl / nby;
-    const int y0 = jy * By, y1 = min(y0 + By, n);
-    const int z0 = DIM == 3 ? jz * Bz : 0, z1 = DIM == 3 ? min(z0 + Bz, n) : 1;
-    const int owned = n * (y1 - y0) * (z1 - z0);
-    const InstInfo ii = inst[k];
+    const SlabGeom g = slab_geom<DIM>(blockIdx.x, n, By, Bz, nby, nbz);
+    const int y0 = g.y0, y1 = g.y1, z0 = g.z0, z1 = g.z1, owned = g.owned;
+    const InstInfo ii = inst[g.k];
     for (int l = threadIdx.x; l < owned * (UPT ? 2 : 1); l += blockDim.x) sums[l] = 0ull;
     if (NS == 0) load_tab(p, tab);
     // runs: one per z bin layer of the box and y interval, holding all x bins
@@ -158,74 +255,169 @@ k_chem_slabs(StepParams p, PdeParams q, const InstInfo *__restrict__ inst,
     }
     __syncthreads();
     const uint32_t total = run_pre[nrun];
+    const bool heavy = total > split;
+    if (threadIdx.x == 0) slab_cnt[blockIdx.x] = heavy ? total : 0u;
+    if (heavy) {
+        // handed over: the run table for k_slab_assist, and zeroed deposits
+        // for its atomics
+        uint32_t *T = slab_tab + (size_t)blockIdx.x * kSlabTableWords;
+        if (threadIdx.x == 0) T[0] = (uint32_t)nrun;
+        if ((int)threadIdx.x < nrun) T[1 + threadIdx.x] = run_a[threadIdx.x];
+        if ((int)threadIdx.x <= nrun) T[1 + kSlabRuns + threadIdx.x] = run_pre[threadIdx.x];
+        int ic[3];
+        for (int l = threadIdx.x; l < owned; l += blockDim.x) {
+            const int64_t node = slab_node<DIM>(g, ii, n, l, ic);
+            Ssrc[node] = 0ull;
+            if (UPT) Supt[node] = 0ull;
+        }
+        return;
+    }
     // agents of the runs, laid end to end; a thread's positions increase, so
     // its run index only moves forward
     int r = 0;
     for (uint32_t w = threadIdx.x; w < total; w += blockDim.x) {
         while (r + 1 < nrun && run_pre[r + 1] <= w) ++r;
-        const float4 x = Ps[run_a[r] + (w - run_pre[r])];
-        const int s = species_of(x.w);
-        const float qs = sel<NS>(p.src_fx, tab.src, s);
-        const float qu = UPT ? sel<NS>(p.upt_fx, tab.upt, s) : 0.0f;
-        if (qs == 0.0f && qu == 0.0f) continue;
-        Cell cc[3];
-        cc[0] = cell_of(p, x.x);
-        cc[1] = cell_of(p, x.y);
-        cc[2] = Cell{0, 0, 0.0f};
-        if (DIM == 3) cc[2] = cell_of(p, x.z);
-        // owned corner offsets along y and z (-1: outside the slab)
-        const int ly0 = cc[1].i0 - y0, ly1 = cc[1].i1 - y0;
-        const int oy[2] = {(ly0 >= 0 && ly0 < y1 - y0) ? ly0 : -1,
-                           (ly1 >= 0 && ly1 < y1 - y0) ? ly1 : -1};
-        int oz[2] = {0, -1};
-        if (DIM == 3) {
-            const int lz0 = cc[2].i0 - z0, lz1 = cc[2].i1 - z0;
-            oz[0] = (lz0 >= 0 && lz0 < z1 - z0) ? lz0 : -1;
-            oz[1] = (lz1 >= 0 && lz1 < z1 - z0) ? lz1 : -1;
-        }
-        const int ox[2] = {cc[0].i0, cc[0].i1};
-        const int ny = y1 - y0;
-#pragma unroll
-        for (int m = 0; m < (1 << DIM); ++m) {
-            const int ux = m & 1, uy = (m >> 1) & 1, uz = (m >> 2) & 1;
-            // the charge times the axis weights in axis order, as every
-            // deposit path forms it
-            float ws = qs, wu = qu;
-            const float fx = ux ? cc[0].t : 1.0f - cc[0].t;
-            const float fy = uy ? cc[1].t : 1.0f - cc[1].t;
-            ws *= fx;
-            if (UPT) wu *= fx;
-            ws *= fy;
-            if (UPT) wu *= fy;
-            if (DIM == 3) {
-                const float fz = uz ? cc[2].t : 1.0f - cc[2].t;
-                ws *= fz;
-                if (UPT) wu *= fz;
-            }
-            if (oy[uy] < 0 || oz[uz] < 0) continue;
-            const int l = ox[ux] + n * (oy[uy] + ny * oz[uz]);
-            const unsigned long long vs = (unsigned long long)__float2ull_rn(ws);
-            if (vs) atomicAdd(&sums[l], vs);
-            if (UPT) {
-                const unsigned long long vu = (unsigned long long)__float2ull_rn(wu);
-                if (vu) atomicAdd(&sums[owned + l], vu);
-            }
-        }
+        slab_agent<DIM, NS, UPT>(p, tab, Ps[run_a[r] + (w - run_pre[r])], g, sums);
     }
     __syncthreads();
-    const int ny = y1 - y0;
     uint32_t flag = 0;
+    int ic[3];
     for (int l = threadIdx.x; l < owned; l += blockDim.x) {
-        const int ix = l % n, iy = y0 + (l / n) % ny, iz = z0 + l / (n * ny);
-        const int64_t node = (int64_t)ii.node_base + ix + (int64_t)n * (iy + (int64_t)n * iz);
+        const int64_t node = slab_node<DIM>(g, ii, n, l, ic);
         const unsigned long long sS = sums[l], sU = UPT ? sums[owned + l] : 0ull;
         if (fuse_pde) {
-            const int ic[3] = {ix, iy, iz};
             cout[node] = pde_node<DIM>(q, cin + ii.node_base, ic, sS, sU, flag);
         } else {
             Ssrc[node] = sS;
             if (UPT) Supt[node] = sU;
         }
+    }
+    if (flag) atomicOr(flags, flag);
+}
+
+// The agents of the handed-over slabs.  Slab s contributes ceil(cnt_s /
+// kAssistChunk) chunks, numbered in slab order; work-group b takes chunks
+// b, b + gridDim.x, ...  For a chunk it loads the slab's run table, sums the
+// owned corners of the chunk's agents in LDS and adds each nonzero node sum
+// to the slab's zeroed deposits with one device atomic.  Every work-group
+// scans the slab counts itself (kAssistSlabBlock at a time), so no counter
+// has to be reset between steps; with no handed-over slab it only reads the
+// counts.
+template <int DIM, int NS, bool UPT>
+__global__ void __launch_bounds__(kAssistThreads)
+k_slab_assist(StepParams p, const InstInfo *__restrict__ inst, const float4 *__restrict__ Ps,
+              unsigned long long *__restrict__ Ssrc, unsigned long long *__restrict__ Supt,
+              int By, int Bz, int nby, int nbz, int nslabs,
+              const uint32_t *__restrict__ slab_cnt, const uint32_t *__restrict__ slab_tab) {
+    extern __shared__ unsigned long long sums[];
+    __shared__ uint32_t pre[kAssistSlabBlock + 1];
+    __shared__ uint32_t run_a[kSlabRuns];
+    __shared__ uint32_t run_pre[kSlabRuns + 1];
+    __shared__ uint32_t wtot[kAssistThreads / 64];
+    __shared__ SpTab tab;
+    if (NS == 0) load_tab(p, tab);
+    const int n = p.grid_n;
+    const uint32_t G = gridDim.x, b = blockIdx.x;
+    uint32_t base = 0;   // chunks of the slabs before this block of slabs
+    for (int s0 = 0; s0 < nslabs; s0 += kAssistSlabBlock) {
+        uint32_t c[4], loc = 0;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int sl = s0 + (int)threadIdx.x * 4 + e;
+            const uint32_t cnt = sl < nslabs ? slab_cnt[sl] : 0u;
+            c[e] = (cnt + kAssistChunk - 1) / kAssistChunk;
+            loc += c[e];
+        }
+        // block-wide exclusive scan of the per-thread chunk counts
+        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+        uint32_t x = loc;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint32_t y = __shfl_up(x, d, 64);
+            if (lane >= d) x += y;
+        }
+        if (lane == 63) wtot[wv] = x;
+        __syncthreads();
+        uint32_t wb = 0, tot = 0;
+#pragma unroll
+        for (int w = 0; w < kAssistThreads / 64; ++w) {
+            if (w < wv) wb += wtot[w];
+            tot += wtot[w];
+        }
+        uint32_t run = base + wb + x - loc;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            pre[threadIdx.x * 4 + e] = run;
+            run += c[e];
+        }
+        if (threadIdx.x == 0) pre[kAssistSlabBlock] = base + tot;
+        __syncthreads();
+        // this work-group's chunks among [base, base + tot)
+        uint32_t ch = base + (b + G - base % G) % G;
+        for (; ch < base + tot; ch += G) {
+            // slab: the last j with pre[j] <= ch (pre is non-decreasing)
+            int lo = 0, hi = kAssistSlabBlock - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (pre[mid] <= ch) lo = mid;
+                else hi = mid - 1;
+            }
+            const int sl = s0 + lo;
+            const uint32_t cnt = slab_cnt[sl];
+            const uint32_t a0 = (ch - pre[lo]) * (uint32_t)kAssistChunk;
+            const uint32_t a1 = min(a0 + (uint32_t)kAssistChunk, cnt);
+            const SlabGeom g = slab_geom<DIM>(sl, n, By, Bz, nby, nbz);
+            const InstInfo ii = inst[g.k];
+            const uint32_t *T = slab_tab + (size_t)sl * kSlabTableWords;
+            const int nrun = (int)T[0];
+            for (int t = threadIdx.x; t < nrun; t += blockDim.x) run_a[t] = T[1 + t];
+            for (int t = threadIdx.x; t <= nrun; t += blockDim.x) run_pre[t] = T[1 + kSlabRuns + t];
+            for (int l = threadIdx.x; l < g.owned * (UPT ? 2 : 1); l += blockDim.x) sums[l] = 0ull;
+            __syncthreads();
+            for (uint32_t w = a0 + threadIdx.x; w < a1; w += blockDim.x) {
+                int r0 = 0, r1 = nrun - 1;   // the run holding agent w
+                while (r0 < r1) {
+                    const int mid = (r0 + r1 + 1) >> 1;
+                    if (run_pre[mid] <= w) r0 = mid;
+                    else r1 = mid - 1;
+                }
+                slab_agent<DIM, NS, UPT>(p, tab, Ps[run_a[r0] + (w - run_pre[r0])], g, sums);
+            }
+            __syncthreads();
+            int ic[3];
+            for (int l = threadIdx.x; l < g.owned; l += blockDim.x) {
+                const unsigned long long vS = sums[l], vU = UPT ? sums[g.owned + l] : 0ull;
+                if (vS == 0ull && vU == 0ull) continue;
+                const int64_t node = slab_node<DIM>(g, ii, n, l, ic);
+                if (vS) atomicAdd(&Ssrc[node], vS);
+                if (UPT && vU) atomicAdd(&Supt[node], vU);
+            }
+            __syncthreads();
+        }
+        base += tot;
+        __syncthreads();   // pre and wtot are rewritten by the next block of slabs
+    }
+}
+
+// The single PDE substep at the nodes of the handed-over slabs, from their
+// deposits in HBM (the other slabs applied it in k_chem_slabs).
+template <int DIM, bool UPT>
+__global__ void __launch_bounds__(256)
+k_slab_finish(StepParams p, PdeParams q, const InstInfo *__restrict__ inst,
+              const float *__restrict__ cin, float *__restrict__ cout,
+              const unsigned long long *__restrict__ Ssrc,
+              const unsigned long long *__restrict__ Supt, int By, int Bz, int nby, int nbz,
+              const uint32_t *__restrict__ slab_cnt, uint32_t *__restrict__ flags) {
+    if (slab_cnt[blockIdx.x] == 0u) return;
+    const int n = p.grid_n;
+    const SlabGeom g = slab_geom<DIM>(blockIdx.x, n, By, Bz, nby, nbz);
+    const InstInfo ii = inst[g.k];
+    uint32_t flag = 0;
+    int ic[3];
+    for (int l = threadIdx.x; l < g.owned; l += blockDim.x) {
+        const int64_t node = slab_node<DIM>(g, ii, n, l, ic);
+        cout[node] = pde_node<DIM>(q, cin + ii.node_base, ic, Ssrc[node], UPT ? Supt[node] : 0ull,
+                                   flag);
     }
     if (flag) atomicOr(flags, flag);
 }
@@ -237,11 +429,9 @@ k_chem_slabs(StepParams p, PdeParams q, const InstInfo *__restrict__ inst,
 // f bins per cell.  Returns false when no height keeps them within
 // kSlabRuns (very fine bins on a coarse grid): the step then deposits with
 // device atomics.
-bool chem_slab_shape(const StepParams &p, int &By, int &Bz, int &nby, int &nbz) {
-    const int n = p.grid_n;
-    const double f = (double)p.h * (double)p.inv_bin;
-    if (p.dim == 3) {
-        By = 4;
+bool chem_slab_shape(int dim, int n, double f, int n_inst, SlabShape &sh) {
+    int By = 4, Bz = 1;
+    if (dim == 3) {
         Bz = 4;
         while (n * By * Bz > 2048 && (By > 1 || Bz > 1)) {
             if (By >= Bz) By /= 2;
@@ -250,40 +440,44 @@ bool chem_slab_shape(const StepParams &p, int &By, int &Bz, int &nby, int &nbz) 
         while (Bz > 1 && 2.0 * ((Bz + 2) * f + 6.0) > kSlabRuns - 1) Bz /= 2;
         if (2.0 * ((Bz + 2) * f + 6.0) > kSlabRuns - 1) return false;
     } else {
-        By = 4;
         while (n * By > 2048 && By > 1) By /= 2;
-        Bz = 1;
     }
-    nby = (n + By - 1) / By;
-    nbz = p.dim == 3 ? (n + Bz - 1) / Bz : 1;
+    sh.By = By;
+    sh.Bz = Bz;
+    sh.nby = (n + By - 1) / By;
+    sh.nbz = dim == 3 ? (n + Bz - 1) / Bz : 1;
+    sh.nslabs = (int64_t)sh.nby * sh.nbz * n_inst;
+    sh.lds_bytes = 8 * (size_t)n * By * Bz;   // per deposited field
     return true;
 }
 
-// LDS sums of a slab (0 when the slab path does not apply).
-size_t chem_slab_lds_bytes(const StepParams &p) {
-    int By, Bz, nby, nbz;
-    if (!chem_slab_shape(p, By, Bz, nby, nbz)) return 0;
-    return 8 * (size_t)p.grid_n * By * (p.dim == 3 ? Bz : 1) * (p.has_uptake ? 2 : 1);
-}
+size_t chem_slab_table_words() { return kSlabTableWords; }
 
 template <int DIM, int NS, bool UPT>
-static void slabs(const StepParams &p, const PdeParams &q, const Buffers &b, int src, int cur,
-                  int fuse, hipStream_t s) {
-    int By, Bz, nby, nbz;
-    if (!chem_slab_shape(p, By, Bz, nby, nbz)) return;   // the host checked
-    const size_t lds = chem_slab_lds_bytes(p);
-    hipLaunchKernelGGL((k_chem_slabs<DIM, NS, UPT>), dim3((unsigned)(nby * nbz * p.n_inst)),
-                       dim3(1024), lds, s, p, q, b.inst, b.P[src], b.start, b.c[cur],
-                       b.c[1 - cur], b.S_src, b.S_upt, By, Bz, nby, nbz, fuse, b.flags, b.step);
+static void slabs(const StepParams &p, const PdeParams &q, const Buffers &b, const SlabShape &sh,
+                  uint32_t split, int src, int cur, int fuse, hipStream_t s) {
+    const size_t lds = sh.lds_bytes * (UPT ? 2 : 1);
+    hipLaunchKernelGGL((k_chem_slabs<DIM, NS, UPT>), dim3((unsigned)sh.nslabs), dim3(1024), lds,
+                       s, p, q, b.inst, b.P[src], b.start, b.c[cur], b.c[1 - cur], b.S_src,
+                       b.S_upt, sh.By, sh.Bz, sh.nby, sh.nbz, fuse, split, b.slab_cnt,
+                       b.slab_tab, b.flags, b.step);
+    hipLaunchKernelGGL((k_slab_assist<DIM, NS, UPT>), dim3(kAssistBlocks), dim3(kAssistThreads),
+                       lds, s, p, b.inst, b.P[src], b.S_src, b.S_upt, sh.By, sh.Bz, sh.nby,
+                       sh.nbz, (int)sh.nslabs, b.slab_cnt, b.slab_tab);
+    if (fuse)
+        hipLaunchKernelGGL((k_slab_finish<DIM, UPT>), dim3((unsigned)sh.nslabs), dim3(256), 0, s,
+                           p, q, b.inst, b.c[cur], b.c[1 - cur], b.S_src, b.S_upt, sh.By, sh.Bz,
+                           sh.nby, sh.nbz, b.slab_cnt, b.flags);
 }
 
-void launch_chem_slabs(const StepParams &p, const PdeParams &q, const Buffers &b, int src,
-                       int cur, int fuse_pde, hipStream_t s) {
+void launch_chem_slabs(const StepParams &p, const PdeParams &q, const Buffers &b,
+                       const SlabShape &sh, uint32_t split, int src, int cur, int fuse_pde,
+                       hipStream_t s) {
     const int ns = p.n_species == 1 ? 1 : (p.n_species == 2 ? 2 : 0);
-#define PC_SLAB(D, N)                                                    \
-    do {                                                                 \
-        if (p.has_uptake) slabs<D, N, true>(p, q, b, src, cur, fuse_pde, s); \
-        else slabs<D, N, false>(p, q, b, src, cur, fuse_pde, s);         \
+#define PC_SLAB(D, N)                                                                   \
+    do {                                                                                \
+        if (p.has_uptake) slabs<D, N, true>(p, q, b, sh, split, src, cur, fuse_pde, s); \
+        else slabs<D, N, false>(p, q, b, sh, split, src, cur, fuse_pde, s);             \
     } while (0)
     if (p.dim == 2) {
         if (ns == 1) PC_SLAB(2, 1);

@@ -36,8 +36,10 @@ __device__ __forceinline__ U4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c
     const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t hi0 = __umulhi(M0, c0), lo0 = M0 * c0;
-        const uint32_t hi1 = __umulhi(M1, c2), lo1 = M1 * c2;
+        // each 32 x 32 -> 64-bit product in one multiply-add instruction
+        const uint64_t p0 = (uint64_t)M0 * c0, p1 = (uint64_t)M1 * c2;
+        const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
         const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
         c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
         k0 += W0; k1 += W1;
@@ -52,20 +54,25 @@ __device__ __forceinline__ float uniform24(uint32_t w) {
     return (float)((w >> 8) | 1u) * 5.9604644775390625e-8f;
 }
 
-// Box-Muller normals: (xi0, xi1) from words 0, 1 and xi2 from words 2, 3.
+// Box-Muller normals: (xi0, xi1) from words 0, 1 and xi2 from words 2, 3,
+// xi = sqrt(-2 ln u) (cos 2 pi v, sin 2 pi v), with the hardware base-2
+// logarithm (u >= 2^-24 is a normal float), square root, sine and cosine
+// (the last two take their argument in revolutions, so 2 pi v needs no
+// range reduction), each within a few float32 ulps.
+__device__ __forceinline__ float bm_radius(float u) {
+    return __builtin_amdgcn_sqrtf(-1.38629436111989061f * __builtin_amdgcn_logf(u));
+}
+
 template <int DIM>
 __device__ __forceinline__ void normals(const U4 &w, float xi[3]) {
     const float u0 = uniform24(w.v[0]), u1 = uniform24(w.v[1]);
-    const float r0 = sqrtf(-2.0f * logf(u0));
-    float s1, c1;
-    sincospif(2.0f * u1, &s1, &c1);
-    xi[0] = r0 * c1;
-    xi[1] = r0 * s1;
+    const float r0 = bm_radius(u0);
+    xi[0] = r0 * __builtin_amdgcn_cosf(u1);
+    xi[1] = r0 * __builtin_amdgcn_sinf(u1);
     xi[2] = 0.0f;
     if (DIM == 3) {
         const float u2 = uniform24(w.v[2]), u3 = uniform24(w.v[3]);
-        const float r1 = sqrtf(-2.0f * logf(u2));
-        xi[2] = r1 * cospif(2.0f * u3);
+        xi[2] = bm_radius(u2) * __builtin_amdgcn_cosf(u3);
     }
 }
 
@@ -297,7 +304,7 @@ __device__ __forceinline__ void pair_loop(const StepParams &p, const SpTab &tab,
     int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
     // squared distance from x_i to the lower / upper face of its own bin
     float glo2[3] = {0.f, 0.f, 0.f}, ghi2[3] = {0.f, 0.f, 0.f};
-    const float side = p.L / (float)nb;
+    const float side = p.bin_w;
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
         const float s = fmaxf(pc[a] * p.inv_bin, 0.0f);
@@ -610,7 +617,14 @@ __device__ __forceinline__ void grad_interp(const StepParams &p, const float *__
 __device__ __forceinline__ float boundary(const StepParams &p, float x, uint32_t &flag) {
     const float L = p.L;
     if (p.periodic) {
-        x = x - L * floorf(x / L);
+        // x - L floor(x / L), which for x in [-L/2, 3L/2) (a step moves an
+        // agent far less than L) is the same single add or subtract
+        if (x >= -0.5f * L && x < 1.5f * L) {
+            if (x < 0.0f) x += L;
+            else if (x >= L) x -= L;
+        } else {
+            x = x - L * floorf(x / L);
+        }
         if (x >= L) x -= L;
         if (!(x >= 0.0f)) {
             x = 0.0f;

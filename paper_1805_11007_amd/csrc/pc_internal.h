@@ -40,6 +40,7 @@ struct StepParams {
     int32_t deposit_agg;   // 1: LDS-aggregated deposit; 0: direct device atomics
     float L, halfL;
     float inv_bin;         // nb / L
+    float bin_w;           // L / nb in float32 arithmetic
     float h, inv_h, inv_2h, inv_h2;
     float dt, k;
     int32_t tile_totals;   // 1: the histogram also totals each scan tile
@@ -102,6 +103,8 @@ struct Buffers {
                            // each), added with the bin counts
     float *c[2];           // chemical, two buffers for substeps
     unsigned long long *S_src, *S_upt;  // fixed-point deposits
+    uint32_t *slab_cnt;    // per node slab: its agent count if handed over, else 0
+    uint32_t *slab_tab;    // per node slab: the run table of a handed-over slab
     InstInfo *inst;
     uint8_t *species_id;   // species in id order (for set_state)
     uint32_t *step;        // device step counter
@@ -158,10 +161,18 @@ void launch_overlap(const StepParams &p, const Buffers &b, int src, int dst, int
                     hipStream_t s);
 size_t chem_inst_lds_bytes(const PdeParams &q);
 // owner-computes deposit by slabs of nodes (pc_deposit.hip); with fuse_pde
-// also the single PDE substep of the step (and the step counter)
-size_t chem_slab_lds_bytes(const StepParams &p);
-void launch_chem_slabs(const StepParams &p, const PdeParams &q, const Buffers &b, int src,
-                       int cur, int fuse_pde, hipStream_t s);
+// also the single PDE substep of the step (and the step counter).  Slabs
+// with more than split agents are handed to an agent-parallel pass.
+struct SlabShape {
+    int By, Bz, nby, nbz;
+    int64_t nslabs;        // over all instances
+    size_t lds_bytes;      // LDS sums per deposited field
+};
+bool chem_slab_shape(int dim, int n, double bins_per_cell, int n_inst, SlabShape &sh);
+size_t chem_slab_table_words();
+void launch_chem_slabs(const StepParams &p, const PdeParams &q, const Buffers &b,
+                       const SlabShape &sh, uint32_t split, int src, int cur, int fuse_pde,
+                       hipStream_t s);
 void launch_chem_inst(const StepParams &p, const PdeParams &q, const Buffers &b, int src, int cur,
                       int n_sub, hipStream_t s);
 int launch_species_hist(const StepParams &p, const Buffers &b, int src, int m, float s,

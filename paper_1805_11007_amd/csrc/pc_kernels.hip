@@ -318,18 +318,24 @@ k_update(StepParams p, const InstInfo *__restrict__ inst, const float4 *__restri
     const float4 pi = Ps[i];
     const uint32_t id = Is[i];
     const int si = species_of(pi.w);
-    const InstInfo ii = inst[inst_of(pi.w)];
+    // instance tables are equal-sized: the bin and node bases follow from
+    // the instance index without waiting for its table entry (whose noise
+    // key and chi scale are needed only after the pair loop)
+    const uint32_t kin = inst_of(pi.w);
+    const uint32_t bin_base = kin * (uint32_t)p.bins_per_inst;
+    const uint32_t node_base = kin * (uint32_t)p.nodes_per_inst;
+    const InstInfo ii = inst[kin];
 
     float F[3] = {0.f, 0.f, 0.f};
     if (POT == 0) {
         ForceVisitor fv{p.k, p.fcap, {0.f, 0.f, 0.f}};
-        pair_loop<DIM, NS, STENCIL>(p, tab, Ps, start, ii.bin_base, pi, si, fv);
+        pair_loop<DIM, NS, STENCIL>(p, tab, Ps, start, bin_base, pi, si, fv);
         F[0] = fv.F[0];
         F[1] = fv.F[1];
         F[2] = fv.F[2];
     } else if (POT == 1) {
         ExpVisitor ev{p.k, {0.f, 0.f, 0.f}};
-        pair_loop<DIM, NS, STENCIL>(p, tab, Ps, start, ii.bin_base, pi, si, ev);
+        pair_loop<DIM, NS, STENCIL>(p, tab, Ps, start, bin_base, pi, si, ev);
         F[0] = ev.F[0];
         F[1] = ev.F[1];
         F[2] = ev.F[2];
@@ -346,7 +352,7 @@ k_update(StepParams p, const InstInfo *__restrict__ inst, const float4 *__restri
     const float chi = sel<NS>(p.chi, tab.chi, si) * ii.chi_scale;
     if (chi != 0.0f) {
         float g[3];
-        grad_interp<DIM>(p, c + ii.node_base, pi, g);
+        grad_interp<DIM>(p, c + node_base, pi, g);
         drift[0] = chi * g[0];
         drift[1] = chi * g[1];
         drift[2] = chi * g[2];
@@ -372,7 +378,7 @@ k_update(StepParams p, const InstInfo *__restrict__ inst, const float4 *__restri
         if (to >= 0) {
             float prob = sel<NS>(p.react_p, p.react_p, si);
             const float rc = sel<NS>(p.react_cdt, p.react_cdt, si);
-            if (rc != 0.0f) prob = fmaf(rc, value_interp<DIM>(p, c + ii.node_base, pi), prob);
+            if (rc != 0.0f) prob = fmaf(rc, value_interp<DIM>(p, c + node_base, pi), prob);
             const U4 wr = philox4x32_10(*stepc, id, ii.stream, 1u, ii.key0, ii.key1);
             if (uniform24(wr.v[0]) < prob)
                 xn.w = __uint_as_float((__float_as_uint(pi.w) & ~0xffu) | (uint32_t)to);
@@ -382,7 +388,7 @@ k_update(StepParams p, const InstInfo *__restrict__ inst, const float4 *__restri
     if (!(isfinite(xn.x) && isfinite(xn.y) && isfinite(xn.z))) flag |= FLAG_NONFINITE;
     Pout[i] = xn;
     Iout[i] = id;
-    const uint32_t b = ii.bin_base + agent_bin<DIM>(p, xn);
+    const uint32_t b = bin_base + agent_bin<DIM>(p, xn);
     bin[i] = b;
     rank[i] = count_bin(count, tile_cnt, b, p.tile_totals, p.tile_reps);
     if (flag) atomicOr(flags, flag);

@@ -56,6 +56,7 @@ class ModelSpec:
     deposit_mode: int = 0    # 0 auto, 1 LDS-aggregated, 2 direct atomics, 3 fused per instance,
                              # 4 owner-computes node slabs (3D)
     deposit_kernel: int = 0  # 0 particle-in-cell, 1 Gaussian kernel density (Sect. 2.3)
+    slab_split: int = 0      # slab deposit: agents above which a slab is handed over (0: 2048)
     kde_radius: float = 0.0  # kernel truncation in bandwidths (0: 3)
     potential: int = 0       # 0 harmonic, 1 exponential k exp(-r/d), 2 hard spheres
     tamed: bool = False      # tamed Euler pair drift (eq. sde_ETamed)
@@ -95,6 +96,7 @@ class ModelSpec:
         cfg.bin_order = 0
         cfg.deposit_mode = self.deposit_mode
         cfg.deposit_kernel = self.deposit_kernel
+        cfg.slab_split = self.slab_split
         cfg.kde_radius = self.kde_radius
         cfg.potential = self.potential
         cfg.tamed = 1 if self.tamed else 0

@@ -283,19 +283,23 @@ def test_deposit_modes_bitwise_equal(name, n, g, modes):
     """The deposit is an integer sum: LDS-aggregated, direct-atomic,
     per-instance fused (deposit + PDE substeps in one work-group) and
     owner-computes slab (gathered through the cell list of X^{n+1}, fused
-    with a single PDE substep) paths give the same bits, step after step."""
+    with a single PDE substep) paths give the same bits, step after step.
+    The slab path runs with its default hand-over threshold, with every
+    slab of more than one agent handed to the agent-parallel pass, and with
+    a threshold that splits the slabs into both kinds."""
     w = _dep_case(name, n, g)
     inp = W.make_inputs(w)
     a = make_sim(w, inp, deterministic=True, deposit_mode=1)
     assert a.info["deposit_path"] == 1
     a.step(7)
     xa, ca = _state(a)
-    for m in modes:
-        b = make_sim(w, inp, deterministic=True, deposit_mode=m)
+    runs = [(m, 0) for m in modes] + [(4, 1), (4, 150)] * (4 in modes)
+    for m, split in runs:
+        b = make_sim(w, inp, deterministic=True, deposit_mode=m, slab_split=split)
         assert b.info["deposit_path"] == (5 if m == 4 else m)
         b.step(7)
         xb, cb = _state(b)
-        assert np.array_equal(xa, xb) and np.array_equal(ca, cb), m
+        assert np.array_equal(xa, xb) and np.array_equal(ca, cb), (m, split)
         b.close()
 
 
