@@ -67,7 +67,7 @@ static bool reacts(const pc_species_t &s) {
 }
 
 struct Layout {
-    size_t P[3], I[3], bin, rank, count, start, tile_sum, tile_cnt, c[2], S_src, S_upt, slab_cnt,
+    size_t P[3], I[3], bin, count, start, tile_sum, tile_cnt, c[2], S_src, S_upt, slab_cnt,
         slab_tab, inst, species_id, step, flags, seg_x, seg_c, lamX[2], lamY, lamC[2], aSrc, aUpt, lamG, csub, dth;
     size_t total;
 };
@@ -218,7 +218,6 @@ Layout layout(const Derived &d, int seg_steps) {
     for (int k = 0; k < 3; ++k) L.P[k] = take(cur, 16 * N);
     for (int k = 0; k < 3; ++k) L.I[k] = take(cur, 4 * N);
     L.bin = take(cur, 4 * N);
-    L.rank = take(cur, 4 * N);
     L.count = take(cur, 4 * ((size_t)d.bins_total + 1));
     L.start = take(cur, 4 * ((size_t)d.bins_total + 1));
     L.tile_sum = take(cur, 4 * (((size_t)d.bins_total + 1 + kScanTile - 1) / kScanTile));
@@ -277,7 +276,7 @@ struct pc_sim {
     int seg_steps;
     uint32_t flags_host;
     // Pipeline state.  A step is: [bin] scan scatter [stable] update deposit pde.
-    // binned:  count/bin/rank hold the cell-list counts of the positions in P[0]
+    // binned:  count/bin hold the cell-list counts of the positions in P[0]
     // sorted:  P[sorted_src] / start hold the cell-sorted current positions
     int binned, sorted, sorted_src;
     int chem_fused;           // deposit + PDE in one per-instance kernel (k_chem_inst)
@@ -402,7 +401,6 @@ static void carve(pc_sim *s, char *ws) {
         b.I[k] = (uint32_t *)(ws + L.I[k]);
     }
     b.bin = (uint32_t *)(ws + L.bin);
-    b.rank = (uint32_t *)(ws + L.rank);
     b.count = (uint32_t *)(ws + L.count);
     b.start = (uint32_t *)(ws + L.start);
     b.tile_sum = (uint32_t *)(ws + L.tile_sum);

@@ -47,17 +47,43 @@ __global__ void k_init_agents(StepParams p, const InstInfo *__restrict__ inst,
     I[g] = (uint32_t)g - inst[lo].agent_base;
 }
 
-// Histogram of one agent's bin b: its rank within the bin and, when the
-// scan takes its tile totals from the histogram (totals != 0), the agent
-// added to the total of b's scan tile.  The tile totals are summed over the
-// wave first, one device atomic per distinct tile: in the update and the
-// overlap pass agents come in cell order and a wave rarely spans more than
-// two tiles; after a state load (k_bin, id order) it may span many.
-__device__ __forceinline__ uint32_t count_bin(uint32_t *__restrict__ count,
-                                              uint32_t *__restrict__ tile_cnt, uint32_t b,
-                                              int32_t totals, int32_t reps) {
-    const uint32_t r = atomicAdd(count + b, 1u);
-    if (!totals) return r;
+// Runs of one bin over consecutive active lanes of a wave (agents come in
+// cell order, so a collapsed cluster fills whole waves with one bin): the
+// run's first lane, its length and this lane's place in it.  Inactive lanes
+// are only the tail of the last wave.
+struct WaveRun {
+    int head, len, pos;
+};
+
+__device__ __forceinline__ WaveRun wave_run(uint32_t b) {
+    const int lane = (int)__lane_id();
+    const unsigned long long act = __ballot(1);
+    const uint32_t prev = __shfl_up(b, 1u, 64);
+    const unsigned long long heads = __ballot(lane == 0 || prev != b) | ~act;
+    const unsigned long long upto = lane == 63 ? ~0ull : (2ull << lane) - 1ull;
+    WaveRun r;
+    r.head = 63 - __clzll((long long)(heads & upto));
+    const unsigned long long after = heads & ~upto;
+    r.len = (after ? __ffsll((long long)after) - 1 : 64) - r.head;
+    r.pos = lane - r.head;
+    return r;
+}
+
+// Histogram of one agent's bin b: one added to its count and, when the scan
+// takes its tile totals from the histogram (totals != 0), to the total of
+// b's scan tile.  Neither add returns a value, so the wave does not wait on
+// the device atomic (the scatter takes the agent's slot in the bin later,
+// when it counts the bin back down to zero), and a run of lanes with one
+// bin adds its length with one atomic.  The tile totals are summed
+// over the wave first, one device atomic per distinct tile: in the update
+// and the overlap pass agents come in cell order and a wave rarely spans
+// more than two tiles; after a state load (k_bin, id order) it may span many.
+__device__ __forceinline__ void count_bin(uint32_t *__restrict__ count,
+                                          uint32_t *__restrict__ tile_cnt, uint32_t b,
+                                          int32_t totals, int32_t reps) {
+    const WaveRun run = wave_run(b);
+    if (run.pos == 0) atomicAdd(count + b, (uint32_t)run.len);
+    if (!totals) return;
     // this wave's counter of the tile (reps is 1 or a power of two)
     const uint32_t rep = ((blockIdx.x * blockDim.x + threadIdx.x) >> 6) & (uint32_t)(reps - 1);
     const uint32_t t = b >> kScanTileLog2;
@@ -70,13 +96,12 @@ __device__ __forceinline__ uint32_t count_bin(uint32_t *__restrict__ count,
             break;
         }
     }
-    return r;
 }
 
 template <int DIM>
 __global__ void k_bin(StepParams p, const InstInfo *__restrict__ inst,
                       const float4 *__restrict__ P, uint32_t *__restrict__ bin,
-                      uint32_t *__restrict__ rank, uint32_t *__restrict__ count,
+                      uint32_t *__restrict__ count,
                       uint32_t *__restrict__ tile_cnt) {
     const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
     const int i = blk * blockDim.x + threadIdx.x;
@@ -84,7 +109,7 @@ __global__ void k_bin(StepParams p, const InstInfo *__restrict__ inst,
     const float4 x = P[i];
     const uint32_t b = inst[inst_of(x.w)].bin_base + agent_bin<DIM>(p, x);
     bin[i] = b;
-    rank[i] = count_bin(count, tile_cnt, b, p.tile_totals, p.tile_reps);
+    count_bin(count, tile_cnt, b, p.tile_totals, p.tile_reps);
 }
 
 // Block-wide exclusive scan of one value per thread (blockDim = 256).
@@ -215,8 +240,9 @@ __global__ void __launch_bounds__(1024) k_scan_tiles(uint32_t *__restrict__ tile
 // Bin starts of one tile from its counts and the tile's prefix.  A tile
 // holding no agent (its prefix equals the next one; the last tile ends at
 // n_agents) has only zero counts: its starts are all the prefix, written
-// without reading or clearing the counts.
-__global__ void __launch_bounds__(256) k_scan_apply(uint32_t *__restrict__ count, int64_t n,
+// without reading the counts.  The counts stay: the scatter counts them
+// back down to zero.
+__global__ void __launch_bounds__(256) k_scan_apply(const uint32_t *__restrict__ count, int64_t n,
                                                     const uint32_t *__restrict__ tile_sum,
                                                     uint32_t *__restrict__ start, int T,
                                                     uint32_t n_agents) {
@@ -249,28 +275,30 @@ __global__ void __launch_bounds__(256) k_scan_apply(uint32_t *__restrict__ count
         uint4 *st4 = reinterpret_cast<uint4 *>(start + base);
         st4[0] = make_uint4(o[0], o[1], o[2], o[3]);
         st4[1] = make_uint4(o[4], o[5], o[6], o[7]);
-        // clear the counts for the next histogram, skipping groups already
-        // zero (most bins are empty, so most lines stay clean)
-        uint4 *c4 = reinterpret_cast<uint4 *>(count + base);
-        if (v[0] | v[1] | v[2] | v[3]) c4[0] = make_uint4(0u, 0u, 0u, 0u);
-        if (v[4] | v[5] | v[6] | v[7]) c4[1] = make_uint4(0u, 0u, 0u, 0u);
     } else {
         for (int k = 0; k < 8; ++k)
-            if (base + k < n) {
-                start[base + k] = o[k];
-                count[base + k] = 0u;
-            }
+            if (base + k < n) start[base + k] = o[k];
     }
 }
 
+// Each agent takes a slot in its bin by counting the bin down: the slots
+// 0 .. n_b - 1 go to its n_b agents in the order their decrements arrive
+// (deterministic mode then orders each bin by id), and the counts are back
+// at zero for the next histogram.  A run of lanes with one bin takes its
+// slots with one atomic, its first lane's, and shares the old count.
 __global__ void k_scatter(int n, const float4 *__restrict__ P, const uint32_t *__restrict__ I,
-                          const uint32_t *__restrict__ bin, const uint32_t *__restrict__ rank,
+                          const uint32_t *__restrict__ bin, uint32_t *__restrict__ count,
                           const uint32_t *__restrict__ start, float4 *__restrict__ Ps,
                           uint32_t *__restrict__ Is) {
     const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
     const int i = blk * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const uint32_t d = start[bin[i]] + rank[i];
+    const uint32_t b = bin[i];
+    const WaveRun run = wave_run(b);
+    uint32_t top = 0;
+    if (run.pos == 0) top = atomicSub(count + b, (uint32_t)run.len);
+    top = __shfl(top, run.head, 64);
+    const uint32_t d = start[b] + top - 1u - (uint32_t)run.pos;
     Ps[d] = P[i];
     Is[d] = I[i];
 }
@@ -296,15 +324,15 @@ __global__ void k_stable(StepParams p, const InstInfo *__restrict__ inst,
 
 // The fused particle update of one step, one thread per cell-sorted agent:
 // pair repulsion at X^n, chemotactic drift from c^n at X^n, Euler-Maruyama
-// with Philox normals, boundary closure; then the cell-list bin of X^{n+1}
-// and the agent's rank in it (the counting sort of the next step).
+// with Philox normals, boundary closure; then the cell-list bin of X^{n+1},
+// counted into the histogram of the next step's counting sort.
 // POT: 0 harmonic, 1 exponential, 2 hard spheres (no pair force here).
 template <int DIM, int NS, int STENCIL, int POT>
 __global__ void __launch_bounds__(1024)
 k_update(StepParams p, const InstInfo *__restrict__ inst, const float4 *__restrict__ Ps,
          const uint32_t *__restrict__ Is, const uint32_t *__restrict__ start,
          const float *__restrict__ c, float4 *__restrict__ Pout, uint32_t *__restrict__ Iout,
-         uint32_t *__restrict__ bin, uint32_t *__restrict__ rank, uint32_t *__restrict__ count,
+         uint32_t *__restrict__ bin, uint32_t *__restrict__ count,
          uint32_t *__restrict__ tile_cnt,
          const uint32_t *__restrict__ stepc, uint32_t *__restrict__ flags) {
     __shared__ SpTab tab;
@@ -390,7 +418,7 @@ k_update(StepParams p, const InstInfo *__restrict__ inst, const float4 *__restri
     Iout[i] = id;
     const uint32_t b = bin_base + agent_bin<DIM>(p, xn);
     bin[i] = b;
-    rank[i] = count_bin(count, tile_cnt, b, p.tile_totals, p.tile_reps);
+    count_bin(count, tile_cnt, b, p.tile_totals, p.tile_reps);
     if (flag) atomicOr(flags, flag);
 }
 
@@ -722,14 +750,14 @@ k_debug_pairs(StepParams p, const InstInfo *__restrict__ inst, const float4 *__r
 // Hard-sphere overlap correction (Sect. 2.2) at the updated, cell-sorted
 // positions: every pair closer than its contact distance pushes i away by
 // 2 (d - r) D_i / (D_i + D_j); all pushes come from the same positions.
-// Then the boundary closure, and the bin / rank of the corrected position
-// (the counting sort of the next step), as the update kernel does.
+// Then the boundary closure, and the bin of the corrected position counted
+// for the counting sort of the next step, as the update kernel does.
 template <int DIM, int NS, int STENCIL>
 __global__ void __launch_bounds__(1024)
 k_overlap(StepParams p, const InstInfo *__restrict__ inst, const float4 *__restrict__ Ps,
           const uint32_t *__restrict__ Is, const uint32_t *__restrict__ start,
           float4 *__restrict__ Pout, uint32_t *__restrict__ Iout, uint32_t *__restrict__ bin,
-          uint32_t *__restrict__ rank, uint32_t *__restrict__ count,
+          uint32_t *__restrict__ count,
           uint32_t *__restrict__ tile_cnt, uint32_t *__restrict__ flags) {
     __shared__ SpTab tab;
     load_tab(p, tab);
@@ -753,7 +781,7 @@ k_overlap(StepParams p, const InstInfo *__restrict__ inst, const float4 *__restr
     Iout[i] = Is[i];
     const uint32_t b = ii.bin_base + agent_bin<DIM>(p, xn);
     bin[i] = b;
-    rank[i] = count_bin(count, tile_cnt, b, p.tile_totals, p.tile_reps);
+    count_bin(count, tile_cnt, b, p.tile_totals, p.tile_reps);
     if (flag) atomicOr(flags, flag);
 }
 
@@ -780,10 +808,10 @@ void launch_init_agents(const StepParams &p, const Buffers &b, const float *x, c
 void launch_bin(const StepParams &p, const Buffers &b, int src, int block, hipStream_t s) {
     const dim3 g(grid_for(p.n_total, block)), t(block);
     if (p.dim == 2)
-        hipLaunchKernelGGL(k_bin<2>, g, t, 0, s, p, b.inst, b.P[src], b.bin, b.rank, b.count,
+        hipLaunchKernelGGL(k_bin<2>, g, t, 0, s, p, b.inst, b.P[src], b.bin, b.count,
                            b.tile_cnt);
     else
-        hipLaunchKernelGGL(k_bin<3>, g, t, 0, s, p, b.inst, b.P[src], b.bin, b.rank, b.count,
+        hipLaunchKernelGGL(k_bin<3>, g, t, 0, s, p, b.inst, b.P[src], b.bin, b.count,
                            b.tile_cnt);
 }
 
@@ -801,7 +829,7 @@ void launch_scan(const StepParams &p, const Buffers &b, int64_t n_bins_total, hi
 void launch_scatter(const StepParams &p, const Buffers &b, int src, int dst, int block,
                     hipStream_t s) {
     hipLaunchKernelGGL(k_scatter, dim3(grid_for(p.n_total, block)), dim3(block), 0, s, p.n_total,
-                       b.P[src], b.I[src], b.bin, b.rank, b.start, b.P[dst], b.I[dst]);
+                       b.P[src], b.I[src], b.bin, b.count, b.start, b.P[dst], b.I[dst]);
 }
 
 void launch_stable(const StepParams &p, const Buffers &b, int src, int dst, int block,
@@ -820,7 +848,7 @@ static void upd(const StepParams &p, const Buffers &b, int src, int dst, int cbu
                 hipStream_t s) {
     hipLaunchKernelGGL((k_update<DIM, NS, ST, 0>), dim3(grid_for(p.n_total, block)), dim3(block),
                        0, s, p, b.inst, b.P[src], b.I[src], b.start, b.c[cbuf], b.P[dst],
-                       b.I[dst], b.bin, b.rank, b.count, b.tile_cnt, b.step, b.flags);
+                       b.I[dst], b.bin, b.count, b.tile_cnt, b.step, b.flags);
 }
 
 // the exponential potential with the species specialisations of the
@@ -830,7 +858,7 @@ static void upd_exp(const StepParams &p, const Buffers &b, int src, int dst, int
                     hipStream_t s) {
     hipLaunchKernelGGL((k_update<DIM, NS, ST, 1>), dim3(grid_for(p.n_total, block)), dim3(block),
                        0, s, p, b.inst, b.P[src], b.I[src], b.start, b.c[cbuf], b.P[dst],
-                       b.I[dst], b.bin, b.rank, b.count, b.tile_cnt, b.step, b.flags);
+                       b.I[dst], b.bin, b.count, b.tile_cnt, b.step, b.flags);
 }
 
 // the hard-sphere overlap pass with the species specialisations of the pair
@@ -840,7 +868,7 @@ static void ovl(const StepParams &p, const Buffers &b, int src, int dst, int blo
                 hipStream_t s) {
     hipLaunchKernelGGL((k_overlap<DIM, NS, ST>), dim3(grid_for(p.n_total, block)), dim3(block),
                        0, s, p, b.inst, b.P[src], b.I[src], b.start, b.P[dst], b.I[dst], b.bin,
-                       b.rank, b.count, b.tile_cnt, b.flags);
+                       b.count, b.tile_cnt, b.flags);
 }
 
 // hard spheres (and a harmonic k = 0) use the generic (LDS) species table
@@ -849,7 +877,7 @@ static void upd_pot(const StepParams &p, const Buffers &b, int src, int dst, int
                     hipStream_t s) {
     hipLaunchKernelGGL((k_update<DIM, 0, ST, POT>), dim3(grid_for(p.n_total, block)),
                        dim3(block), 0, s, p, b.inst, b.P[src], b.I[src], b.start, b.c[cbuf],
-                       b.P[dst], b.I[dst], b.bin, b.rank, b.count, b.tile_cnt, b.step,
+                       b.P[dst], b.I[dst], b.bin, b.count, b.tile_cnt, b.step,
                        b.flags);
 }
 
