@@ -122,7 +122,7 @@ typedef struct {
                                ignored (3 and 4 are rejected)                          */
     int32_t slab_split;     /* deposit_mode 4 (slabs): a slab whose cells hold more than
                                this many agents (0: 2048) is handed over: its agents are
-                               spread in chunks of 2048 over many work-groups, which
+                               spread in chunks of 1024 over many work-groups, which
                                add their node sums with device atomics, so that a blob
                                collapsed into a few cells does not serialise on one
                                work-group.  The sums are integers: the bits do not

@@ -40,8 +40,18 @@ def cache_path() -> Path:
     return Path.home() / ".cache" / "paper_1805_11007_amd" / "autotune.json"
 
 
+def device_key() -> str:
+    """The device's ISA and compute-unit count (its marketing name is not
+    always available, e.g. under a profiler)."""
+    if not torch.cuda.is_available():
+        return "cpu"
+    pr = torch.cuda.get_device_properties(0)
+    arch = getattr(pr, "gcnArchName", "") or torch.cuda.get_device_name(0) or "gpu"
+    return f"{arch.split(':')[0]}x{pr.multi_processor_count}"
+
+
 def shape_key(spec: ModelSpec, horizon: int = 0) -> str:
-    dev = torch.cuda.get_device_name(0) if torch.cuda.is_available() else "cpu"
+    dev = device_key()
     n = spec.n_total
     bucket = 2 ** round(math.log2(max(n, 1)))
     return (f"{dev}|d{spec.dim}|N~{bucket}|inst{len(spec.instances)}|g{spec.grid_n}|"

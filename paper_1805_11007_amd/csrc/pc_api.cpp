@@ -58,8 +58,7 @@ constexpr int64_t kDepositAggMinAgents = 256 * 1024;
 // runs deposit + PDE as one work-group per instance.
 constexpr int kFusedMinInstances = 64;
 // Agents above which a slab of the owner-computes deposit is handed to the
-// agent-parallel pass (2 per thread of its 1024-thread work-group; 1024 to
-// 4096 measured within 3% on the 1M 3D run).
+// agent-parallel pass (8 per thread of its 256-thread work-group).
 constexpr uint32_t kSlabSplitDefault = 2048;
 
 static bool reacts(const pc_species_t &s) {

@@ -13,9 +13,9 @@
 // the slab lie in the bin rows of a range of y for each z of a range: in
 // the row-major bin order each such z layer is one contiguous run of the
 // sorted agents.  The work-group lays its few runs end to end, every thread
-// takes agents from them (consecutive threads on consecutive agents), adds
-// the corners that fall in its slab into LDS sums, and then either stores
-// each owned node's sums once, or, when the step has a single PDE substep,
+// takes eight consecutive agents from them, sums the corners that fall in
+// its slab per cell in registers and adds them to LDS sums, and then stores
+// each owned node's sums once or, when the step has a single PDE substep,
 // applies the forward-Euler update of eq. pde_c to its owned nodes
 // directly (the sums never reach HBM).  Each corner is added by exactly one
 // work-group, so every node receives the same integer as on every other
@@ -35,12 +35,14 @@
 namespace pc {
 
 constexpr int kSlabRuns = 256;   // contiguous agent runs per slab (LDS table)
+constexpr int kSlabThreads = kSlabRuns;   // one run lookup per thread
 // per-slab run table handed to k_slab_assist: run count, run starts, prefixes
 constexpr int kSlabTableWords = 2 * kSlabRuns + 2;
-constexpr int kAssistChunk = 2048;   // agents of a heavy slab per assisting pass
+constexpr int kAssistChunk = 1024;   // agents of a heavy slab per assisting pass
 constexpr int kAssistThreads = 256;
 constexpr int kAssistBlocks = 1024;
 constexpr int kAssistSlabBlock = 4 * kAssistThreads;   // slab counts scanned per pass
+constexpr int kFinishParts = 4;   // work-groups per handed-over slab in k_slab_finish
 
 // Bins holding every agent whose cell lies in [c0, c1] along one axis, as
 // up to two disjoint inclusive intervals (c0 = -1 on the torus: cell n - 1
@@ -107,59 +109,124 @@ __device__ __forceinline__ SlabGeom slab_geom(int s, int n, int By, int Bz, int 
     return g;
 }
 
-// The corners of agent x that fall in the slab's owned nodes, added to the
-// LDS sums (source, then uptake at offset owned).
+// Corner sums of a run of agents in one cell, kept in registers and added
+// to the LDS sums when the cell changes: agents in cell order repeat their
+// cell, and inside a collapsed blob every lane of a wave would otherwise
+// add to the same few LDS words.  Each corner value is the fixed-point
+// integer of the charge times the axis weights in axis order, as on every
+// deposit path, so sums of them are the same integers in any grouping.
 template <int DIM, int NS, bool UPT>
-__device__ __forceinline__ void slab_agent(const StepParams &p, const SpTab &tab, const float4 x,
-                                           const SlabGeom &g, unsigned long long *sums) {
-    const int n = p.grid_n;
-    const int s = species_of(x.w);
-    const float qs = sel<NS>(p.src_fx, tab.src, s);
-    const float qu = UPT ? sel<NS>(p.upt_fx, tab.upt, s) : 0.0f;
-    if (qs == 0.0f && qu == 0.0f) return;
-    Cell cc[3];
-    cc[0] = cell_of(p, x.x);
-    cc[1] = cell_of(p, x.y);
-    cc[2] = Cell{0, 0, 0.0f};
-    if (DIM == 3) cc[2] = cell_of(p, x.z);
-    // owned corner offsets along y and z (-1: outside the slab)
-    const int ly0 = cc[1].i0 - g.y0, ly1 = cc[1].i1 - g.y0;
-    const int oy[2] = {(ly0 >= 0 && ly0 < g.y1 - g.y0) ? ly0 : -1,
-                       (ly1 >= 0 && ly1 < g.y1 - g.y0) ? ly1 : -1};
-    int oz[2] = {0, -1};
-    if (DIM == 3) {
-        const int lz0 = cc[2].i0 - g.z0, lz1 = cc[2].i1 - g.z0;
-        oz[0] = (lz0 >= 0 && lz0 < g.z1 - g.z0) ? lz0 : -1;
-        oz[1] = (lz1 >= 0 && lz1 < g.z1 - g.z0) ? lz1 : -1;
-    }
-    const int ox[2] = {cc[0].i0, cc[0].i1};
-    const int ny = g.y1 - g.y0;
+struct SlabAcc {
+    int key;                      // cell of the held sums (-1: none)
+    int l[1 << DIM];              // their owned-node indices (-1: not owned)
+    unsigned long long s[1 << DIM], u[1 << DIM];
+
+    __device__ __forceinline__ void init() { key = -1; }
+
+    __device__ __forceinline__ void flush(unsigned long long *sums, int owned) {
+        if (key < 0) return;
 #pragma unroll
-    for (int m = 0; m < (1 << DIM); ++m) {
-        const int ux = m & 1, uy = (m >> 1) & 1, uz = (m >> 2) & 1;
-        // the charge times the axis weights in axis order, as every deposit
-        // path forms it
-        float ws = qs, wu = qu;
-        const float fx = ux ? cc[0].t : 1.0f - cc[0].t;
-        const float fy = uy ? cc[1].t : 1.0f - cc[1].t;
-        ws *= fx;
-        if (UPT) wu *= fx;
-        ws *= fy;
-        if (UPT) wu *= fy;
-        if (DIM == 3) {
-            const float fz = uz ? cc[2].t : 1.0f - cc[2].t;
-            ws *= fz;
-            if (UPT) wu *= fz;
+        for (int m = 0; m < (1 << DIM); ++m) {
+            if (l[m] < 0) continue;
+            if (s[m]) atomicAdd(&sums[l[m]], s[m]);
+            if (UPT && u[m]) atomicAdd(&sums[owned + l[m]], u[m]);
         }
-        if (oy[uy] < 0 || oz[uz] < 0) continue;
-        const int l = ox[ux] + n * (oy[uy] + ny * oz[uz]);
-        const unsigned long long vs = (unsigned long long)__float2ull_rn(ws);
-        if (vs) atomicAdd(&sums[l], vs);
-        if (UPT) {
-            const unsigned long long vu = (unsigned long long)__float2ull_rn(wu);
-            if (vu) atomicAdd(&sums[g.owned + l], vu);
+        key = -1;
+    }
+
+    __device__ __forceinline__ void add(const StepParams &p, const SpTab &tab, const float4 x,
+                                        const SlabGeom &g, unsigned long long *sums) {
+        const int n = p.grid_n;
+        const int sp = species_of(x.w);
+        const float qs = sel<NS>(p.src_fx, tab.src, sp);
+        const float qu = UPT ? sel<NS>(p.upt_fx, tab.upt, sp) : 0.0f;
+        if (qs == 0.0f && qu == 0.0f) return;
+        Cell cc[3];
+        cc[0] = cell_of(p, x.x);
+        cc[1] = cell_of(p, x.y);
+        cc[2] = Cell{0, 0, 0.0f};
+        if (DIM == 3) cc[2] = cell_of(p, x.z);
+        const int k = cc[0].i0 + n * (cc[1].i0 + n * cc[2].i0);
+        if (k != key) {
+            flush(sums, g.owned);
+            key = k;
+            const int ly0 = cc[1].i0 - g.y0, ly1 = cc[1].i1 - g.y0;
+            const int oy[2] = {(ly0 >= 0 && ly0 < g.y1 - g.y0) ? ly0 : -1,
+                               (ly1 >= 0 && ly1 < g.y1 - g.y0) ? ly1 : -1};
+            int oz[2] = {0, -1};
+            if (DIM == 3) {
+                const int lz0 = cc[2].i0 - g.z0, lz1 = cc[2].i1 - g.z0;
+                oz[0] = (lz0 >= 0 && lz0 < g.z1 - g.z0) ? lz0 : -1;
+                oz[1] = (lz1 >= 0 && lz1 < g.z1 - g.z0) ? lz1 : -1;
+            }
+            const int ny = g.y1 - g.y0;
+#pragma unroll
+            for (int m = 0; m < (1 << DIM); ++m) {
+                const int ux = m & 1, uy = (m >> 1) & 1, uz = (m >> 2) & 1;
+                l[m] = (oy[uy] < 0 || oz[uz] < 0) ? -1
+                                                  : (ux ? cc[0].i1 : cc[0].i0) + n * (oy[uy] + ny * oz[uz]);
+                s[m] = 0ull;
+                u[m] = 0ull;
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < (1 << DIM); ++m) {
+            const int ux = m & 1, uy = (m >> 1) & 1, uz = (m >> 2) & 1;
+            // the charge times the axis weights in axis order, as every
+            // deposit path forms it
+            float ws = qs, wu = qu;
+            const float fx = ux ? cc[0].t : 1.0f - cc[0].t;
+            const float fy = uy ? cc[1].t : 1.0f - cc[1].t;
+            ws *= fx;
+            if (UPT) wu *= fx;
+            ws *= fy;
+            if (UPT) wu *= fy;
+            if (DIM == 3) {
+                const float fz = uz ? cc[2].t : 1.0f - cc[2].t;
+                ws *= fz;
+                if (UPT) wu *= fz;
+            }
+            s[m] += (unsigned long long)__float2ull_rn(ws);
+            if (UPT) u[m] += (unsigned long long)__float2ull_rn(wu);
         }
     }
+};
+
+// Agents [a, e) of a slab's runs laid end to end (run_a: run starts in the
+// cell list, run_pre: exclusive prefixes of the run lengths), kPer
+// consecutive agents per thread and pass: their loads are issued together,
+// then they are summed per cell in registers and added to the LDS sums.
+template <int DIM, int NS, bool UPT, int kPer>
+__device__ __forceinline__ void slab_run_agents(const StepParams &p, const SpTab &tab,
+                                                const float4 *__restrict__ Ps,
+                                                const uint32_t *run_a, const uint32_t *run_pre,
+                                                int nrun, uint32_t a, uint32_t e,
+                                                const SlabGeom &g, unsigned long long *sums) {
+    SlabAcc<DIM, NS, UPT> acc;
+    acc.init();
+    for (uint32_t w0 = a + threadIdx.x * (uint32_t)kPer; w0 < e;
+         w0 += blockDim.x * (uint32_t)kPer) {
+        int r0 = 0, r1 = nrun - 1;   // the run holding w0
+        while (r0 < r1) {
+            const int mid = (r0 + r1 + 1) >> 1;
+            if (run_pre[mid] <= w0) r0 = mid;
+            else r1 = mid - 1;
+        }
+        float4 xs[kPer];
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            const uint32_t w = w0 + (uint32_t)k;
+            xs[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (w < e) {
+                while (r0 + 1 < nrun && run_pre[r0 + 1] <= w) ++r0;
+                xs[k] = Ps[run_a[r0] + (w - run_pre[r0])];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kPer; ++k)
+            if (w0 + (uint32_t)k < e) acc.add(p, tab, xs[k], g, sums);
+    }
+    acc.flush(sums, g.owned);
 }
 
 template <int DIM>
@@ -172,8 +239,37 @@ __device__ __forceinline__ int64_t slab_node(const SlabGeom &g, const InstInfo &
     return (int64_t)ii.node_base + ic[0] + (int64_t)n * (ic[1] + (int64_t)n * ic[2]);
 }
 
+// The PDE substep at the slab's owned nodes from their deposits (with
+// BY_NODE, HBM arrays indexed by node; else the LDS sums indexed by owned
+// node), two nodes per thread and pass: the second node's index is clamped
+// so that both stencils load unconditionally and only its store is guarded.
+template <int DIM, bool UPT, bool BY_NODE>
+__device__ __forceinline__ void slab_pde_nodes(const PdeParams &q, const SlabGeom &g,
+                                               const InstInfo &ii, int n,
+                                               const float *__restrict__ cin,
+                                               float *__restrict__ cout,
+                                               const unsigned long long *sS,
+                                               const unsigned long long *sU, int lbeg, int lend,
+                                               uint32_t &flag) {
+    for (int l0 = lbeg + threadIdx.x; l0 < lend; l0 += 2 * blockDim.x) {
+        const int l1 = l0 + (int)blockDim.x;
+        const bool two = l1 < lend;
+        const int l1c = two ? l1 : l0;
+        int ic0[3], ic1[3];
+        const int64_t n0 = slab_node<DIM>(g, ii, n, l0, ic0);
+        const int64_t n1 = slab_node<DIM>(g, ii, n, l1c, ic1);
+        const int64_t k0 = BY_NODE ? n0 : l0, k1 = BY_NODE ? n1 : l1c;
+        const unsigned long long s0 = sS[k0], s1 = sS[k1];
+        const unsigned long long u0 = UPT ? sU[k0] : 0ull, u1 = UPT ? sU[k1] : 0ull;
+        const float v0 = pde_node<DIM>(q, cin + ii.node_base, ic0, s0, u0, flag);
+        const float v1 = pde_node<DIM>(q, cin + ii.node_base, ic1, s1, u1, flag);
+        cout[n0] = v0;
+        if (two) cout[n1] = v1;
+    }
+}
+
 template <int DIM, int NS, bool UPT>
-__global__ void __launch_bounds__(1024)
+__global__ void __launch_bounds__(kSlabThreads)
 k_chem_slabs(StepParams p, PdeParams q, const InstInfo *__restrict__ inst,
              const float4 *__restrict__ Ps, const uint32_t *__restrict__ start,
              const float *__restrict__ cin, float *__restrict__ cout,
@@ -262,8 +358,10 @@ k_chem_slabs(StepParams p, PdeParams q, const InstInfo *__restrict__ inst,
         // for its atomics
         uint32_t *T = slab_tab + (size_t)blockIdx.x * kSlabTableWords;
         if (threadIdx.x == 0) T[0] = (uint32_t)nrun;
-        if ((int)threadIdx.x < nrun) T[1 + threadIdx.x] = run_a[threadIdx.x];
-        if ((int)threadIdx.x <= nrun) T[1 + kSlabRuns + threadIdx.x] = run_pre[threadIdx.x];
+        for (int t = threadIdx.x; t <= nrun; t += blockDim.x) {
+            if (t < nrun) T[1 + t] = run_a[t];
+            T[1 + kSlabRuns + t] = run_pre[t];
+        }
         int ic[3];
         for (int l = threadIdx.x; l < owned; l += blockDim.x) {
             const int64_t node = slab_node<DIM>(g, ii, n, l, ic);
@@ -272,24 +370,18 @@ k_chem_slabs(StepParams p, PdeParams q, const InstInfo *__restrict__ inst,
         }
         return;
     }
-    // agents of the runs, laid end to end; a thread's positions increase, so
-    // its run index only moves forward
-    int r = 0;
-    for (uint32_t w = threadIdx.x; w < total; w += blockDim.x) {
-        while (r + 1 < nrun && run_pre[r + 1] <= w) ++r;
-        slab_agent<DIM, NS, UPT>(p, tab, Ps[run_a[r] + (w - run_pre[r])], g, sums);
-    }
+    slab_run_agents<DIM, NS, UPT, 8>(p, tab, Ps, run_a, run_pre, nrun, 0u, total, g, sums);
     __syncthreads();
     uint32_t flag = 0;
-    int ic[3];
-    for (int l = threadIdx.x; l < owned; l += blockDim.x) {
-        const int64_t node = slab_node<DIM>(g, ii, n, l, ic);
-        const unsigned long long sS = sums[l], sU = UPT ? sums[owned + l] : 0ull;
-        if (fuse_pde) {
-            cout[node] = pde_node<DIM>(q, cin + ii.node_base, ic, sS, sU, flag);
-        } else {
-            Ssrc[node] = sS;
-            if (UPT) Supt[node] = sU;
+    if (fuse_pde) {
+        slab_pde_nodes<DIM, UPT, false>(q, g, ii, n, cin, cout, sums, sums + owned, 0, owned,
+                                        flag);
+    } else {
+        int ic[3];
+        for (int l = threadIdx.x; l < owned; l += blockDim.x) {
+            const int64_t node = slab_node<DIM>(g, ii, n, l, ic);
+            Ssrc[node] = sums[l];
+            if (UPT) Supt[node] = sums[owned + l];
         }
     }
     if (flag) atomicOr(flags, flag);
@@ -374,15 +466,9 @@ k_slab_assist(StepParams p, const InstInfo *__restrict__ inst, const float4 *__r
             for (int t = threadIdx.x; t <= nrun; t += blockDim.x) run_pre[t] = T[1 + kSlabRuns + t];
             for (int l = threadIdx.x; l < g.owned * (UPT ? 2 : 1); l += blockDim.x) sums[l] = 0ull;
             __syncthreads();
-            for (uint32_t w = a0 + threadIdx.x; w < a1; w += blockDim.x) {
-                int r0 = 0, r1 = nrun - 1;   // the run holding agent w
-                while (r0 < r1) {
-                    const int mid = (r0 + r1 + 1) >> 1;
-                    if (run_pre[mid] <= w) r0 = mid;
-                    else r1 = mid - 1;
-                }
-                slab_agent<DIM, NS, UPT>(p, tab, Ps[run_a[r0] + (w - run_pre[r0])], g, sums);
-            }
+            slab_run_agents<DIM, NS, UPT, kAssistChunk / kAssistThreads>(p, tab, Ps, run_a,
+                                                                        run_pre, nrun, a0, a1, g,
+                                                                        sums);
             __syncthreads();
             int ic[3];
             for (int l = threadIdx.x; l < g.owned; l += blockDim.x) {
@@ -400,7 +486,8 @@ k_slab_assist(StepParams p, const InstInfo *__restrict__ inst, const float4 *__r
 }
 
 // The single PDE substep at the nodes of the handed-over slabs, from their
-// deposits in HBM (the other slabs applied it in k_chem_slabs).
+// deposits in HBM (the other slabs applied it in k_chem_slabs), a quarter
+// of a slab's nodes per work-group.
 template <int DIM, bool UPT>
 __global__ void __launch_bounds__(256)
 k_slab_finish(StepParams p, PdeParams q, const InstInfo *__restrict__ inst,
@@ -408,17 +495,15 @@ k_slab_finish(StepParams p, PdeParams q, const InstInfo *__restrict__ inst,
               const unsigned long long *__restrict__ Ssrc,
               const unsigned long long *__restrict__ Supt, int By, int Bz, int nby, int nbz,
               const uint32_t *__restrict__ slab_cnt, uint32_t *__restrict__ flags) {
-    if (slab_cnt[blockIdx.x] == 0u) return;
+    const int sl = blockIdx.x / kFinishParts, part = blockIdx.x % kFinishParts;
+    if (slab_cnt[sl] == 0u) return;
     const int n = p.grid_n;
-    const SlabGeom g = slab_geom<DIM>(blockIdx.x, n, By, Bz, nby, nbz);
+    const SlabGeom g = slab_geom<DIM>(sl, n, By, Bz, nby, nbz);
     const InstInfo ii = inst[g.k];
+    const int per = (g.owned + kFinishParts - 1) / kFinishParts;
     uint32_t flag = 0;
-    int ic[3];
-    for (int l = threadIdx.x; l < g.owned; l += blockDim.x) {
-        const int64_t node = slab_node<DIM>(g, ii, n, l, ic);
-        cout[node] = pde_node<DIM>(q, cin + ii.node_base, ic, Ssrc[node], UPT ? Supt[node] : 0ull,
-                                   flag);
-    }
+    slab_pde_nodes<DIM, UPT, true>(q, g, ii, n, cin, cout, Ssrc, Supt, part * per,
+                                   min(g.owned, (part + 1) * per), flag);
     if (flag) atomicOr(flags, flag);
 }
 
@@ -457,7 +542,8 @@ template <int DIM, int NS, bool UPT>
 static void slabs(const StepParams &p, const PdeParams &q, const Buffers &b, const SlabShape &sh,
                   uint32_t split, int src, int cur, int fuse, hipStream_t s) {
     const size_t lds = sh.lds_bytes * (UPT ? 2 : 1);
-    hipLaunchKernelGGL((k_chem_slabs<DIM, NS, UPT>), dim3((unsigned)sh.nslabs), dim3(1024), lds,
+    hipLaunchKernelGGL((k_chem_slabs<DIM, NS, UPT>), dim3((unsigned)sh.nslabs), dim3(kSlabThreads),
+                       lds,
                        s, p, q, b.inst, b.P[src], b.start, b.c[cur], b.c[1 - cur], b.S_src,
                        b.S_upt, sh.By, sh.Bz, sh.nby, sh.nbz, fuse, split, b.slab_cnt,
                        b.slab_tab, b.flags, b.step);
@@ -465,7 +551,8 @@ static void slabs(const StepParams &p, const PdeParams &q, const Buffers &b, con
                        lds, s, p, b.inst, b.P[src], b.S_src, b.S_upt, sh.By, sh.Bz, sh.nby,
                        sh.nbz, (int)sh.nslabs, b.slab_cnt, b.slab_tab);
     if (fuse)
-        hipLaunchKernelGGL((k_slab_finish<DIM, UPT>), dim3((unsigned)sh.nslabs), dim3(256), 0, s,
+        hipLaunchKernelGGL((k_slab_finish<DIM, UPT>), dim3((unsigned)(sh.nslabs * kFinishParts)),
+                           dim3(256), 0, s,
                            p, q, b.inst, b.c[cur], b.c[1 - cur], b.S_src, b.S_upt, sh.By, sh.Bz,
                            sh.nby, sh.nbz, b.slab_cnt, b.flags);
 }
