@@ -50,13 +50,19 @@ FLOP_PER_PAIR, FLOP_PER_AGENT = 18.0, 140.0
 # agent 3D workload, over the window the default run times (the first 20
 # steps after 5 warm-up steps; each counter in its own run, FETCH_SIZE scaled
 # by 2.0 and WRITE_SIZE by 1.0 from a plain device copy).  Bytes per step
-# (summed over the step's kernels) and per launch of the update kernel.
-# Valid only for the kernel sources they were taken with (a hash of every
-# file under csrc/) and for that workload; reported as null otherwise.
-COUNTER_STEP_BYTES = None
-COUNTER_UPDATE_BYTES = None
-COUNTER_SOURCES_SHA = None
+# (summed over the step's kernels) and per launch of the update kernel,
+# with the tuned choice of that run (bin side = cutoff, 64-thread agent
+# work-groups, slab deposit).  Valid only for the kernel sources they were
+# taken with (a hash of every file under csrc/), for that workload and that
+# deposit path; reported as null otherwise.
+COUNTER_STEP_BYTES = 339288283.0
+COUNTER_UPDATE_BYTES = 82301924.0
+# SQ_INSTS_VALU of the update over its chip issue capacity in the same
+# window (1024 SIMDs x GRBM_GUI_ACTIVE / 8 XCDs / 4 cycles per wave64 op)
+COUNTER_UPDATE_VALU_FRAC = 0.594
+COUNTER_SOURCES_SHA = "47df6974f5a0674d"
 COUNTER_WORKLOAD = "3d_periodic_1M_blobs"
+COUNTER_DEPOSIT_PATH = 5
 
 
 def sources_sha() -> str:
@@ -587,7 +593,8 @@ def main() -> int:
         sim.step(min(10, args.steps - t))
     nbr_mean = float(np.mean(nbr))
 
-    valid = counters_valid(w.name) and not args.deterministic and not args.no_graph
+    valid = (counters_valid(w.name) and not args.deterministic and not args.no_graph
+             and sim.info["deposit_path"] == COUNTER_DEPOSIT_PATH)
     alg = algorithmic_bytes(dom, w, n_sub)
     achieved = alg / (prof[dom] * 1e-3) / 1e9
     roof = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
@@ -600,7 +607,8 @@ def main() -> int:
         roof["alu_view"] = {"achieved_TFLOPs": tf, "peak_attainable": FP32_ATTAINABLE_TFLOPS,
                             "frac": tf / FP32_ATTAINABLE_TFLOPS,
                             "algorithmic_flop_per_launch": flops,
-                            "mean_neighbours": nbr_mean}
+                            "mean_neighbours": nbr_mean,
+                            "valu_issue_frac": COUNTER_UPDATE_VALU_FRAC if valid else None}
     fb = floor_bytes(w)
     step_hbm = {"floor_bytes": fb, "floor_GBs": fb / (ms_step * 1e-3) / 1e9,
                 "floor_frac": fb / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
