@@ -179,10 +179,11 @@ def _timed(fn) -> float:
     return e0.elapsed_time(e1)
 
 
-def ensemble_leg(steps: int = 500, plain_steps: int = 50) -> dict:
+def ensemble_leg(steps: int = 500) -> dict:
     """256 independent 2D instances of uneven size stepped together (one launch
-    per stage, HIP-graph replay, autotuned bin side and work-group size) vs the
-    same instances stepped one after another as single-instance handles."""
+    per stage, HIP-graph replay, bin side, work-group size and deposit mode
+    tuned on states along the run) vs the same instances, for the same steps,
+    stepped one after another as single-instance handles."""
     import dataclasses
     import torch
     import workloads as W
@@ -191,7 +192,7 @@ def ensemble_leg(steps: int = 500, plain_steps: int = 50) -> dict:
     w = W.workload(W.ENSEMBLE_256)
     inp = W.make_inputs(w)
     x0, s0, c0 = (torch.from_numpy(inp[k]).cuda() for k in ("x0", "species0", "c0"))
-    spec, rep = tune(ModelSpec.from_workload(w), x0, s0, c0)
+    spec, rep = tune(ModelSpec.from_workload(w), x0, s0, c0, horizon=steps)
     sim = Sim(spec, x0, s0, c0)
     sim.use_graph(True)
     sim.step(4)
@@ -205,14 +206,16 @@ def ensemble_leg(steps: int = 500, plain_steps: int = 50) -> dict:
     tot_ms, tot_ps, off = 0.0, 0, 0
     for k, ins in enumerate(w.instances):
         n = ins.n_agents
-        one = dataclasses.replace(spec, instances=[dataclasses.replace(spec.instances[k],
-                                                                       stream=k)])
+        # a single instance with the tuned bin side and work-groups, and the
+        # deposit the library picks for one instance
+        one = dataclasses.replace(spec, deposit_mode=0,
+                                  instances=[dataclasses.replace(spec.instances[k], stream=k)])
         s1 = Sim(one, x0[off:off + n], s0[off:off + n], c0[k * G:(k + 1) * G])
         s1.use_graph(True)
         s1.step(2)
         s1.set_state(x0[off:off + n], c0[k * G:(k + 1) * G], 0)
-        tot_ms += _timed(lambda: s1.step(plain_steps))
-        tot_ps += n * plain_steps
+        tot_ms += _timed(lambda: s1.step(steps))
+        tot_ps += n * steps
         s1.close()
         off += n
     plain = tot_ps / (tot_ms / 1e3)
@@ -222,7 +225,7 @@ def ensemble_leg(steps: int = 500, plain_steps: int = 50) -> dict:
             "batched_ms_per_step": ms / steps,
             "floor_bytes_per_step": fb,
             "floor_frac": fb / (ms / steps * 1e-3) / 1e9 / HBM_PEAK_GBS,
-            "plain_particle_steps_per_s": plain, "plain_steps_per_instance": plain_steps,
+            "plain_particle_steps_per_s": plain, "plain_steps_per_instance": steps,
             "speedup_vs_plain": batched / plain,
             "tuned": {"bin_size": spec.bin_size, "block": spec.block,
                       "deposit_mode": spec.deposit_mode}}
