@@ -164,7 +164,30 @@ def cpu_baseline(w, inp, budget_s: float = 10.0, max_steps: int = 40,
             "sample": f"first {steps} steps of the same workload, FP64 cell-list oracle, "
                       f"{el:.1f} s on {n_all} threads",
             "one_thread": {"value": w.n_total * steps1 / el1, "unit": "particle-steps/s",
-                           "cores": 1, "sample": f"first {steps1} steps, {el1:.1f} s"}}
+                           "cores": 1, "sample": f"first {steps1} steps, {el1:.1f} s"},
+            "brute_force": brute_force_baseline()}
+
+
+def brute_force_baseline() -> dict:
+    """The oracle's all-pairs mode (every pair tested, no cell list) on all
+    host threads: the 1k-agent 2D run in full (100 steps) and one step of the
+    100k-agent 2D walls run."""
+    import oracle
+    import workloads as W
+    out = {}
+    for name, n_steps in ((W.PERIODIC_1K, None), (W.WALLS_100K, 1)):
+        w = W.workload(name)
+        inp = W.make_inputs(w)
+        k = n_steps or w.steps
+        p = oracle.params(w, 0, mode=0)
+        X, sp, c, st = inp["x0"], inp["species0"], inp["c0"], 0
+        t0 = time.perf_counter()
+        for _ in range(k):
+            X, c, st = oracle.step(p, X, sp, c, st)
+        el = time.perf_counter() - t0
+        out[name] = {"value": w.n_total * k / el, "unit": "particle-steps/s", "steps": k,
+                     "seconds": el, "cores": oracle.num_threads()}
+    return out
 
 
 def _timed(fn) -> float:
