@@ -68,7 +68,8 @@ def test_validation_of_variant_parameters():
     ok = [dict(species=[SpeciesSpec(0.01, 1.0, react_to=1, react_rate=5.0), two[1]]),
           dict(species=[SpeciesSpec(0.01, 1.0, react_to=0, react_rate=0.0)]),  # no rate: no switch
           dict(deposit_kernel=1, kde_radius=4.0), dict(potential=1, pot_range=2.0),
-          dict(potential=2), dict(tamed=True), dict(deposit_mode=2), dict(deposit_mode=4)]
+          dict(potential=2), dict(tamed=True), dict(deposit_mode=2), dict(deposit_mode=4),
+          dict(deposit_mode=4, slab_split=1)]
     for over in ok:
         assert workspace_bytes(_spec(**over)) > 0, over
     bad = [dict(species=[SpeciesSpec(0.01, 1.0, react_to=2, react_rate=5.0), two[1]]),
@@ -78,7 +79,8 @@ def test_validation_of_variant_parameters():
            dict(deposit_kernel=2), dict(deposit_kernel=1, kde_radius=60.0),
            dict(deposit_kernel=1, deposit_mode=3), dict(deposit_kernel=1, potential=2),
            dict(potential=3), dict(potential=1, pot_range=0.5), dict(potential=1, pot_range=60.0),
-           dict(deposit_kernel=1, deposit_mode=4), dict(deposit_mode=5)]
+           dict(deposit_kernel=1, deposit_mode=4), dict(deposit_mode=5),
+           dict(deposit_mode=4, slab_split=-1)]
     for over in bad:
         with pytest.raises(PcError):
             workspace_bytes(_spec(**over))
