@@ -60,7 +60,7 @@ COUNTER_UPDATE_BYTES = 82301924.0
 # SQ_INSTS_VALU of the update over its chip issue capacity in the same
 # window (1024 SIMDs x GRBM_GUI_ACTIVE / 8 XCDs / 4 cycles per wave64 op)
 COUNTER_UPDATE_VALU_FRAC = 0.594
-COUNTER_SOURCES_SHA = "47df6974f5a0674d"
+COUNTER_SOURCES_SHA = "13c0c1af9c151b81"
 COUNTER_WORKLOAD = "3d_periodic_1M_blobs"
 COUNTER_DEPOSIT_PATH = 5
 

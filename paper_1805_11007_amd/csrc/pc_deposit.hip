@@ -282,8 +282,8 @@ k_chem_slabs(StepParams p, PdeParams q, const InstInfo *__restrict__ inst,
     __shared__ uint32_t run_pre[kSlabRuns + 1];
     __shared__ uint32_t wtot[kSlabRuns / 64];
     __shared__ SpTab tab;
-    // the step's last kernel advances the step counter (the update, which
-    // reads it, has finished)
+    // with the PDE fused, this kernel advances the step counter: the update,
+    // which reads it, has finished, and nothing after it in the step reads it
     if (fuse_pde && stepc && blockIdx.x == 0 && threadIdx.x == 0) *stepc += 1u;
     const int n = p.grid_n;
     const int nb = p.nb;
