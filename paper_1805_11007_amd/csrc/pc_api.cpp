@@ -296,6 +296,10 @@ static void fill_params(pc_sim *s) {
     p.nb = d.nb;
     p.stencil = d.stencil;
     p.bin_order = 0;
+    // Row order changes only the float summation order of a lane's forces;
+    // deterministic mode keeps the fixed order, so that an agent's bits do
+    // not depend on which path its wave takes.
+    p.sort_rows = c.deterministic ? 0 : 1;
     p.grid_n = c.grid_n;
     p.n_total = (int32_t)d.n_total;
     p.nodes_per_inst = (int32_t)d.nodes_per_inst;

@@ -285,6 +285,21 @@ struct DebugVisitor {
     }
 };
 
+// Nine keys in descending order (a 28-comparator network, Batcher's
+// odd-even merge sort of 16 inputs restricted to the first 9).
+__device__ __forceinline__ void sort9_desc(uint32_t k[9]) {
+    constexpr int kNet[28][2] = {{0, 1}, {2, 3}, {4, 5}, {6, 7}, {0, 2}, {1, 3}, {4, 6},
+                                 {5, 7}, {1, 2}, {5, 6}, {0, 4}, {1, 5}, {2, 6}, {3, 7},
+                                 {2, 4}, {3, 5}, {1, 2}, {3, 4}, {5, 6}, {0, 8}, {4, 8},
+                                 {2, 4}, {3, 5}, {6, 8}, {1, 2}, {3, 4}, {5, 6}, {7, 8}};
+#pragma unroll
+    for (int c = 0; c < 28; ++c) {
+        const uint32_t a = k[kNet[c][0]], b = k[kNet[c][1]];
+        k[kNet[c][0]] = max(a, b);
+        k[kNet[c][1]] = min(a, b);
+    }
+}
+
 // Pair loop over the neighbour bins of an agent at position pi.
 // dx = x_j - x_i, plus -L / +L for bins reached through the periodic seam:
 // for every pair closer than the cutoff this is exactly the minimum image,
@@ -294,11 +309,14 @@ struct DebugVisitor {
 // widest run of x bins a wave may span on the wave-uniform pair path
 constexpr int kSpan = 5;
 
+// rowa: this lane's slot of an LDS table of 9 words per lane (stride
+// blockDim.x) for the longest-row-first walk; nullptr walks rows in order.
 template <int DIM, int NS, int STENCIL, class V>
 __device__ __forceinline__ void pair_loop(const StepParams &p, const SpTab &tab,
                                           const float4 *__restrict__ Ps,
                                           const uint32_t *__restrict__ start, uint32_t bin_base,
-                                          float4 pi, int si, V &v) {
+                                          float4 pi, int si, V &v,
+                                          uint32_t *__restrict__ rowa = nullptr) {
     const int nb = p.nb;
     const float pc[3] = {pi.x, pi.y, pi.z};
     int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
@@ -427,6 +445,72 @@ __device__ __forceinline__ void pair_loop(const StepParams &p, const SpTab &tab,
             }
         }
         return;
+    }
+    // Lanes of one wave walk their own rows in step: each row costs the wave
+    // its longest lane.  In 3D, outside the periodic seams, a lane may walk
+    // its 9 rows longest first instead, which lines up long rows with long
+    // rows across the wave (modelled on the initial 1M-agent blob state: 84
+    // instead of 110 candidate slots per wave).  Each row is one x range
+    // there.  The order changes only the float summation order of the
+    // lane's sum, so it is used only where the caller allows that.
+    if (DIM == 3 && STENCIL == 3 && rowa != nullptr && p.sort_rows) {
+        bool inner = true;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) inner = inner && lo[a] >= 0 && hi[a] <= nb - 1;
+        if (!p.periodic || __all(inner)) {
+            // key: length << 5 | row, 16 bits (rows of up to 2047 agents; the
+            // row index makes keys distinct); the row's first agent goes to
+            // the LDS table.  Every row writes its slot, an empty one 0: the
+            // walk reads the slot of empty rows too, and LDS holds whatever
+            // the CU's previous work-group left there (a stale first agent
+            // near 2^32 would wrap the walk's bound a0 + 8 <= a0 + len).
+            const uint32_t bd = blockDim.x;
+            uint32_t key[9];
+            bool big = false;
+#pragma unroll
+            for (int r = 0; r < 9; ++r) {
+                const int oz = lo[2] + r / 3, oy = lo[1] + r % 3;
+                uint32_t a0 = 0u, len = 0u;
+                float d2 = r % 3 == 0 ? glo2[1] : (r % 3 == 2 ? ghi2[1] : 0.0f);
+                d2 += r / 3 == 0 ? glo2[2] : (r / 3 == 2 ? ghi2[2] : 0.0f);
+                // (a row beyond a wall holds nothing)
+                if (oy >= 0 && oy < nb && oz >= 0 && oz < nb && d2 < cmax2) {
+                    int xlo = lo[0], xhi = hi[0];
+                    if (d2 + glo2[0] >= cmax2) xlo += 1;
+                    if (d2 + ghi2[0] >= cmax2) xhi -= 1;
+                    const int m0 = max(xlo, 0), m1 = min(xhi, nb - 1);
+                    const uint32_t row = bin_base + (uint32_t)((oz * nb + oy) * nb);
+                    a0 = start[row + m0];
+                    len = start[row + m1 + 1] - a0;
+                    big = big || len > 2047u;
+                }
+                rowa[r * bd] = a0;
+                key[r] = (len << 5) | (uint32_t)r;
+            }
+            if (!__any(big)) {
+                sort9_desc(key);
+                // two keys per register while the rows are walked
+                uint32_t pk[5];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) pk[q] = key[2 * q] | (key[2 * q + 1] << 16);
+                pk[4] = key[8];
+                uint32_t kk = pk[0] & 0xffffu;
+                uint32_t a0 = rowa[(kk & 15u) * bd];
+#pragma unroll 1
+                for (int k = 0; k < 9; ++k) {
+                    const uint32_t len = kk >> 5;
+                    if (!__any(len != 0u)) break;   // the rest are empty for every lane
+                    const uint32_t kn =
+                        k < 8 ? (pk[(k + 1) >> 1] >> (((k + 1) & 1) * 16)) & 0xffffu : 0u;
+                    const uint32_t an = rowa[(kn & 15u) * bd];
+                    pair_range<DIM, NS, false>(p, tab, Ps, a0, a0 + len, pi, si, 0.f, 0.f, 0.f,
+                                               c2row, drow, v);
+                    kk = kn;
+                    a0 = an;
+                }
+                return;
+            }
+        }
     }
     const int zlo = DIM == 3 ? lo[2] : 0, zhi = DIM == 3 ? hi[2] : 0;
     for (int oz = zlo; oz <= zhi; ++oz) {

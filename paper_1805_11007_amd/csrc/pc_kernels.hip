@@ -354,16 +354,20 @@ k_update(StepParams p, const InstInfo *__restrict__ inst, const float4 *__restri
     const uint32_t node_base = kin * (uint32_t)p.nodes_per_inst;
     const InstInfo ii = inst[kin];
 
+    // 3D: the row table of the longest-row-first pair walk (9 words per
+    // thread, launched with that much dynamic LDS)
+    extern __shared__ uint32_t upd_rows[];
+    uint32_t *rowa = (DIM == 3 && STENCIL == 3) ? upd_rows + threadIdx.x : nullptr;
     float F[3] = {0.f, 0.f, 0.f};
     if (POT == 0) {
         ForceVisitor fv{p.k, p.fcap, {0.f, 0.f, 0.f}};
-        pair_loop<DIM, NS, STENCIL>(p, tab, Ps, start, bin_base, pi, si, fv);
+        pair_loop<DIM, NS, STENCIL>(p, tab, Ps, start, bin_base, pi, si, fv, rowa);
         F[0] = fv.F[0];
         F[1] = fv.F[1];
         F[2] = fv.F[2];
     } else if (POT == 1) {
         ExpVisitor ev{p.k, {0.f, 0.f, 0.f}};
-        pair_loop<DIM, NS, STENCIL>(p, tab, Ps, start, bin_base, pi, si, ev);
+        pair_loop<DIM, NS, STENCIL>(p, tab, Ps, start, bin_base, pi, si, ev, rowa);
         F[0] = ev.F[0];
         F[1] = ev.F[1];
         F[2] = ev.F[2];
@@ -843,11 +847,17 @@ void launch_stable(const StepParams &p, const Buffers &b, int src, int dst, int 
                            b.P[dst], b.I[dst]);
 }
 
+// dynamic LDS of k_update: the 3D pair walk's row table, 9 words per thread
+template <int DIM, int ST>
+static size_t upd_lds(int block) {
+    return (DIM == 3 && ST == 3) ? (size_t)36 * (size_t)block : 0;
+}
+
 template <int DIM, int NS, int ST>
 static void upd(const StepParams &p, const Buffers &b, int src, int dst, int cbuf, int block,
                 hipStream_t s) {
     hipLaunchKernelGGL((k_update<DIM, NS, ST, 0>), dim3(grid_for(p.n_total, block)), dim3(block),
-                       0, s, p, b.inst, b.P[src], b.I[src], b.start, b.c[cbuf], b.P[dst],
+                       (upd_lds<DIM, ST>(block)), s, p, b.inst, b.P[src], b.I[src], b.start, b.c[cbuf], b.P[dst],
                        b.I[dst], b.bin, b.count, b.tile_cnt, b.step, b.flags);
 }
 
@@ -857,7 +867,7 @@ template <int DIM, int NS, int ST>
 static void upd_exp(const StepParams &p, const Buffers &b, int src, int dst, int cbuf, int block,
                     hipStream_t s) {
     hipLaunchKernelGGL((k_update<DIM, NS, ST, 1>), dim3(grid_for(p.n_total, block)), dim3(block),
-                       0, s, p, b.inst, b.P[src], b.I[src], b.start, b.c[cbuf], b.P[dst],
+                       (upd_lds<DIM, ST>(block)), s, p, b.inst, b.P[src], b.I[src], b.start, b.c[cbuf], b.P[dst],
                        b.I[dst], b.bin, b.count, b.tile_cnt, b.step, b.flags);
 }
 
@@ -876,7 +886,7 @@ template <int DIM, int ST, int POT>
 static void upd_pot(const StepParams &p, const Buffers &b, int src, int dst, int cbuf, int block,
                     hipStream_t s) {
     hipLaunchKernelGGL((k_update<DIM, 0, ST, POT>), dim3(grid_for(p.n_total, block)),
-                       dim3(block), 0, s, p, b.inst, b.P[src], b.I[src], b.start, b.c[cbuf],
+                       dim3(block), (upd_lds<DIM, ST>(block)), s, p, b.inst, b.P[src], b.I[src], b.start, b.c[cbuf],
                        b.P[dst], b.I[dst], b.bin, b.count, b.tile_cnt, b.step,
                        b.flags);
 }
