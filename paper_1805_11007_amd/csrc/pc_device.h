@@ -169,9 +169,9 @@ __device__ __forceinline__ void pair_one(const StepParams &p, const SpTab &tab, 
 }
 
 // Candidates j in [a, e) of one contiguous bin range, each as pair_one.
-// Loads are issued eight (then four) candidates ahead of the arithmetic so
-// that one wave keeps several memory requests in flight.
-template <int DIM, int NS, bool SHIFT, class V>
+// Loads are issued DEEP (8: eight, then four; 4: four) candidates ahead of
+// the arithmetic so that one wave keeps several memory requests in flight.
+template <int DIM, int NS, bool SHIFT, class V, int DEEP = 8>
 __device__ __forceinline__ void pair_range(const StepParams &p, const SpTab &tab,
                                            const float4 *__restrict__ Ps, uint32_t a,
                                            uint32_t e, const float4 &pi, int si, float sx,
@@ -180,7 +180,7 @@ __device__ __forceinline__ void pair_range(const StepParams &p, const SpTab &tab
     uint32_t j = a;
     // one 64-bit address per group of four; the rest are immediate offsets
     const float4 *__restrict__ qp = Ps + a;
-    for (; j + 8 <= e; j += 8, qp += 8) {
+    for (; DEEP >= 8 && j + 8 <= e; j += 8, qp += 8) {
         const float4 q0 = qp[0], q1 = qp[1], q2 = qp[2], q3 = qp[3];
         const float4 q4 = qp[4], q5 = qp[5], q6 = qp[6], q7 = qp[7];
         pair_one<DIM, NS, SHIFT>(p, tab, j, q0, pi, si, sx, sy, sz, c2row, drow, v);
@@ -503,8 +503,8 @@ __device__ __forceinline__ void pair_loop(const StepParams &p, const SpTab &tab,
                     const uint32_t kn =
                         k < 8 ? (pk[(k + 1) >> 1] >> (((k + 1) & 1) * 16)) & 0xffffu : 0u;
                     const uint32_t an = rowa[(kn & 15u) * bd];
-                    pair_range<DIM, NS, false>(p, tab, Ps, a0, a0 + len, pi, si, 0.f, 0.f, 0.f,
-                                               c2row, drow, v);
+                    pair_range<DIM, NS, false, V, 4>(p, tab, Ps, a0, a0 + len, pi, si, 0.f,
+                                                     0.f, 0.f, c2row, drow, v);
                     kk = kn;
                     a0 = an;
                 }
