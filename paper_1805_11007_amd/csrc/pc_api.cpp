@@ -66,7 +66,7 @@ static bool reacts(const pc_species_t &s) {
 }
 
 struct Layout {
-    size_t P[3], I[3], bin, count, start, tile_sum, tile_cnt, c[2], S_src, S_upt, slab_cnt,
+    size_t P[3], I[3], count, start, tile_sum, tile_cnt, c[2], S_src, S_upt, slab_cnt,
         slab_tab, inst, species_id, step, flags, seg_x, seg_c, lamX[2], lamY, lamC[2], aSrc, aUpt, lamG, csub, dth;
     size_t total;
 };
@@ -216,7 +216,6 @@ Layout layout(const Derived &d, int seg_steps) {
     const size_t N = (size_t)d.n_total;
     for (int k = 0; k < 3; ++k) L.P[k] = take(cur, 16 * N);
     for (int k = 0; k < 3; ++k) L.I[k] = take(cur, 4 * N);
-    L.bin = take(cur, 4 * N);
     L.count = take(cur, 4 * ((size_t)d.bins_total + 1));
     L.start = take(cur, 4 * ((size_t)d.bins_total + 1));
     L.tile_sum = take(cur, 4 * (((size_t)d.bins_total + 1 + kScanTile - 1) / kScanTile));
@@ -403,7 +402,6 @@ static void carve(pc_sim *s, char *ws) {
         b.P[k] = (float4 *)(ws + L.P[k]);
         b.I[k] = (uint32_t *)(ws + L.I[k]);
     }
-    b.bin = (uint32_t *)(ws + L.bin);
     b.count = (uint32_t *)(ws + L.count);
     b.start = (uint32_t *)(ws + L.start);
     b.tile_sum = (uint32_t *)(ws + L.tile_sum);

@@ -96,7 +96,6 @@ enum : uint32_t {
 struct Buffers {
     float4 *P[3];          // positions (x, y, z, bits(inst << 8 | species))
     uint32_t *I[3];        // local ids, same order as P[k]
-    uint32_t *bin;         // bin of each agent (counted, then scattered)
     uint32_t *count;       // bins_total + 1
     uint32_t *start;       // bins_total + 1
     uint32_t *tile_sum;    // ceil((bins_total + 1) / kScanTile): exclusive tile prefixes

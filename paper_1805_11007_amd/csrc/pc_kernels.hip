@@ -100,15 +100,13 @@ __device__ __forceinline__ void count_bin(uint32_t *__restrict__ count,
 
 template <int DIM>
 __global__ void k_bin(StepParams p, const InstInfo *__restrict__ inst,
-                      const float4 *__restrict__ P, uint32_t *__restrict__ bin,
-                      uint32_t *__restrict__ count,
+                      const float4 *__restrict__ P, uint32_t *__restrict__ count,
                       uint32_t *__restrict__ tile_cnt) {
     const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
     const int i = blk * blockDim.x + threadIdx.x;
     if (i >= p.n_total) return;
     const float4 x = P[i];
     const uint32_t b = inst[inst_of(x.w)].bin_base + agent_bin<DIM>(p, x);
-    bin[i] = b;
     count_bin(count, tile_cnt, b, p.tile_totals, p.tile_reps);
 }
 
@@ -286,20 +284,24 @@ __global__ void __launch_bounds__(256) k_scan_apply(const uint32_t *__restrict__
 // (deterministic mode then orders each bin by id), and the counts are back
 // at zero for the next histogram.  A run of lanes with one bin takes its
 // slots with one atomic, its first lane's, and shares the old count.
-__global__ void k_scatter(int n, const float4 *__restrict__ P, const uint32_t *__restrict__ I,
-                          const uint32_t *__restrict__ bin, uint32_t *__restrict__ count,
+template <int DIM>
+__global__ void k_scatter(StepParams p, const float4 *__restrict__ P,
+                          const uint32_t *__restrict__ I, uint32_t *__restrict__ count,
                           const uint32_t *__restrict__ start, float4 *__restrict__ Ps,
                           uint32_t *__restrict__ Is) {
     const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
     const int i = blk * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const uint32_t b = bin[i];
+    if (i >= p.n_total) return;
+    // the bin counted by the kernel that wrote x, recomputed from x by the
+    // same float32 arithmetic (instance tables are equal-sized)
+    const float4 x = P[i];
+    const uint32_t b = inst_of(x.w) * (uint32_t)p.bins_per_inst + agent_bin<DIM>(p, x);
     const WaveRun run = wave_run(b);
     uint32_t top = 0;
     if (run.pos == 0) top = atomicSub(count + b, (uint32_t)run.len);
     top = __shfl(top, run.head, 64);
     const uint32_t d = start[b] + top - 1u - (uint32_t)run.pos;
-    Ps[d] = P[i];
+    Ps[d] = x;
     Is[d] = I[i];
 }
 
@@ -332,7 +334,7 @@ __global__ void __launch_bounds__(1024)
 k_update(StepParams p, const InstInfo *__restrict__ inst, const float4 *__restrict__ Ps,
          const uint32_t *__restrict__ Is, const uint32_t *__restrict__ start,
          const float *__restrict__ c, float4 *__restrict__ Pout, uint32_t *__restrict__ Iout,
-         uint32_t *__restrict__ bin, uint32_t *__restrict__ count,
+         uint32_t *__restrict__ count,
          uint32_t *__restrict__ tile_cnt,
          const uint32_t *__restrict__ stepc, uint32_t *__restrict__ flags) {
     __shared__ SpTab tab;
@@ -421,7 +423,6 @@ k_update(StepParams p, const InstInfo *__restrict__ inst, const float4 *__restri
     Pout[i] = xn;
     Iout[i] = id;
     const uint32_t b = bin_base + agent_bin<DIM>(p, xn);
-    bin[i] = b;
     count_bin(count, tile_cnt, b, p.tile_totals, p.tile_reps);
     if (flag) atomicOr(flags, flag);
 }
@@ -760,8 +761,7 @@ template <int DIM, int NS, int STENCIL>
 __global__ void __launch_bounds__(1024)
 k_overlap(StepParams p, const InstInfo *__restrict__ inst, const float4 *__restrict__ Ps,
           const uint32_t *__restrict__ Is, const uint32_t *__restrict__ start,
-          float4 *__restrict__ Pout, uint32_t *__restrict__ Iout, uint32_t *__restrict__ bin,
-          uint32_t *__restrict__ count,
+          float4 *__restrict__ Pout, uint32_t *__restrict__ Iout, uint32_t *__restrict__ count,
           uint32_t *__restrict__ tile_cnt, uint32_t *__restrict__ flags) {
     __shared__ SpTab tab;
     load_tab(p, tab);
@@ -784,7 +784,6 @@ k_overlap(StepParams p, const InstInfo *__restrict__ inst, const float4 *__restr
     Pout[i] = xn;
     Iout[i] = Is[i];
     const uint32_t b = ii.bin_base + agent_bin<DIM>(p, xn);
-    bin[i] = b;
     count_bin(count, tile_cnt, b, p.tile_totals, p.tile_reps);
     if (flag) atomicOr(flags, flag);
 }
@@ -812,10 +811,10 @@ void launch_init_agents(const StepParams &p, const Buffers &b, const float *x, c
 void launch_bin(const StepParams &p, const Buffers &b, int src, int block, hipStream_t s) {
     const dim3 g(grid_for(p.n_total, block)), t(block);
     if (p.dim == 2)
-        hipLaunchKernelGGL(k_bin<2>, g, t, 0, s, p, b.inst, b.P[src], b.bin, b.count,
+        hipLaunchKernelGGL(k_bin<2>, g, t, 0, s, p, b.inst, b.P[src], b.count,
                            b.tile_cnt);
     else
-        hipLaunchKernelGGL(k_bin<3>, g, t, 0, s, p, b.inst, b.P[src], b.bin, b.count,
+        hipLaunchKernelGGL(k_bin<3>, g, t, 0, s, p, b.inst, b.P[src], b.count,
                            b.tile_cnt);
 }
 
@@ -832,8 +831,13 @@ void launch_scan(const StepParams &p, const Buffers &b, int64_t n_bins_total, hi
 
 void launch_scatter(const StepParams &p, const Buffers &b, int src, int dst, int block,
                     hipStream_t s) {
-    hipLaunchKernelGGL(k_scatter, dim3(grid_for(p.n_total, block)), dim3(block), 0, s, p.n_total,
-                       b.P[src], b.I[src], b.bin, b.count, b.start, b.P[dst], b.I[dst]);
+    const dim3 g(grid_for(p.n_total, block)), t(block);
+    if (p.dim == 2)
+        hipLaunchKernelGGL(k_scatter<2>, g, t, 0, s, p, b.P[src], b.I[src], b.count, b.start,
+                           b.P[dst], b.I[dst]);
+    else
+        hipLaunchKernelGGL(k_scatter<3>, g, t, 0, s, p, b.P[src], b.I[src], b.count, b.start,
+                           b.P[dst], b.I[dst]);
 }
 
 void launch_stable(const StepParams &p, const Buffers &b, int src, int dst, int block,
@@ -858,7 +862,7 @@ static void upd(const StepParams &p, const Buffers &b, int src, int dst, int cbu
                 hipStream_t s) {
     hipLaunchKernelGGL((k_update<DIM, NS, ST, 0>), dim3(grid_for(p.n_total, block)), dim3(block),
                        (upd_lds<DIM, ST>(block)), s, p, b.inst, b.P[src], b.I[src], b.start, b.c[cbuf], b.P[dst],
-                       b.I[dst], b.bin, b.count, b.tile_cnt, b.step, b.flags);
+                       b.I[dst], b.count, b.tile_cnt, b.step, b.flags);
 }
 
 // the exponential potential with the species specialisations of the
@@ -868,7 +872,7 @@ static void upd_exp(const StepParams &p, const Buffers &b, int src, int dst, int
                     hipStream_t s) {
     hipLaunchKernelGGL((k_update<DIM, NS, ST, 1>), dim3(grid_for(p.n_total, block)), dim3(block),
                        (upd_lds<DIM, ST>(block)), s, p, b.inst, b.P[src], b.I[src], b.start, b.c[cbuf], b.P[dst],
-                       b.I[dst], b.bin, b.count, b.tile_cnt, b.step, b.flags);
+                       b.I[dst], b.count, b.tile_cnt, b.step, b.flags);
 }
 
 // the hard-sphere overlap pass with the species specialisations of the pair
@@ -877,7 +881,7 @@ template <int DIM, int NS, int ST>
 static void ovl(const StepParams &p, const Buffers &b, int src, int dst, int block,
                 hipStream_t s) {
     hipLaunchKernelGGL((k_overlap<DIM, NS, ST>), dim3(grid_for(p.n_total, block)), dim3(block),
-                       0, s, p, b.inst, b.P[src], b.I[src], b.start, b.P[dst], b.I[dst], b.bin,
+                       0, s, p, b.inst, b.P[src], b.I[src], b.start, b.P[dst], b.I[dst],
                        b.count, b.tile_cnt, b.flags);
 }
 
@@ -887,7 +891,7 @@ static void upd_pot(const StepParams &p, const Buffers &b, int src, int dst, int
                     hipStream_t s) {
     hipLaunchKernelGGL((k_update<DIM, 0, ST, POT>), dim3(grid_for(p.n_total, block)),
                        dim3(block), (upd_lds<DIM, ST>(block)), s, p, b.inst, b.P[src], b.I[src], b.start, b.c[cbuf],
-                       b.P[dst], b.I[dst], b.bin, b.count, b.tile_cnt, b.step,
+                       b.P[dst], b.I[dst], b.count, b.tile_cnt, b.step,
                        b.flags);
 }
 
