@@ -104,8 +104,8 @@ def algorithmic_bytes(stage: str, w, n_sub: int) -> float:
                deposited field once (4F per node)
       pde:     per substep read and write c (8 per node), read each deposited
                field once (4F per node)
-      bin:     read position, write bin (4d + 4 per agent)
-      scatter: read position/id/bin, write position/id (8d + 12 per agent)
+      bin:     read position (4d per agent)
+      scatter: read position/id, write position/id (8d + 8 per agent)
       scan:    read count, write start (8 per bin)
     """
     N, d = w.n_total, w.dim
@@ -118,9 +118,9 @@ def algorithmic_bytes(stage: str, w, n_sub: int) -> float:
     if stage == "pde":
         return G * (8 * n_sub + 4 * F)
     if stage == "bin":
-        return N * (4 * d + 4)
+        return N * 4 * d
     if stage == "scatter":
-        return N * (8 * d + 12)
+        return N * (8 * d + 8)
     return 0.0
 
 

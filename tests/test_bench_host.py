@@ -36,7 +36,7 @@ def test_stage_bytes_of_the_3d_run():
     assert bench.algorithmic_bytes("update", w, 1) == N * 28 + 4 * G
     assert bench.algorithmic_bytes("deposit", w, 1) == N * 13 + 4 * G
     assert bench.algorithmic_bytes("pde", w, 1) == G * 12
-    assert bench.algorithmic_bytes("scatter", w, 1) == N * 36
+    assert bench.algorithmic_bytes("scatter", w, 1) == N * 32
 
 
 def test_counter_guard_follows_the_sources_and_the_workload():
