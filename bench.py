@@ -55,12 +55,12 @@ FLOP_PER_PAIR, FLOP_PER_AGENT = 18.0, 140.0
 # work-groups, slab deposit).  Valid only for the kernel sources they were
 # taken with (a hash of every file under csrc/), for that workload and that
 # deposit path; reported as null otherwise.
-COUNTER_STEP_BYTES = 339288283.0
-COUNTER_UPDATE_BYTES = 82301924.0
+COUNTER_STEP_BYTES = 331481747.7
+COUNTER_UPDATE_BYTES = 78313340.3
 # SQ_INSTS_VALU of the update over its chip issue capacity in the same
 # window (1024 SIMDs x GRBM_GUI_ACTIVE / 8 XCDs / 4 cycles per wave64 op)
-COUNTER_UPDATE_VALU_FRAC = 0.594
-COUNTER_SOURCES_SHA = "13c0c1af9c151b81"
+COUNTER_UPDATE_VALU_FRAC = 0.549
+COUNTER_SOURCES_SHA = "8ad007d8b4cc0fec"
 COUNTER_WORKLOAD = "3d_periodic_1M_blobs"
 COUNTER_DEPOSIT_PATH = 5
 
