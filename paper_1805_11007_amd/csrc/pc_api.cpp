@@ -605,6 +605,7 @@ static int common_create(const pc_config *cfg, const pc_species_t *species, int 
         }
         s->slab = slab_ok && (cfg->deposit_mode == 4 || (cfg->deposit_mode == 0 && d.dim == 3));
         s->slab_split = cfg->slab_split > 0 ? (uint32_t)cfg->slab_split : kSlabSplitDefault;
+        if (s->slab) chem_slab_assist_grid(s->sp, s->d.slab);
     }
     carve(s, (char *)workspace_dev);
     s->inst_host.resize(n_inst);

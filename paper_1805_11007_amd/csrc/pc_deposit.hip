@@ -40,7 +40,7 @@ constexpr int kSlabThreads = kSlabRuns;   // one run lookup per thread
 constexpr int kSlabTableWords = 2 * kSlabRuns + 2;
 constexpr int kAssistChunk = 1024;   // agents of a heavy slab per assisting pass
 constexpr int kAssistThreads = 256;
-constexpr int kAssistBlocks = 1024;
+constexpr int kAssistBlocks = 1024;   // grid when the occupancy query fails
 constexpr int kAssistSlabBlock = 4 * kAssistThreads;   // slab counts scanned per pass
 constexpr int kFinishParts = 4;   // work-groups per handed-over slab in k_slab_finish
 
@@ -533,7 +533,50 @@ bool chem_slab_shape(int dim, int n, double f, int n_inst, SlabShape &sh) {
     sh.nbz = dim == 3 ? (n + Bz - 1) / Bz : 1;
     sh.nslabs = (int64_t)sh.nby * sh.nbz * n_inst;
     sh.lds_bytes = 8 * (size_t)n * By * Bz;   // per deposited field
+    sh.assist_blocks = kAssistBlocks;
     return true;
+}
+
+// One round of resident work-groups takes every chunk of the handed-over
+// slabs at once where they number fewer (the 1M-agent 3D run has about
+// 1,400 chunks): on 256 CUs with six resident work-groups each, 1536
+// work-groups instead of 1024 cut the assist by ~2 us per step, while a
+// second round (2048) or more than fit (1792) made it slower.
+template <int DIM, int NS, bool UPT>
+static int assist_occupancy(size_t lds) {
+    int occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &occ, reinterpret_cast<const void *>(&k_slab_assist<DIM, NS, UPT>), kAssistThreads,
+            lds) != hipSuccess)
+        return 0;
+    return occ;
+}
+
+void chem_slab_assist_grid(const StepParams &p, SlabShape &sh) {
+    const bool upt = p.has_uptake != 0;
+    const size_t lds = sh.lds_bytes * (upt ? 2 : 1);
+    const int ns = p.n_species == 1 ? 1 : (p.n_species == 2 ? 2 : 0);
+    int occ = 0;
+#define PC_OCC(D, N) occ = upt ? assist_occupancy<D, N, true>(lds) : assist_occupancy<D, N, false>(lds)
+    if (p.dim == 2) {
+        if (ns == 1) PC_OCC(2, 1);
+        else if (ns == 2) PC_OCC(2, 2);
+        else PC_OCC(2, 0);
+    } else {
+        if (ns == 1) PC_OCC(3, 1);
+        else if (ns == 2) PC_OCC(3, 2);
+        else PC_OCC(3, 0);
+    }
+#undef PC_OCC
+    int dev = 0, cus = 0;
+    if (occ <= 0 || hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus <= 0) {
+        (void)hipGetLastError();
+        sh.assist_blocks = kAssistBlocks;
+        return;
+    }
+    sh.assist_blocks = occ * cus;
 }
 
 size_t chem_slab_table_words() { return kSlabTableWords; }
@@ -547,7 +590,8 @@ static void slabs(const StepParams &p, const PdeParams &q, const Buffers &b, con
                        s, p, q, b.inst, b.P[src], b.start, b.c[cur], b.c[1 - cur], b.S_src,
                        b.S_upt, sh.By, sh.Bz, sh.nby, sh.nbz, fuse, split, b.slab_cnt,
                        b.slab_tab, b.flags, b.step);
-    hipLaunchKernelGGL((k_slab_assist<DIM, NS, UPT>), dim3(kAssistBlocks), dim3(kAssistThreads),
+    hipLaunchKernelGGL((k_slab_assist<DIM, NS, UPT>), dim3((unsigned)sh.assist_blocks),
+                       dim3(kAssistThreads),
                        lds, s, p, b.inst, b.P[src], b.S_src, b.S_upt, sh.By, sh.Bz, sh.nby,
                        sh.nbz, (int)sh.nslabs, b.slab_cnt, b.slab_tab);
     if (fuse)

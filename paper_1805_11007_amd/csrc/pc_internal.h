@@ -167,8 +167,12 @@ struct SlabShape {
     int By, Bz, nby, nbz;
     int64_t nslabs;        // over all instances
     size_t lds_bytes;      // LDS sums per deposited field
+    int assist_blocks;     // grid of k_slab_assist: the work-groups resident at once
 };
 bool chem_slab_shape(int dim, int n, double bins_per_cell, int n_inst, SlabShape &sh);
+// Size the hand-over kernel's grid for the current device: work-groups per
+// CU at its LDS use times the CU count (1024 if the runtime cannot say).
+void chem_slab_assist_grid(const StepParams &p, SlabShape &sh);
 size_t chem_slab_table_words();
 void launch_chem_slabs(const StepParams &p, const PdeParams &q, const Buffers &b,
                        const SlabShape &sh, uint32_t split, int src, int cur, int fuse_pde,
