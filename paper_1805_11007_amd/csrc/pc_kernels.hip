@@ -724,12 +724,16 @@ k_debug_pairs(StepParams p, const InstInfo *__restrict__ inst, const float4 *__r
     const int si = species_of(pi.w);
     const InstInfo ii = inst[inst_of(pi.w)];
     const size_t row = ii.agent_base + Is[i];
+    // the update's walk, with its LDS row table (same launch shape, so the
+    // same waves and the same row order)
+    extern __shared__ uint32_t dbg_rows[];
+    uint32_t *rowa = (DIM == 3 && STENCIL == 3) ? dbg_rows + threadIdx.x : nullptr;
     uint32_t cnt;
     unsigned long long hs;
     float F[3];
     if (POT == 1) {
         DebugVisitor<ExpVisitor> dv{ExpVisitor{p.k, {0.f, 0.f, 0.f}}, (uint32_t)i, Is, 0u, 0ull};
-        pair_loop<DIM, NS, STENCIL>(p, tab, Ps, start, ii.bin_base, pi, si, dv);
+        pair_loop<DIM, NS, STENCIL>(p, tab, Ps, start, ii.bin_base, pi, si, dv, rowa);
         cnt = dv.cnt;
         hs = dv.hs;
         F[0] = dv.fv.F[0], F[1] = dv.fv.F[1], F[2] = dv.fv.F[2];
@@ -738,7 +742,7 @@ k_debug_pairs(StepParams p, const InstInfo *__restrict__ inst, const float4 *__r
         const float k = POT == 0 ? p.k : 0.0f;
         DebugVisitor<ForceVisitor> dv{ForceVisitor{k, p.fcap, {0.f, 0.f, 0.f}}, (uint32_t)i, Is,
                                       0u, 0ull};
-        pair_loop<DIM, NS, STENCIL>(p, tab, Ps, start, ii.bin_base, pi, si, dv);
+        pair_loop<DIM, NS, STENCIL>(p, tab, Ps, start, ii.bin_base, pi, si, dv, rowa);
         cnt = dv.cnt;
         hs = dv.hs;
         const bool force = k != 0.0f;
@@ -900,15 +904,15 @@ static void dbg(const StepParams &p, const Buffers &b, int src, uint32_t *count,
                 unsigned long long *hash, float *F, int block, hipStream_t s) {
     if (p.potential == 0)
         hipLaunchKernelGGL((k_debug_pairs<DIM, NS, ST, 0>), dim3(grid_for(p.n_total, block)),
-                           dim3(block), 0, s, p, b.inst, b.P[src], b.I[src], b.start, count, hash,
+                           dim3(block), (upd_lds<DIM, ST>(block)), s, p, b.inst, b.P[src], b.I[src], b.start, count, hash,
                            F);
     else if (p.potential == 1)
         hipLaunchKernelGGL((k_debug_pairs<DIM, 0, ST, 1>), dim3(grid_for(p.n_total, block)),
-                           dim3(block), 0, s, p, b.inst, b.P[src], b.I[src], b.start, count, hash,
+                           dim3(block), (upd_lds<DIM, ST>(block)), s, p, b.inst, b.P[src], b.I[src], b.start, count, hash,
                            F);
     else
         hipLaunchKernelGGL((k_debug_pairs<DIM, 0, ST, 2>), dim3(grid_for(p.n_total, block)),
-                           dim3(block), 0, s, p, b.inst, b.P[src], b.I[src], b.start, count, hash,
+                           dim3(block), (upd_lds<DIM, ST>(block)), s, p, b.inst, b.P[src], b.I[src], b.start, count, hash,
                            F);
 }
 

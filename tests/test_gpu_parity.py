@@ -52,6 +52,37 @@ def test_neighbour_sets_bit_exact_full_size(name):
     assert np.array_equal(hsh.cpu().numpy().view(np.uint64), ohsh)
 
 
+@pytest.mark.parametrize("det", [False, True])
+def test_pair_walk_after_lds_hash_deposits(det):
+    """3D, after steps with the LDS-hash deposit, whose table is filled with
+    0xFFFFFFFF: outside deterministic mode a lane walks its stencil rows
+    longest first from an LDS table of row starts, which every row must
+    write (a stale slot would wrap the walk).  Neighbour sets bit-exact and
+    forces against the oracle at the device's own positions; the debug
+    kernel walks the rows as the update does.  Forces are compared away
+    from the periodic seam (the agents the sorted walk serves): across it,
+    x_j - x_i of coordinates near 0 and near L rounds to an ulp of L before
+    the shift, which a close pair's factor k (d / r - 1) multiplies (8e-5
+    at r = d / 4, whatever the row order)."""
+    w = W.scaled(W.workload(W.BLOBS_1M), n_agents=250000, grid_n=40)
+    inp = W.make_inputs(w)
+    sim = make_sim(w, inp, deterministic=det, deposit_mode=1)
+    sim.step(3)
+    sim.sync()
+    here = {"x0": sim.positions().cpu().numpy(), "species0": inp["species0"]}
+    cnt, hsh = sim.debug_neighbours()
+    ocnt, ohsh = oracle_neighbours(w, here)
+    assert np.array_equal(cnt.cpu().numpy().astype(np.uint32), ocnt)
+    assert np.array_equal(hsh.cpu().numpy().view(np.uint64), ohsh)
+    assert ocnt.mean() > 1.0   # 1.5 neighbours per agent at a quarter of the agents
+    F = sim.debug_forces().cpu().numpy().astype(np.float64)
+    Fo = oracle_forces(w, here)
+    d = max(s.diameter for s in w.species)
+    inner = np.all((here["x0"] >= 2 * d) & (here["x0"] <= w.L - 2 * d), axis=1)
+    assert inner.mean() > 0.9
+    assert np.abs(F - Fo)[inner].max() <= 1e-5 * w.k * d
+
+
 @pytest.mark.parametrize("name,n,g", SMALL)
 def test_forces(name, n, g):
     w = _w(name, n, g)
