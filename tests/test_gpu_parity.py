@@ -83,6 +83,35 @@ def test_pair_walk_after_lds_hash_deposits(det):
     assert np.abs(F - Fo)[inner].max() <= 1e-5 * w.k * d
 
 
+def test_pair_walk_rows_beyond_2047_agents():
+    """3D pile: 30,000 of 36,000 agents inside 3 x 3 x 3 bins (~1,100 each),
+    so stencil rows hold more agents than the 16-bit keys of the
+    longest-row-first walk carry (2047); waves with such a row take the
+    fixed-order walk.  Neighbour sets bit-exact and forces against the
+    oracle (non-deterministic mode)."""
+    w = W.scaled(W.workload(W.BLOBS_1M), n_agents=36000, grid_n=32)
+    inp = W.make_inputs(w)
+    x0 = inp["x0"].copy()
+    rng = np.random.default_rng(7)
+    lo, side = 125 / 249 + 1e-6, 3 / 249 - 2e-6   # bins 125..127 of 249 on each axis
+    x0[:30000] = (lo + rng.uniform(0, side, (30000, 3))).astype(np.float32)
+    inp = dict(inp, x0=x0)
+    sim = make_sim(w, inp)
+    cnt, hsh = sim.debug_neighbours()
+    ocnt, ohsh = oracle_neighbours(w, inp)
+    assert ocnt.max() > 2047
+    assert np.array_equal(cnt.cpu().numpy().astype(np.uint32), ocnt)
+    assert np.array_equal(hsh.cpu().numpy().view(np.uint64), ohsh)
+    F = sim.debug_forces().cpu().numpy().astype(np.float64)
+    Fo = oracle_forces(w, inp)
+    # a pile agent sums up to ~4,700 float32 pair terms of size up to k d:
+    # 1e-5 k d plus 2^-20 k d per neighbour (a float32 emulation of the same
+    # sums on the CPU stays within a third of it)
+    kd = w.k * max(s.diameter for s in w.species)
+    bar = 1e-5 * kd + 2.0 ** -20 * kd * ocnt.astype(np.float64)
+    assert np.all(np.abs(F - Fo).max(axis=1) <= bar)
+
+
 @pytest.mark.parametrize("name,n,g", SMALL)
 def test_forces(name, n, g):
     w = _w(name, n, g)
