@@ -51,16 +51,16 @@ FLOP_PER_PAIR, FLOP_PER_AGENT = 18.0, 140.0
 # steps after 5 warm-up steps; each counter in its own run, FETCH_SIZE scaled
 # by 2.0 and WRITE_SIZE by 1.0 from a plain device copy).  Bytes per step
 # (summed over the step's kernels) and per launch of the update kernel,
-# with the tuned choice of that run (bin side = cutoff, 64-thread agent
+# with the tuned choice of that run (bin side = cutoff, 128-thread agent
 # work-groups, slab deposit).  Valid only for the kernel sources they were
 # taken with (a hash of every file under csrc/), for that workload and that
 # deposit path; reported as null otherwise.
-COUNTER_STEP_BYTES = 331481747.7
-COUNTER_UPDATE_BYTES = 78313340.3
+COUNTER_STEP_BYTES = 331650798.0
+COUNTER_UPDATE_BYTES = 78302667.1
 # SQ_INSTS_VALU of the update over its chip issue capacity in the same
 # window (1024 SIMDs x GRBM_GUI_ACTIVE / 8 XCDs / 4 cycles per wave64 op)
-COUNTER_UPDATE_VALU_FRAC = 0.549
-COUNTER_SOURCES_SHA = "8ad007d8b4cc0fec"
+COUNTER_UPDATE_VALU_FRAC = 0.541
+COUNTER_SOURCES_SHA = "50e4b9c8c6ec6f29"
 COUNTER_WORKLOAD = "3d_periodic_1M_blobs"
 COUNTER_DEPOSIT_PATH = 5
 
