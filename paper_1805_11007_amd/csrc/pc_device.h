@@ -447,16 +447,17 @@ __device__ __forceinline__ void pair_loop(const StepParams &p, const SpTab &tab,
         return;
     }
     // Lanes of one wave walk their own rows in step: each row costs the wave
-    // its longest lane.  In 3D, outside the periodic seams, a lane may walk
-    // its 9 rows longest first instead, which lines up long rows with long
-    // rows across the wave (modelled on the initial 1M-agent blob state: 84
-    // instead of 110 candidate slots per wave).  Each row is one x range
-    // there.  The order changes only the float summation order of the
-    // lane's sum, so it is used only where the caller allows that.
-    if (DIM == 3 && STENCIL == 3 && rowa != nullptr && p.sort_rows) {
+    // its longest lane.  Outside the periodic seams a lane may walk its rows
+    // (9 in 3D, 3 in 2D) longest first instead, which lines up long rows
+    // with long rows across the wave (modelled on the initial 1M-agent 3D
+    // blob state: 84 instead of 110 candidate slots per wave).  Each row is
+    // one x range there.  The order changes only the float summation order
+    // of the lane's sum, so it is used only where the caller allows that.
+    if (STENCIL == 3 && rowa != nullptr && p.sort_rows) {
+        constexpr int R = DIM == 3 ? 9 : 3;   // rows of the stencil
         bool inner = true;
 #pragma unroll
-        for (int a = 0; a < 3; ++a) inner = inner && lo[a] >= 0 && hi[a] <= nb - 1;
+        for (int a = 0; a < DIM; ++a) inner = inner && lo[a] >= 0 && hi[a] <= nb - 1;
         if (!p.periodic || __all(inner)) {
             // key: length << 5 | row, 16 bits (rows of up to 2047 agents; the
             // row index makes keys distinct); the row's first agent goes to
@@ -465,14 +466,14 @@ __device__ __forceinline__ void pair_loop(const StepParams &p, const SpTab &tab,
             // the CU's previous work-group left there (a stale first agent
             // near 2^32 would wrap the walk's bound a0 + 8 <= a0 + len).
             const uint32_t bd = blockDim.x;
-            uint32_t key[9];
+            uint32_t key[R];
             bool big = false;
 #pragma unroll
-            for (int r = 0; r < 9; ++r) {
-                const int oz = lo[2] + r / 3, oy = lo[1] + r % 3;
+            for (int r = 0; r < R; ++r) {
+                const int oy = lo[1] + r % 3, oz = DIM == 3 ? lo[2] + r / 3 : 0;
                 uint32_t a0 = 0u, len = 0u;
                 float d2 = r % 3 == 0 ? glo2[1] : (r % 3 == 2 ? ghi2[1] : 0.0f);
-                d2 += r / 3 == 0 ? glo2[2] : (r / 3 == 2 ? ghi2[2] : 0.0f);
+                if (DIM == 3) d2 += r / 3 == 0 ? glo2[2] : (r / 3 == 2 ? ghi2[2] : 0.0f);
                 // (a row beyond a wall holds nothing)
                 if (oy >= 0 && oy < nb && oz >= 0 && oz < nb && d2 < cmax2) {
                     int xlo = lo[0], xhi = hi[0];
@@ -488,20 +489,34 @@ __device__ __forceinline__ void pair_loop(const StepParams &p, const SpTab &tab,
                 key[r] = (len << 5) | (uint32_t)r;
             }
             if (!__any(big)) {
-                sort9_desc(key);
+                if (DIM == 3) {
+                    sort9_desc(key);
+                } else {
+                    // three keys: a three-comparator network
+                    uint32_t t = max(key[0], key[1]);
+                    key[1] = min(key[0], key[1]);
+                    key[0] = t;
+                    t = max(key[1], key[R - 1]);
+                    key[R - 1] = min(key[1], key[R - 1]);
+                    key[1] = t;
+                    t = max(key[0], key[1]);
+                    key[1] = min(key[0], key[1]);
+                    key[0] = t;
+                }
                 // two keys per register while the rows are walked
-                uint32_t pk[5];
+                constexpr int NP = (R + 1) / 2;
+                uint32_t pk[NP];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) pk[q] = key[2 * q] | (key[2 * q + 1] << 16);
-                pk[4] = key[8];
+                for (int q = 0; q < R / 2; ++q) pk[q] = key[2 * q] | (key[2 * q + 1] << 16);
+                pk[NP - 1] = key[R - 1];
                 uint32_t kk = pk[0] & 0xffffu;
                 uint32_t a0 = rowa[(kk & 15u) * bd];
 #pragma unroll 1
-                for (int k = 0; k < 9; ++k) {
+                for (int k = 0; k < R; ++k) {
                     const uint32_t len = kk >> 5;
                     if (!__any(len != 0u)) break;   // the rest are empty for every lane
                     const uint32_t kn =
-                        k < 8 ? (pk[(k + 1) >> 1] >> (((k + 1) & 1) * 16)) & 0xffffu : 0u;
+                        k < R - 1 ? (pk[(k + 1) >> 1] >> (((k + 1) & 1) * 16)) & 0xffffu : 0u;
                     const uint32_t an = rowa[(kn & 15u) * bd];
                     pair_range<DIM, NS, false, V, 4>(p, tab, Ps, a0, a0 + len, pi, si, 0.f,
                                                      0.f, 0.f, c2row, drow, v);

@@ -38,7 +38,7 @@ struct StepParams {
     int32_t bins_per_inst;
     int32_t has_uptake;
     int32_t deposit_agg;   // 1: LDS-aggregated deposit; 0: direct device atomics
-    int32_t sort_rows;     // 1: a lane walks its 3D stencil rows longest first
+    int32_t sort_rows;     // 1: a lane walks its stencil rows longest first
     float L, halfL;
     float inv_bin;         // nb / L
     float bin_w;           // L / nb in float32 arithmetic

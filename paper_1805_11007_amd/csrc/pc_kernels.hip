@@ -356,10 +356,10 @@ k_update(StepParams p, const InstInfo *__restrict__ inst, const float4 *__restri
     const uint32_t node_base = kin * (uint32_t)p.nodes_per_inst;
     const InstInfo ii = inst[kin];
 
-    // 3D: the row table of the longest-row-first pair walk (9 words per
-    // thread, launched with that much dynamic LDS)
+    // the row table of the longest-row-first pair walk (a word per stencil
+    // row and thread, launched with that much dynamic LDS)
     extern __shared__ uint32_t upd_rows[];
-    uint32_t *rowa = (DIM == 3 && STENCIL == 3) ? upd_rows + threadIdx.x : nullptr;
+    uint32_t *rowa = STENCIL == 3 ? upd_rows + threadIdx.x : nullptr;
     float F[3] = {0.f, 0.f, 0.f};
     if (POT == 0) {
         ForceVisitor fv{p.k, p.fcap, {0.f, 0.f, 0.f}};
@@ -727,7 +727,7 @@ k_debug_pairs(StepParams p, const InstInfo *__restrict__ inst, const float4 *__r
     // the update's walk, with its LDS row table (same launch shape, so the
     // same waves and the same row order)
     extern __shared__ uint32_t dbg_rows[];
-    uint32_t *rowa = (DIM == 3 && STENCIL == 3) ? dbg_rows + threadIdx.x : nullptr;
+    uint32_t *rowa = STENCIL == 3 ? dbg_rows + threadIdx.x : nullptr;
     uint32_t cnt;
     unsigned long long hs;
     float F[3];
@@ -855,10 +855,11 @@ void launch_stable(const StepParams &p, const Buffers &b, int src, int dst, int 
                            b.P[dst], b.I[dst]);
 }
 
-// dynamic LDS of k_update: the 3D pair walk's row table, 9 words per thread
+// dynamic LDS of k_update: the pair walk's row table, a word per stencil
+// row (9 in 3D, 3 in 2D) and thread
 template <int DIM, int ST>
 static size_t upd_lds(int block) {
-    return (DIM == 3 && ST == 3) ? (size_t)36 * (size_t)block : 0;
+    return ST == 3 ? (size_t)(DIM == 3 ? 36 : 12) * (size_t)block : 0;
 }
 
 template <int DIM, int NS, int ST>
