@@ -55,12 +55,12 @@ FLOP_PER_PAIR, FLOP_PER_AGENT = 18.0, 140.0
 # work-groups, slab deposit).  Valid only for the kernel sources they were
 # taken with (a hash of every file under csrc/), for that workload and that
 # deposit path; reported as null otherwise.
-COUNTER_STEP_BYTES = 331650798.0
-COUNTER_UPDATE_BYTES = 78302667.1
+COUNTER_STEP_BYTES = 331573052.9
+COUNTER_UPDATE_BYTES = 78313765.7
 # SQ_INSTS_VALU of the update over its chip issue capacity in the same
 # window (1024 SIMDs x GRBM_GUI_ACTIVE / 8 XCDs / 4 cycles per wave64 op)
-COUNTER_UPDATE_VALU_FRAC = 0.541
-COUNTER_SOURCES_SHA = "50e4b9c8c6ec6f29"
+COUNTER_UPDATE_VALU_FRAC = 0.546
+COUNTER_SOURCES_SHA = "4474b18f4d109168"
 COUNTER_WORKLOAD = "3d_periodic_1M_blobs"
 COUNTER_DEPOSIT_PATH = 5
 
