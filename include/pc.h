@@ -87,8 +87,12 @@ typedef struct {
     int32_t pde_substeps;   /* 0: smallest count with D_c dt'/h^2 <= 0.9/(2 dim);
                                > 0: used as given, PC_EUNSTABLE above the limit 1/(2 dim) */
     double bin_size;        /* 0: automatic; else the cell-list bin side (>= cutoff)    */
-    int32_t deterministic;  /* 1: agents ordered by id inside each bin, so results are
-                               bitwise reproducible run to run                          */
+    int32_t deterministic;  /* 1: agents ordered by id inside each bin and every lane
+                               walks its stencil rows in a fixed order, so results are
+                               bitwise reproducible run to run and an instance of a
+                               batch evolves bit for bit as it does alone; 0: the
+                               counting sort's atomics order each bin and a lane walks
+                               its rows longest first (float summation order only)      */
     int32_t block;          /* 0: 128; else work-group size of the agent kernels
                                (64, 128, 256, 512 or 1024)                              */
     int32_t bin_order;      /* must be 0: row-major bins (x fastest); others PC_ENOTSUP   */
@@ -338,7 +342,8 @@ const char *pc_last_error(void);
  * hash_dev: uint64, both sum(N). */
 int pc_debug_neighbours(pc_sim *sim, uint32_t *count_dev, uint64_t *hash_dev);
 
-/* Pair forces of the current state (float32, sum(N) x dim, id order). */
+/* Pair forces of the current state (float32, sum(N) x dim, id order), from
+ * the update's own walk over the stencil rows (same order of summation). */
 int pc_debug_forces(pc_sim *sim, float *F_dev);
 
 /* --- differentiation (reverse mode through the step; not in the paper) ---
