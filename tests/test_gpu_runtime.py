@@ -275,6 +275,7 @@ def _dep_case(name, n, g):
 
 @pytest.mark.parametrize("name,n,g,modes", [
     (W.BLOBS_1M, 40000, 32, (2, 4)), (W.WALLS_100K, 20011, 129, (2, 4)),
+    (W.BLOBS_1M, 400000, 200, (2, 4)),
     ("3d_uniform_sparse", 60000, 64, (2, 4)), ("3d_walls", 30011, 33, (2, 4)),
     ("3d_batch", 9001, 20, (2, 4)),
     (W.PERIODIC_1K, 3001, 37, (2, 3, 4)), (W.ENSEMBLE_256, None, 24, (2, 3, 4)),
@@ -286,7 +287,9 @@ def test_deposit_modes_bitwise_equal(name, n, g, modes):
     with a single PDE substep) paths give the same bits, step after step.
     The slab path runs with its default hand-over threshold, with every
     slab of more than one agent handed to the agent-parallel pass, and with
-    a threshold that splits the slabs into both kinds."""
+    a threshold that splits the slabs into both kinds.  On the 200^3 grid
+    (5,000 slabs) the handed-over chunks outnumber the hand-over kernel's
+    resident work-groups, which then take several chunks each."""
     w = _dep_case(name, n, g)
     inp = W.make_inputs(w)
     a = make_sim(w, inp, deterministic=True, deposit_mode=1)
