@@ -105,11 +105,42 @@ def test_pair_walk_rows_beyond_2047_agents():
     F = sim.debug_forces().cpu().numpy().astype(np.float64)
     Fo = oracle_forces(w, inp)
     # a pile agent sums up to ~4,700 float32 pair terms of size up to k d:
-    # 1e-5 k d plus 2^-20 k d per neighbour (a float32 emulation of the same
-    # sums on the CPU stays within a third of it)
+    # 1e-5 k d plus 2^-19 k d per neighbour (a float32 emulation of the same
+    # sums on the CPU reaches 0.17 of it)
     kd = w.k * max(s.diameter for s in w.species)
-    bar = 1e-5 * kd + 2.0 ** -20 * kd * ocnt.astype(np.float64)
+    bar = 1e-5 * kd + 2.0 ** -19 * kd * ocnt.astype(np.float64)
     assert np.all(np.abs(F - Fo).max(axis=1) <= bar)
+
+
+def test_pair_walk_rows_beyond_2047_agents_2d():
+    """2D pile: 12,000 of 14,000 agents inside 3 x 3 bins (~1,330 each), so
+    the three-bin rows of the longest-row-first walk exceed its 2047-agent
+    keys and those waves take the fixed-order walk.  Neighbour sets
+    bit-exact and forces against the oracle (non-deterministic mode)."""
+    w = W.scaled(W.workload(W.PERIODIC_1K), n_agents=14000, grid_n=64)
+    inp = W.make_inputs(w)
+    nb = int(np.floor(w.L / (max(s.diameter for s in w.species) * (1 + 1e-4))))
+    x0 = inp["x0"].copy()
+    rng = np.random.default_rng(9)
+    lo, side = (nb // 2) / nb + 1e-6, 3 / nb - 2e-6   # bins nb/2 .. nb/2 + 2 on both axes
+    x0[:12000] = (lo + rng.uniform(0, side, (12000, 2))).astype(np.float32)
+    inp = dict(inp, x0=x0)
+    sim = make_sim(w, inp)
+    cnt, hsh = sim.debug_neighbours()
+    ocnt, ohsh = oracle_neighbours(w, inp)
+    assert ocnt.max() > 2047
+    assert np.array_equal(cnt.cpu().numpy().astype(np.uint32), ocnt)
+    assert np.array_equal(hsh.cpu().numpy().view(np.uint64), ohsh)
+    F = sim.debug_forces().cpu().numpy().astype(np.float64)
+    Fo = oracle_forces(w, inp)
+    d = max(s.diameter for s in w.species)
+    kd = w.k * d
+    # as in 3D: 1e-5 k d plus 2^-19 k d per neighbour (the float32 emulation
+    # reaches 0.31 of it here)
+    bar = 1e-5 * kd + 2.0 ** -19 * kd * ocnt.astype(np.float64)
+    # off the periodic seam, where x_j - x_i rounds to an ulp of L
+    inner = np.all((x0 >= 2 * d) & (x0 <= w.L - 2 * d), axis=1)
+    assert np.all(np.abs(F - Fo).max(axis=1)[inner] <= bar[inner])
 
 
 @pytest.mark.parametrize("name,n,g", SMALL)
