@@ -40,6 +40,7 @@ constexpr int kSlabThreads = kSlabRuns;   // one run lookup per thread
 constexpr int kSlabTableWords = 2 * kSlabRuns + 2;
 constexpr int kAssistChunk = 1024;   // agents of a heavy slab per assisting pass
 constexpr int kAssistThreads = 256;
+static_assert(kAssistThreads == kSlabThreads, "k_slab_merged runs both kinds of work-group");
 constexpr int kAssistBlocks = 1024;   // grid when the occupancy query fails
 constexpr int kAssistSlabBlock = 4 * kAssistThreads;   // slab counts scanned per pass
 constexpr int kFinishParts = 4;   // work-groups per handed-over slab in k_slab_finish
@@ -268,30 +269,31 @@ __device__ __forceinline__ void slab_pde_nodes(const PdeParams &q, const SlabGeo
     }
 }
 
-template <int DIM, int NS, bool UPT>
-__global__ void __launch_bounds__(kSlabThreads)
-k_chem_slabs(StepParams p, PdeParams q, const InstInfo *__restrict__ inst,
-             const float4 *__restrict__ Ps, const uint32_t *__restrict__ start,
-             const float *__restrict__ cin, float *__restrict__ cout,
-             unsigned long long *__restrict__ Ssrc, unsigned long long *__restrict__ Supt,
-             int By, int Bz, int nby, int nbz, int fuse_pde, uint32_t split,
-             uint32_t *__restrict__ slab_cnt, uint32_t *__restrict__ slab_tab,
-             uint32_t *__restrict__ flags, uint32_t *__restrict__ stepc) {
+// One work-group's slab.  PART 0: everything (a heavy slab handed over,
+// a light one deposited and updated); PART 1: only the classification and
+// the hand-over of heavy slabs (slab_cnt, run table, zeroed deposits);
+// PART 2: only the light slabs (the heavy ones were handed over by PART 1).
+template <int DIM, int NS, bool UPT, int PART>
+__device__ __forceinline__ void chem_slab_body(
+    const StepParams &p, const PdeParams &q, const InstInfo *__restrict__ inst,
+    const float4 *__restrict__ Ps, const uint32_t *__restrict__ start,
+    const float *__restrict__ cin, float *__restrict__ cout,
+    unsigned long long *__restrict__ Ssrc, unsigned long long *__restrict__ Supt, int By,
+    int Bz, int nby, int nbz, int fuse_pde, uint32_t split, uint32_t *__restrict__ slab_cnt,
+    uint32_t *__restrict__ slab_tab, uint32_t *__restrict__ flags, int slab) {
     extern __shared__ unsigned long long sums[];   // owned source sums, then uptake
     __shared__ uint32_t run_a[kSlabRuns];
     __shared__ uint32_t run_pre[kSlabRuns + 1];
     __shared__ uint32_t wtot[kSlabRuns / 64];
     __shared__ SpTab tab;
-    // with the PDE fused, this kernel advances the step counter: the update,
-    // which reads it, has finished, and nothing after it in the step reads it
-    if (fuse_pde && stepc && blockIdx.x == 0 && threadIdx.x == 0) *stepc += 1u;
     const int n = p.grid_n;
     const int nb = p.nb;
-    const SlabGeom g = slab_geom<DIM>(blockIdx.x, n, By, Bz, nby, nbz);
+    const SlabGeom g = slab_geom<DIM>(slab, n, By, Bz, nby, nbz);
     const int y0 = g.y0, y1 = g.y1, z0 = g.z0, z1 = g.z1, owned = g.owned;
     const InstInfo ii = inst[g.k];
-    for (int l = threadIdx.x; l < owned * (UPT ? 2 : 1); l += blockDim.x) sums[l] = 0ull;
-    if (NS == 0) load_tab(p, tab);
+    if (PART != 1)
+        for (int l = threadIdx.x; l < owned * (UPT ? 2 : 1); l += blockDim.x) sums[l] = 0ull;
+    if (NS == 0 && PART != 1) load_tab(p, tab);
     // runs: one per z bin layer of the box and y interval, holding all x bins
     // of that y interval (contiguous in the row-major bin order); one thread
     // per run looks up its bounds, then the lengths are scanned
@@ -352,11 +354,12 @@ k_chem_slabs(StepParams p, PdeParams q, const InstInfo *__restrict__ inst,
     __syncthreads();
     const uint32_t total = run_pre[nrun];
     const bool heavy = total > split;
-    if (threadIdx.x == 0) slab_cnt[blockIdx.x] = heavy ? total : 0u;
+    if (PART != 2 && threadIdx.x == 0) slab_cnt[slab] = heavy ? total : 0u;
     if (heavy) {
-        // handed over: the run table for k_slab_assist, and zeroed deposits
-        // for its atomics
-        uint32_t *T = slab_tab + (size_t)blockIdx.x * kSlabTableWords;
+        if (PART == 2) return;   // handed over before this kernel
+        // handed over: the run table for the assisting work-groups, and
+        // zeroed deposits for their atomics
+        uint32_t *T = slab_tab + (size_t)slab * kSlabTableWords;
         if (threadIdx.x == 0) T[0] = (uint32_t)nrun;
         for (int t = threadIdx.x; t <= nrun; t += blockDim.x) {
             if (t < nrun) T[1 + t] = run_a[t];
@@ -370,6 +373,7 @@ k_chem_slabs(StepParams p, PdeParams q, const InstInfo *__restrict__ inst,
         }
         return;
     }
+    if (PART == 1) return;   // a light slab: the next kernel's
     slab_run_agents<DIM, NS, UPT, 8>(p, tab, Ps, run_a, run_pre, nrun, 0u, total, g, sums);
     __syncthreads();
     uint32_t flag = 0;
@@ -387,20 +391,37 @@ k_chem_slabs(StepParams p, PdeParams q, const InstInfo *__restrict__ inst,
     if (flag) atomicOr(flags, flag);
 }
 
+template <int DIM, int NS, bool UPT>
+__global__ void __launch_bounds__(kSlabThreads)
+k_chem_slabs(StepParams p, PdeParams q, const InstInfo *__restrict__ inst,
+             const float4 *__restrict__ Ps, const uint32_t *__restrict__ start,
+             const float *__restrict__ cin, float *__restrict__ cout,
+             unsigned long long *__restrict__ Ssrc, unsigned long long *__restrict__ Supt,
+             int By, int Bz, int nby, int nbz, int fuse_pde, uint32_t split,
+             uint32_t *__restrict__ slab_cnt, uint32_t *__restrict__ slab_tab,
+             uint32_t *__restrict__ flags, uint32_t *__restrict__ stepc) {
+    // with the PDE fused, this kernel advances the step counter: the update,
+    // which reads it, has finished, and nothing after it in the step reads it
+    if (fuse_pde && stepc && blockIdx.x == 0 && threadIdx.x == 0) *stepc += 1u;
+    chem_slab_body<DIM, NS, UPT, 0>(p, q, inst, Ps, start, cin, cout, Ssrc, Supt, By, Bz, nby,
+                                    nbz, fuse_pde, split, slab_cnt, slab_tab, flags,
+                                    (int)blockIdx.x);
+}
+
 // The agents of the handed-over slabs.  Slab s contributes ceil(cnt_s /
-// kAssistChunk) chunks, numbered in slab order; work-group b takes chunks
-// b, b + gridDim.x, ...  For a chunk it loads the slab's run table, sums the
+// kAssistChunk) chunks, numbered in slab order; assisting work-group b of G
+// takes chunks b, b + G, ...  For a chunk it loads the slab's run table, sums the
 // owned corners of the chunk's agents in LDS and adds each nonzero node sum
 // to the slab's zeroed deposits with one device atomic.  Every work-group
 // scans the slab counts itself (kAssistSlabBlock at a time), so no counter
 // has to be reset between steps; with no handed-over slab it only reads the
 // counts.
 template <int DIM, int NS, bool UPT>
-__global__ void __launch_bounds__(kAssistThreads)
-k_slab_assist(StepParams p, const InstInfo *__restrict__ inst, const float4 *__restrict__ Ps,
-              unsigned long long *__restrict__ Ssrc, unsigned long long *__restrict__ Supt,
-              int By, int Bz, int nby, int nbz, int nslabs,
-              const uint32_t *__restrict__ slab_cnt, const uint32_t *__restrict__ slab_tab) {
+__device__ __forceinline__ void slab_assist_body(
+    const StepParams &p, const InstInfo *__restrict__ inst, const float4 *__restrict__ Ps,
+    unsigned long long *__restrict__ Ssrc, unsigned long long *__restrict__ Supt, int By,
+    int Bz, int nby, int nbz, int nslabs, const uint32_t *__restrict__ slab_cnt,
+    const uint32_t *__restrict__ slab_tab, uint32_t b, uint32_t G) {
     extern __shared__ unsigned long long sums[];
     __shared__ uint32_t pre[kAssistSlabBlock + 1];
     __shared__ uint32_t run_a[kSlabRuns];
@@ -409,7 +430,6 @@ k_slab_assist(StepParams p, const InstInfo *__restrict__ inst, const float4 *__r
     __shared__ SpTab tab;
     if (NS == 0) load_tab(p, tab);
     const int n = p.grid_n;
-    const uint32_t G = gridDim.x, b = blockIdx.x;
     uint32_t base = 0;   // chunks of the slabs before this block of slabs
     for (int s0 = 0; s0 < nslabs; s0 += kAssistSlabBlock) {
         uint32_t c[4], loc = 0;
@@ -483,6 +503,54 @@ k_slab_assist(StepParams p, const InstInfo *__restrict__ inst, const float4 *__r
         base += tot;
         __syncthreads();   // pre and wtot are rewritten by the next block of slabs
     }
+}
+
+template <int DIM, int NS, bool UPT>
+__global__ void __launch_bounds__(kAssistThreads)
+k_slab_assist(StepParams p, const InstInfo *__restrict__ inst, const float4 *__restrict__ Ps,
+              unsigned long long *__restrict__ Ssrc, unsigned long long *__restrict__ Supt,
+              int By, int Bz, int nby, int nbz, int nslabs,
+              const uint32_t *__restrict__ slab_cnt, const uint32_t *__restrict__ slab_tab) {
+    slab_assist_body<DIM, NS, UPT>(p, inst, Ps, Ssrc, Supt, By, Bz, nby, nbz, nslabs, slab_cnt,
+                                   slab_tab, blockIdx.x, gridDim.x);
+}
+
+// The hand-over alone: every slab classified (slab_cnt), the heavy ones'
+// run tables written and deposits zeroed.
+template <int DIM, int NS, bool UPT>
+__global__ void __launch_bounds__(kSlabThreads)
+k_slab_classify(StepParams p, PdeParams q, const InstInfo *__restrict__ inst,
+                const float4 *__restrict__ Ps, const uint32_t *__restrict__ start,
+                unsigned long long *__restrict__ Ssrc, unsigned long long *__restrict__ Supt,
+                int By, int Bz, int nby, int nbz, uint32_t split,
+                uint32_t *__restrict__ slab_cnt, uint32_t *__restrict__ slab_tab,
+                uint32_t *__restrict__ flags) {
+    chem_slab_body<DIM, NS, UPT, 1>(p, q, inst, Ps, start, nullptr, nullptr, Ssrc, Supt, By, Bz,
+                                    nby, nbz, 0, split, slab_cnt, slab_tab, flags,
+                                    (int)blockIdx.x);
+}
+
+// After k_slab_classify: the first nslabs work-groups deposit (and update)
+// the light slabs, the rest assist with the heavy slabs' chunks, so that
+// both kinds of work run side by side in one grid.
+template <int DIM, int NS, bool UPT>
+__global__ void __launch_bounds__(kSlabThreads)
+k_slab_merged(StepParams p, PdeParams q, const InstInfo *__restrict__ inst,
+              const float4 *__restrict__ Ps, const uint32_t *__restrict__ start,
+              const float *__restrict__ cin, float *__restrict__ cout,
+              unsigned long long *__restrict__ Ssrc, unsigned long long *__restrict__ Supt,
+              int By, int Bz, int nby, int nbz, int fuse_pde, uint32_t split, int nslabs,
+              uint32_t *__restrict__ slab_cnt, uint32_t *__restrict__ slab_tab,
+              uint32_t *__restrict__ flags, uint32_t *__restrict__ stepc) {
+    if (fuse_pde && stepc && blockIdx.x == 0 && threadIdx.x == 0) *stepc += 1u;
+    if ((int)blockIdx.x < nslabs)
+        chem_slab_body<DIM, NS, UPT, 2>(p, q, inst, Ps, start, cin, cout, Ssrc, Supt, By, Bz,
+                                        nby, nbz, fuse_pde, split, slab_cnt, slab_tab, flags,
+                                        (int)blockIdx.x);
+    else
+        slab_assist_body<DIM, NS, UPT>(p, inst, Ps, Ssrc, Supt, By, Bz, nby, nbz, nslabs,
+                                       slab_cnt, slab_tab, blockIdx.x - (uint32_t)nslabs,
+                                       gridDim.x - (uint32_t)nslabs);
 }
 
 // The single PDE substep at the nodes of the handed-over slabs, from their
@@ -585,15 +653,15 @@ template <int DIM, int NS, bool UPT>
 static void slabs(const StepParams &p, const PdeParams &q, const Buffers &b, const SlabShape &sh,
                   uint32_t split, int src, int cur, int fuse, hipStream_t s) {
     const size_t lds = sh.lds_bytes * (UPT ? 2 : 1);
-    hipLaunchKernelGGL((k_chem_slabs<DIM, NS, UPT>), dim3((unsigned)sh.nslabs), dim3(kSlabThreads),
-                       lds,
+    hipLaunchKernelGGL((k_slab_classify<DIM, NS, UPT>), dim3((unsigned)sh.nslabs),
+                       dim3(kSlabThreads), 0, s, p, q, b.inst, b.P[src], b.start, b.S_src,
+                       b.S_upt, sh.By, sh.Bz, sh.nby, sh.nbz, split, b.slab_cnt, b.slab_tab,
+                       b.flags);
+    hipLaunchKernelGGL((k_slab_merged<DIM, NS, UPT>),
+                       dim3((unsigned)(sh.nslabs + sh.assist_blocks)), dim3(kSlabThreads), lds,
                        s, p, q, b.inst, b.P[src], b.start, b.c[cur], b.c[1 - cur], b.S_src,
-                       b.S_upt, sh.By, sh.Bz, sh.nby, sh.nbz, fuse, split, b.slab_cnt,
-                       b.slab_tab, b.flags, b.step);
-    hipLaunchKernelGGL((k_slab_assist<DIM, NS, UPT>), dim3((unsigned)sh.assist_blocks),
-                       dim3(kAssistThreads),
-                       lds, s, p, b.inst, b.P[src], b.S_src, b.S_upt, sh.By, sh.Bz, sh.nby,
-                       sh.nbz, (int)sh.nslabs, b.slab_cnt, b.slab_tab);
+                       b.S_upt, sh.By, sh.Bz, sh.nby, sh.nbz, fuse, split, (int)sh.nslabs,
+                       b.slab_cnt, b.slab_tab, b.flags, b.step);
     if (fuse)
         hipLaunchKernelGGL((k_slab_finish<DIM, UPT>), dim3((unsigned)(sh.nslabs * kFinishParts)),
                            dim3(256), 0, s,
