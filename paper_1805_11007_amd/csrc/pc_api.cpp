@@ -494,10 +494,10 @@ static void enqueue_chem(pc_sim *s, hipStream_t st) {
 // Owner-computes deposit by node slabs from the sorted X^{n+1}; with one PDE
 // substep the same kernel updates the field (and advances the step counter),
 // otherwise it stores the deposits for the substeps.
-static void enqueue_slabs(pc_sim *s, hipStream_t st) {
+static void enqueue_slabs(pc_sim *s, hipStream_t st, int classify = 1) {
     const int fuse = s->d.n_sub == 1 ? 1 : 0;
     launch_chem_slabs(s->sp, s->pp, s->b, s->d.slab, s->slab_split, s->sorted_src, s->cur_c,
-                      fuse, st);
+                      fuse, st, classify);
     if (fuse) s->cur_c = 1 - s->cur_c;
     else enqueue_pde(s, st);
 }
@@ -526,11 +526,20 @@ static void enqueue_step(pc_sim *s, hipStream_t st) {
         return;
     }
     if (s->slab) {
-        // the slab deposit gathers through the cell list of X^{n+1}
-        s->binned = 1;
-        s->sorted = 0;
-        ensure_sorted(s, st);
-        enqueue_slabs(s, st);
+        // the slab deposit gathers through the cell list of X^{n+1}; the
+        // scatter's grid also classifies the slabs, which needs only the
+        // bin starts of the scan
+        const int blk = s->d.block;
+        launch_scan(s->sp, s->b, s->d.bins_total, st);
+        s->binned = 0;
+        launch_scatter_classify(s->sp, s->pp, s->b, s->d.slab, s->slab_split, 0, 1, st);
+        s->sorted_src = 1;
+        if (s->cfg.deterministic) {
+            launch_stable(s->sp, s->b, 1, 2, blk, st);
+            s->sorted_src = 2;
+        }
+        s->sorted = 1;
+        enqueue_slabs(s, st, 0);
         return;
     }
     enqueue_chem(s, st);

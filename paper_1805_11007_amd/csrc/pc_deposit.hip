@@ -530,6 +530,33 @@ k_slab_classify(StepParams p, PdeParams q, const InstInfo *__restrict__ inst,
                                     (int)blockIdx.x);
 }
 
+// The counting sort's scatter of X^{n+1} and the slab classification in
+// one grid: the first nsc work-groups scatter the agents, the rest classify
+// the slabs (and hand the heavy ones over).  The classification reads only
+// the bin starts, which the scan wrote before this kernel, and writes
+// nothing the scatter reads.
+template <int DIM, int NS, bool UPT>
+__global__ void __launch_bounds__(kSlabThreads)
+k_scatter_classify(StepParams p, PdeParams q, const InstInfo *__restrict__ inst,
+                   const float4 *__restrict__ P, const uint32_t *__restrict__ I,
+                   uint32_t *__restrict__ count, const uint32_t *__restrict__ start,
+                   float4 *__restrict__ Ps, uint32_t *__restrict__ Is,
+                   unsigned long long *__restrict__ Ssrc, unsigned long long *__restrict__ Supt,
+                   int By, int Bz, int nby, int nbz, uint32_t split,
+                   uint32_t *__restrict__ slab_cnt, uint32_t *__restrict__ slab_tab,
+                   uint32_t *__restrict__ flags, uint32_t nsc) {
+    if (blockIdx.x < nsc) {
+        const uint32_t blk = xcd_block(blockIdx.x, nsc);
+        const int i = blk * blockDim.x + threadIdx.x;
+        if (i >= p.n_total) return;
+        scatter_agent<DIM>(p, P, I, count, start, Ps, Is, i);
+        return;
+    }
+    chem_slab_body<DIM, NS, UPT, 1>(p, q, inst, Ps, start, nullptr, nullptr, Ssrc, Supt, By, Bz,
+                                    nby, nbz, 0, split, slab_cnt, slab_tab, flags,
+                                    (int)(blockIdx.x - nsc));
+}
+
 // After k_slab_classify: the first nslabs work-groups deposit (and update)
 // the light slabs, the rest assist with the heavy slabs' chunks, so that
 // both kinds of work run side by side in one grid.
@@ -651,12 +678,13 @@ size_t chem_slab_table_words() { return kSlabTableWords; }
 
 template <int DIM, int NS, bool UPT>
 static void slabs(const StepParams &p, const PdeParams &q, const Buffers &b, const SlabShape &sh,
-                  uint32_t split, int src, int cur, int fuse, hipStream_t s) {
+                  uint32_t split, int src, int cur, int fuse, int classify, hipStream_t s) {
     const size_t lds = sh.lds_bytes * (UPT ? 2 : 1);
-    hipLaunchKernelGGL((k_slab_classify<DIM, NS, UPT>), dim3((unsigned)sh.nslabs),
-                       dim3(kSlabThreads), 0, s, p, q, b.inst, b.P[src], b.start, b.S_src,
-                       b.S_upt, sh.By, sh.Bz, sh.nby, sh.nbz, split, b.slab_cnt, b.slab_tab,
-                       b.flags);
+    if (classify)
+        hipLaunchKernelGGL((k_slab_classify<DIM, NS, UPT>), dim3((unsigned)sh.nslabs),
+                           dim3(kSlabThreads), 0, s, p, q, b.inst, b.P[src], b.start, b.S_src,
+                           b.S_upt, sh.By, sh.Bz, sh.nby, sh.nbz, split, b.slab_cnt,
+                           b.slab_tab, b.flags);
     hipLaunchKernelGGL((k_slab_merged<DIM, NS, UPT>),
                        dim3((unsigned)(sh.nslabs + sh.assist_blocks)), dim3(kSlabThreads), lds,
                        s, p, q, b.inst, b.P[src], b.start, b.c[cur], b.c[1 - cur], b.S_src,
@@ -671,12 +699,14 @@ static void slabs(const StepParams &p, const PdeParams &q, const Buffers &b, con
 
 void launch_chem_slabs(const StepParams &p, const PdeParams &q, const Buffers &b,
                        const SlabShape &sh, uint32_t split, int src, int cur, int fuse_pde,
-                       hipStream_t s) {
+                       hipStream_t s, int classify) {
     const int ns = p.n_species == 1 ? 1 : (p.n_species == 2 ? 2 : 0);
-#define PC_SLAB(D, N)                                                                   \
-    do {                                                                                \
-        if (p.has_uptake) slabs<D, N, true>(p, q, b, sh, split, src, cur, fuse_pde, s); \
-        else slabs<D, N, false>(p, q, b, sh, split, src, cur, fuse_pde, s);             \
+#define PC_SLAB(D, N)                                                                      \
+    do {                                                                                   \
+        if (p.has_uptake)                                                                  \
+            slabs<D, N, true>(p, q, b, sh, split, src, cur, fuse_pde, classify, s);        \
+        else                                                                               \
+            slabs<D, N, false>(p, q, b, sh, split, src, cur, fuse_pde, classify, s);       \
     } while (0)
     if (p.dim == 2) {
         if (ns == 1) PC_SLAB(2, 1);
@@ -688,6 +718,38 @@ void launch_chem_slabs(const StepParams &p, const PdeParams &q, const Buffers &b
         else PC_SLAB(3, 0);
     }
 #undef PC_SLAB
+}
+
+
+template <int DIM, int NS, bool UPT>
+static void scat_cls(const StepParams &p, const PdeParams &q, const Buffers &b,
+                     const SlabShape &sh, uint32_t split, int src, int dst, hipStream_t s) {
+    const uint32_t nsc = (uint32_t)(((int64_t)p.n_total + kSlabThreads - 1) / kSlabThreads);
+    hipLaunchKernelGGL((k_scatter_classify<DIM, NS, UPT>), dim3((unsigned)(nsc + sh.nslabs)),
+                       dim3(kSlabThreads), 0, s, p, q, b.inst, b.P[src], b.I[src], b.count,
+                       b.start, b.P[dst], b.I[dst], b.S_src, b.S_upt, sh.By, sh.Bz, sh.nby,
+                       sh.nbz, split, b.slab_cnt, b.slab_tab, b.flags, nsc);
+}
+
+void launch_scatter_classify(const StepParams &p, const PdeParams &q, const Buffers &b,
+                             const SlabShape &sh, uint32_t split, int src, int dst,
+                             hipStream_t s) {
+    const int ns = p.n_species == 1 ? 1 : (p.n_species == 2 ? 2 : 0);
+#define PC_SC(D, N)                                                                  \
+    do {                                                                             \
+        if (p.has_uptake) scat_cls<D, N, true>(p, q, b, sh, split, src, dst, s);     \
+        else scat_cls<D, N, false>(p, q, b, sh, split, src, dst, s);                 \
+    } while (0)
+    if (p.dim == 2) {
+        if (ns == 1) PC_SC(2, 1);
+        else if (ns == 2) PC_SC(2, 2);
+        else PC_SC(2, 0);
+    } else {
+        if (ns == 1) PC_SC(3, 1);
+        else if (ns == 2) PC_SC(3, 2);
+        else PC_SC(3, 0);
+    }
+#undef PC_SC
 }
 
 }  // namespace pc

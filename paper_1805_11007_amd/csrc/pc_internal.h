@@ -174,9 +174,16 @@ bool chem_slab_shape(int dim, int n, double bins_per_cell, int n_inst, SlabShape
 // CU at its LDS use times the CU count (1024 if the runtime cannot say).
 void chem_slab_assist_grid(const StepParams &p, SlabShape &sh);
 size_t chem_slab_table_words();
+// classify 0: the slabs were classified (and the heavy ones handed over)
+// by launch_scatter_classify after this step's scan
 void launch_chem_slabs(const StepParams &p, const PdeParams &q, const Buffers &b,
                        const SlabShape &sh, uint32_t split, int src, int cur, int fuse_pde,
-                       hipStream_t s);
+                       hipStream_t s, int classify = 1);
+// The scatter of P[src] into P[dst] by the counts and starts of the scan,
+// with the slab classification of launch_chem_slabs in the same grid.
+void launch_scatter_classify(const StepParams &p, const PdeParams &q, const Buffers &b,
+                             const SlabShape &sh, uint32_t split, int src, int dst,
+                             hipStream_t s);
 void launch_chem_inst(const StepParams &p, const PdeParams &q, const Buffers &b, int src, int cur,
                       int n_sub, hipStream_t s);
 int launch_species_hist(const StepParams &p, const Buffers &b, int src, int m, float s,

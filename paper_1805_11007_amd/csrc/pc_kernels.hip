@@ -47,28 +47,6 @@ __global__ void k_init_agents(StepParams p, const InstInfo *__restrict__ inst,
     I[g] = (uint32_t)g - inst[lo].agent_base;
 }
 
-// Runs of one bin over consecutive active lanes of a wave (agents come in
-// cell order, so a collapsed cluster fills whole waves with one bin): the
-// run's first lane, its length and this lane's place in it.  Inactive lanes
-// are only the tail of the last wave.
-struct WaveRun {
-    int head, len, pos;
-};
-
-__device__ __forceinline__ WaveRun wave_run(uint32_t b) {
-    const int lane = (int)__lane_id();
-    const unsigned long long act = __ballot(1);
-    const uint32_t prev = __shfl_up(b, 1u, 64);
-    const unsigned long long heads = __ballot(lane == 0 || prev != b) | ~act;
-    const unsigned long long upto = lane == 63 ? ~0ull : (2ull << lane) - 1ull;
-    WaveRun r;
-    r.head = 63 - __clzll((long long)(heads & upto));
-    const unsigned long long after = heads & ~upto;
-    r.len = (after ? __ffsll((long long)after) - 1 : 64) - r.head;
-    r.pos = lane - r.head;
-    return r;
-}
-
 // Histogram of one agent's bin b: one added to its count and, when the scan
 // takes its tile totals from the histogram (totals != 0), to the total of
 // b's scan tile.  Neither add returns a value, so the wave does not wait on
@@ -292,17 +270,7 @@ __global__ void k_scatter(StepParams p, const float4 *__restrict__ P,
     const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
     const int i = blk * blockDim.x + threadIdx.x;
     if (i >= p.n_total) return;
-    // the bin counted by the kernel that wrote x, recomputed from x by the
-    // same float32 arithmetic (instance tables are equal-sized)
-    const float4 x = P[i];
-    const uint32_t b = inst_of(x.w) * (uint32_t)p.bins_per_inst + agent_bin<DIM>(p, x);
-    const WaveRun run = wave_run(b);
-    uint32_t top = 0;
-    if (run.pos == 0) top = atomicSub(count + b, (uint32_t)run.len);
-    top = __shfl(top, run.head, 64);
-    const uint32_t d = start[b] + top - 1u - (uint32_t)run.pos;
-    Ps[d] = x;
-    Is[d] = I[i];
+    scatter_agent<DIM>(p, P, I, count, start, Ps, Is, i);
 }
 
 // Deterministic order inside each bin: an agent's slot is its bin start
