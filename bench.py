@@ -51,16 +51,16 @@ FLOP_PER_PAIR, FLOP_PER_AGENT = 18.0, 140.0
 # steps after 5 warm-up steps; each counter in its own run, FETCH_SIZE scaled
 # by 2.0 and WRITE_SIZE by 1.0 from a plain device copy).  Bytes per step
 # (summed over the step's kernels) and per launch of the update kernel,
-# with the tuned choice of that run (bin side = cutoff, 128-thread agent
+# with the tuned choice of that run (bin side = cutoff, 64-thread agent
 # work-groups, slab deposit).  Valid only for the kernel sources they were
 # taken with (a hash of every file under csrc/), for that workload and that
 # deposit path; reported as null otherwise.
-COUNTER_STEP_BYTES = 325160186.6
-COUNTER_UPDATE_BYTES = 78308472.5
+COUNTER_STEP_BYTES = 325134723.6
+COUNTER_UPDATE_BYTES = 78311565.1
 # SQ_INSTS_VALU of the update over its chip issue capacity in the same
 # window (1024 SIMDs x GRBM_GUI_ACTIVE / 8 XCDs / 4 cycles per wave64 op)
-COUNTER_UPDATE_VALU_FRAC = 0.543
-COUNTER_SOURCES_SHA = "2befa191594641b7"
+COUNTER_UPDATE_VALU_FRAC = 0.546
+COUNTER_SOURCES_SHA = "c4d24e09c33253c2"
 COUNTER_WORKLOAD = "3d_periodic_1M_blobs"
 COUNTER_DEPOSIT_PATH = 5
 

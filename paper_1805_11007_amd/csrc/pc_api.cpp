@@ -801,7 +801,12 @@ int pc_profile_steps(pc_sim *s, int n_steps, double *stage_ms) {
         HIP_OK(hipEventRecord(e1[K], st));             \
         ran[K] = true;                                 \
     } while (0)
-        auto sort_stages = [&]() -> int {
+        // with_classify: the scatter's grid also classifies the slabs, as
+        // in the step (its time is then the scatter's); returns through
+        // classified whether it did
+        bool classified = false;
+        auto sort_stages = [&](bool with_classify = false) -> int {
+            classified = false;
             if (s->sorted) return PC_OK;
             if (!s->binned) {
                 PC_STAGE(PC_STAGE_BIN, launch_bin(s->sp, s->b, 0, blk, st));
@@ -809,7 +814,14 @@ int pc_profile_steps(pc_sim *s, int n_steps, double *stage_ms) {
             }
             PC_STAGE(PC_STAGE_SCAN, launch_scan(s->sp, s->b, s->d.bins_total, st));
             s->binned = 0;
-            PC_STAGE(PC_STAGE_SCATTER, launch_scatter(s->sp, s->b, 0, 1, blk, st));
+            if (with_classify) {
+                PC_STAGE(PC_STAGE_SCATTER,
+                         launch_scatter_classify(s->sp, s->pp, s->b, s->d.slab, s->slab_split, 0,
+                                                 1, st));
+                classified = true;
+            } else {
+                PC_STAGE(PC_STAGE_SCATTER, launch_scatter(s->sp, s->b, 0, 1, blk, st));
+            }
             s->sorted_src = 1;
             if (s->cfg.deterministic) {
                 PC_STAGE(PC_STAGE_STABLE, launch_stable(s->sp, s->b, 1, 2, blk, st));
@@ -836,16 +848,17 @@ int pc_profile_steps(pc_sim *s, int n_steps, double *stage_ms) {
             PC_STAGE(PC_STAGE_DEPOSIT, enqueue_kde(s, st));
             PC_STAGE(PC_STAGE_PDE, enqueue_pde(s, st));
         } else if (s->slab) {
-            rc = sort_stages();
+            rc = sort_stages(true);
             if (rc) return rc;
+            const int cls = classified ? 0 : 1;
             if (s->d.n_sub == 1) {
                 // deposit and PDE in one pass: its time is reported under
                 // the deposit
-                PC_STAGE(PC_STAGE_DEPOSIT, enqueue_slabs(s, st));
+                PC_STAGE(PC_STAGE_DEPOSIT, enqueue_slabs(s, st, cls));
             } else {
                 PC_STAGE(PC_STAGE_DEPOSIT, launch_chem_slabs(s->sp, s->pp, s->b, s->d.slab,
                                                              s->slab_split, s->sorted_src,
-                                                             s->cur_c, 0, st));
+                                                             s->cur_c, 0, st, cls));
                 PC_STAGE(PC_STAGE_PDE, enqueue_pde(s, st));
             }
         } else if (s->chem_fused) {
