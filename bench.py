@@ -60,7 +60,7 @@ COUNTER_UPDATE_BYTES = 78311565.1
 # SQ_INSTS_VALU of the update over its chip issue capacity in the same
 # window (1024 SIMDs x GRBM_GUI_ACTIVE / 8 XCDs / 4 cycles per wave64 op)
 COUNTER_UPDATE_VALU_FRAC = 0.546
-COUNTER_SOURCES_SHA = "c4d24e09c33253c2"
+COUNTER_SOURCES_SHA = "a14bd4617e67dec5"
 COUNTER_WORKLOAD = "3d_periodic_1M_blobs"
 COUNTER_DEPOSIT_PATH = 5
 

@@ -24,12 +24,17 @@
 //
 // One work-group per slab serialises where chemotaxis has collapsed a blob
 // into a few cells: a slab can then hold 10^5 agents.  A slab with more
-// agents than a threshold is handed over: its work-group records its run
-// table and zeroes its nodes' deposits, k_slab_assist spreads its agents in
-// chunks over many work-groups (each sums a chunk's owned corners in LDS and
-// adds the nonzero node sums to HBM with device atomics), and k_slab_finish
-// applies the PDE to its nodes.  The sums are still integers, so the bits
-// do not depend on which slabs were handed over.
+// agents than a threshold is handed over: its run table is recorded and its
+// nodes' deposits zeroed, its agents are spread in chunks over many
+// work-groups (each sums a chunk's owned corners in LDS and adds the nonzero
+// node sums to HBM with device atomics), and k_slab_finish applies the PDE
+// to its nodes.  The sums are still integers, so the bits do not depend on
+// which slabs were handed over.  In the step the hand-over runs in the
+// scatter's grid (k_scatter_classify: it needs only the bin starts), and the
+// light slabs' work-groups and the assisting ones share one grid
+// (k_slab_merged), so that their work overlaps; no work-group ever waits on
+// another inside a kernel.  k_chem_slabs and k_slab_assist are the same
+// bodies launched one after the other.
 #include "pc_device.h"
 
 namespace pc {
