@@ -254,6 +254,10 @@ def _dep_case(name, n, g):
     if name == "3d_walls":
         return dataclasses.replace(W.scaled(W.workload(W.BLOBS_1M), n_agents=n, grid_n=g),
                                    periodic=False, c0="cos")
+    if name == "3d_substeps":
+        # three PDE substeps: the slab path stores its sums (no fused PDE)
+        return dataclasses.replace(W.scaled(W.workload(W.BLOBS_1M), n_agents=n, grid_n=g),
+                                   pde_substeps=3)
     if name == "3d_batch":
         w = W.scaled(W.workload(W.BLOBS_1M), n_agents=[n, n // 3, 7], grid_n=g)
         return dataclasses.replace(w, species=(W.Species(0.004, 1.0, 1.0, 1.0, 0.0),
@@ -275,7 +279,7 @@ def _dep_case(name, n, g):
 
 @pytest.mark.parametrize("name,n,g,modes", [
     (W.BLOBS_1M, 40000, 32, (2, 4)), (W.WALLS_100K, 20011, 129, (2, 4)),
-    (W.BLOBS_1M, 400000, 200, (2, 4)),
+    (W.BLOBS_1M, 400000, 200, (2, 4)), ("3d_substeps", 30011, 40, (2, 4)),
     ("3d_uniform_sparse", 60000, 64, (2, 4)), ("3d_walls", 30011, 33, (2, 4)),
     ("3d_batch", 9001, 20, (2, 4)),
     (W.PERIODIC_1K, 3001, 37, (2, 3, 4)), (W.ENSEMBLE_256, None, 24, (2, 3, 4)),
